@@ -1,0 +1,181 @@
+"""Pins of the oracle's transport: Beer-Lambert, the null-collision
+transmissivity estimator (Section 2.3, Eq. 2), majorant invariance, the HG
+phase function, and radiance closed forms for slabs (pure absorber over a
+Lambertian ground; single scattering)."""
+import math
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from paper_1902_01137_amd.inputs import Camera, FieldDesc, Optics, lognormal_blob, random_rays, slab_field
+
+
+def z_ok(est, se, exact, nsig=4.0):
+    return abs(est - exact) <= nsig * se + 1e-12
+
+
+# ---------------------------------------------------------------- optical depth
+
+def test_optical_depth_slabs(orc):
+    desc, k = slab_field([0.5, 2.0, 0.25], 0.4)
+    f = orc.make_field(desc, k, 0.1)
+    for mu in (1.0, 0.6, 0.17):
+        s = math.sqrt(1 - mu * mu)
+        ray = [0.3, -0.2, 1.2 + 1e-3, s, 0.0, -mu]  # from just above the top, downwards
+        tau = orc.optical_depth(f, ray)
+        exact = (0.5 + 2.0 + 0.25 + 3 * 0.1) * 0.4 / mu
+        assert tau == pytest.approx(exact, rel=1e-12)
+
+
+def test_optical_depth_partial_segment(orc):
+    desc, k = slab_field([3.0], 1.0)
+    f = orc.make_field(desc, k, 0.0)
+    assert orc.optical_depth(f, [0, 0, 0.25, 0, 0, 1], 0.5) == pytest.approx(1.5, rel=1e-14)
+
+
+# ---------------------------------------------------------------- transmissivity
+
+@pytest.mark.parametrize("mode", [1, 2])
+def test_beer_lambert_delta_tracking(orc, mode):
+    desc, k = slab_field([0.7, 2.5], 0.5)
+    g = orc.OracleGrid(desc, k, tau_tilde=1.0, k_gas=0.05)
+    mu = 0.8
+    ray = np.array([[0.0, 0.0, 1.0 + 1e-9, math.sqrt(1 - mu * mu), 0.0, -mu]])
+    n = 40000
+    for m in (1.0, 3.0):
+        mean, se, _ = orc.transmittance(g.field, ray, n, seed=5, mode=mode, majorant_scale=m, grid=g)
+        exact = math.exp(-(0.7 + 2.5 + 0.1) * 0.5 / mu)
+        # the estimator is exactly Bernoulli(exp(-tau)): use its exact SE
+        se_exact = math.sqrt(exact * (1 - exact) / n)
+        assert z_ok(mean[0], se_exact, exact)
+
+
+def test_majorant_invariance_blob(orc):
+    """Any valid majorant field gives the same transmissivity (the rejected
+    collisions are pure forward scattering, Section 2.3)."""
+    desc, k = lognormal_blob()
+    rays = random_rays(desc, 24, seed=21, inside_frac=1.0, axis_frac=0.0)
+    f = orc.make_field(desc, k, 0.0)
+    exact, _, _ = orc.transmittance(f, rays, 1, 0, mode=0)
+    n = 3000
+    for tau in (0.0, 1.0, 10.0, np.inf):
+        g = orc.OracleGrid(desc, k, tau_tilde=tau)
+        for m in (1.0, 2.0, 10.0):
+            mean, _, cnt = orc.transmittance(g.field, rays, n, seed=7, mode=2, majorant_scale=m, grid=g)
+            se = np.sqrt(np.maximum(exact * (1 - exact), 1e-4) / n)
+            z = (mean - exact) / se
+            assert np.abs(z).max() < 4.5, (tau, m, z)
+    gm, _, _ = orc.transmittance(f, rays, n, seed=9, mode=1, majorant_scale=1.0)
+    se = np.sqrt(np.maximum(exact * (1 - exact), 1e-4) / n)
+    assert np.abs((gm - exact) / se).max() < 4.5
+
+
+def test_null_counts_grow_with_majorant(orc):
+    desc, k = lognormal_blob()
+    rays = random_rays(desc, 16, seed=22, inside_frac=1.0, axis_frac=0.0)
+    g = orc.OracleGrid(desc, k, tau_tilde=1.0)
+    _, _, c1 = orc.transmittance(g.field, rays, 500, seed=1, mode=2, majorant_scale=1.0, grid=g)
+    _, _, c2 = orc.transmittance(g.field, rays, 500, seed=1, mode=2, majorant_scale=4.0, grid=g)
+    assert c2[1] > 3 * c1[1]
+    # tau_tilde = 0 keeps k_hat = k in every cell: no null collision at all
+    g0 = orc.OracleGrid(desc, k, tau_tilde=0.0)
+    _, _, c0 = orc.transmittance(g0.field, rays, 500, seed=1, mode=2, majorant_scale=1.0, grid=g0)
+    assert c0[1] == 0 and c0[0] > 0
+
+
+# ---------------------------------------------------------------- HG phase function
+
+@pytest.mark.parametrize("g", [0.0, 0.3, 0.85, -0.5])
+def test_hg_normalisation_and_mean_cosine(orc, g):
+    norm, _ = integrate.quad(lambda mu: 2 * math.pi * orc.hg_phase(g, mu), -1, 1, limit=200)
+    mean, _ = integrate.quad(lambda mu: 2 * math.pi * mu * orc.hg_phase(g, mu), -1, 1, limit=200)
+    assert norm == pytest.approx(1.0, abs=1e-9)
+    assert mean == pytest.approx(g, abs=1e-9)
+
+
+@pytest.mark.parametrize("g", [0.0, 0.5, 0.86, -0.7])
+def test_hg_sampler_inverts_cdf(orc, g):
+    def cdf(mu):
+        if g == 0.0:
+            return (mu + 1) / 2
+        return (1 - g * g) / (2 * g) * (1 / math.sqrt(1 + g * g - 2 * g * mu) - 1 / (1 + g))
+    for xi in np.linspace(0.0, 0.999999, 101):
+        mu = orc.hg_sample_mu(g, xi)
+        assert -1.0 <= mu <= 1.0
+        assert cdf(mu) == pytest.approx(xi, abs=1e-9)
+
+
+# ---------------------------------------------------------------- radiance closed forms
+
+def _slab_camera(mu, z_top):
+    s = math.sqrt(1 - mu * mu)
+    pos = (0.0, 0.0, z_top + 0.5)
+    target = (pos[0] + s, pos[1], pos[2] - mu)
+    return Camera(type=1, pos=pos, target=target, up=(0.0, 0.0, 1.0), ortho_w=0.1, ortho_h=0.1, width=2, height=2)
+
+
+def test_pure_absorber_over_lambertian_ground(orc):
+    tau, H, rho, mu, th0 = 0.8, 0.4, 0.3, 0.7, 40.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=rho, sun_zenith_deg=th0, sun_azimuth_deg=25.0)
+    cam = _slab_camera(mu, H)
+    spp = 20000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=3)
+    mu0 = math.cos(math.radians(th0))
+    c = rho / math.pi * mu0 * math.exp(-tau / mu0)
+    p = math.exp(-tau / mu)
+    exact = c * p
+    mean = s / spp
+    # L is c times Bernoulli(p): exact SE
+    se = c * math.sqrt(p * (1 - p) / spp)
+    for m in mean:
+        assert z_ok(m, se, exact)
+
+
+def test_single_scattering_slab(orc):
+    tau, H, ssa, g, mu, th0, phi0 = 1.3, 0.5, 0.9, 0.6, 0.55, 35.0, 60.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=ssa, g=g, ground_albedo=0.0, sun_zenith_deg=th0, sun_azimuth_deg=phi0, max_scatter=1)
+    cam = _slab_camera(mu, H)
+    spp = 20000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=4)
+    mu0 = math.cos(math.radians(th0))
+    sv = np.array([math.sin(math.radians(th0)) * math.cos(math.radians(phi0)),
+                   math.sin(math.radians(th0)) * math.sin(math.radians(phi0)), mu0])
+    d = np.array([math.sqrt(1 - mu * mu), 0.0, -mu])
+    cosT = float(d @ sv)
+    p = (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * cosT) ** 1.5)
+    exact = ssa * p * mu0 / (mu0 + mu) * (1 - math.exp(-tau * (1 / mu0 + 1 / mu)))
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / (spp - 1))
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact)
+
+
+def test_gas_only_absorbs(orc):
+    """With k_c = 0 and a gas k_g, every collision absorbs (ssa(x) = 0): only
+    the ground term survives, attenuated by the gas both ways."""
+    H, kg, rho, mu, th0 = 1.0, 0.3, 0.5, 0.9, 20.0
+    desc, k = slab_field([0.0], H)
+    op = Optics(ssa=1.0, g=0.5, ground_albedo=rho, sun_zenith_deg=th0, max_scatter=1)
+    cam = _slab_camera(mu, H)
+    spp = 20000
+    s, _, _ = orc.render(desc, k, kg, op, cam, spp, seed=5)
+    mu0 = math.cos(math.radians(th0))
+    c = rho / math.pi * mu0 * math.exp(-kg * H / mu0)
+    p = math.exp(-kg * H / mu)
+    se = c * math.sqrt(p * (1 - p) / spp)
+    for m in s / spp:
+        assert z_ok(m, se, c * p)
+
+
+def test_camera_centre_ray(orc):
+    cam = Camera(type=0, pos=(1.0, 2.0, 3.0), target=(4.0, 2.0, 3.0), up=(0, 0, 1), fov_y_deg=60, width=4, height=2)
+    r = orc.camera_ray(cam, 2, 1, 0.0, 0.0)      # the image centre
+    assert np.allclose(r[3:], [1, 0, 0], atol=1e-15) and np.allclose(r[:3], [1, 2, 3])
+    r = orc.camera_ray(cam, 0, 0, 0.0, 0.0)      # top-left corner: up and to the left
+    t = math.tan(math.radians(30))
+    v = np.array([1.0, -(-2.0 * t), t])          # right = f x up = -y; left of centre is +y
+    v /= np.linalg.norm(v)
+    assert np.allclose(r[3:], v, atol=1e-14)
