@@ -1,0 +1,214 @@
+/*
+ * nctrace.h -- C ABI of the null-collision path tracer for MI355X (gfx950).
+ *
+ * The library implements the method of Villefranque et al. (JAMES 2019,
+ * "Path-tracing Monte Carlo library for 3D radiative transfer in highly
+ * resolved cloudy atmospheres"): a hierarchical grid of per-node minimum and
+ * maximum extinction is built over a voxel field (Section 3.1), and
+ * radiances, transmissivities and fluxes are estimated by null-collision
+ * (maximum cross-section) path sampling through it (Sections 2.3 and 4.1).
+ *
+ * Conventions for every entry point
+ *   - Lengths are km, extinction coefficients km^-1, angles degrees.
+ *   - A field is a contiguous float32 array [nz][ny][nx] (x fastest) of the
+ *     condensed-phase extinction k_c >= 0; a uniform gas k_gas (pure
+ *     absorber) is added inside the field's box.  Outside the box is vacuum;
+ *     the ground is the plane z = 0 (the box must satisfy z0 >= 0).
+ *   - Pointers named d_* are caller-owned DEVICE buffers on the context's
+ *     device; the library never frees them.  Structs are passed as host
+ *     pointers and are read during the call only.
+ *   - Handles (nc_ctx, nc_grid) are library-owned; release them with the
+ *     matching destroy call.
+ *   - Calls enqueue work on the context's stream and return; results are
+ *     valid once that stream is synchronised.  nc_grid_build synchronises
+ *     (it reads back the field-validation flag).
+ *   - Every call returns an nc_status.  Arguments are validated before any
+ *     work is enqueued; on error nothing is written to the outputs and
+ *     nc_last_error() describes the problem.  Calls never abort the process.
+ *   - Determinism: the same seed, sample offset and inputs reproduce every
+ *     path exactly (counter-based Philox4x32-10 random numbers); FP64
+ *     accumulations may differ in the last bits through atomic ordering.
+ */
+#ifndef NCTRACE_H
+#define NCTRACE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NC_ABI_VERSION 1u
+#define NC_MAX_LEVELS 24
+
+typedef int32_t nc_status;
+#define NC_OK 0
+#define NC_ERR_INVALID_ARG 1   /* null pointer, bad size, bad enum */
+#define NC_ERR_RANGE 2         /* NaN/Inf/negative extinction, g outside (-1,1), albedo outside [0,1], ... */
+#define NC_ERR_OOM 3           /* device allocation failed */
+#define NC_ERR_DEVICE 4        /* no usable device, or a HIP runtime error */
+#define NC_ERR_UNSUPPORTED 5
+#define NC_ERR_STATE 6         /* grid built for another field shape */
+
+typedef struct nc_ctx nc_ctx;
+typedef struct nc_grid nc_grid;
+
+/* Voxel field geometry: box [x0, x0+nx dx] x [y0, y0+ny dy] x [z0, z0+nz dz]. */
+typedef struct {
+    int32_t nx, ny, nz, pad_;
+    double x0, y0, z0, dx, dy, dz;
+} nc_field_desc;
+
+/* Merge rule of the acceleration grid (Section 3.1.1, criterion of Section 4.2).
+ * A node of level l (2^l cells per side, clipped to the field) is one voxel of
+ * the grid when its optical-depth criterion, evaluated in double precision, is
+ *   criterion 0: (kmax_c + k_gas) * dz * 2^l < tau_tilde    (default)
+ *   criterion 1: (kmax_c - kmin_c) * dz * 2^l < tau_tilde
+ * tau_tilde = 0 keeps the raw resolution; tau_tilde = +inf gives one voxel. */
+typedef struct {
+    double tau_tilde;
+    double k_gas;
+    int32_t criterion;
+    int32_t pad_;
+} nc_grid_params;
+
+/* Medium, ground and sun.  ssa is the droplets' single-scattering albedo
+ * (the local albedo is ssa k_c / (k_c + k_gas)); g the Henyey-Greenstein
+ * asymmetry; ground_albedo the Lambertian reflectivity of z = 0; the sun is
+ * directional, azimuth measured from +X towards +Y, irradiance normal to the
+ * beam sun_irradiance.  The null-collision majorant of a voxel is
+ * majorant_scale * (kmax_c + k_gas), majorant_scale >= 1.  max_scatter >= 0
+ * limits the number of scattering/reflection events whose sun contribution
+ * is counted (-1: unlimited); max_segments caps tracking steps per path
+ * (paths reaching it are stopped and counted as truncated). */
+typedef struct {
+    double ssa, g, ground_albedo;
+    double sun_zenith_deg, sun_azimuth_deg, sun_irradiance;
+    double majorant_scale;
+    int32_t max_scatter;
+    int32_t max_segments;
+} nc_optics;
+
+/* Camera (Section 4.1, Table 3): type 0 pinhole with vertical field of view
+ * fov_y_deg, type 1 orthographic of extent ortho_w x ortho_h; forward =
+ * target - pos, right = forward x up, row 0 is the top of the image, pixel
+ * (i, j) is index j*width + i; directions are sampled uniformly over the
+ * pixel's footprint on the image plane. */
+typedef struct {
+    int32_t type;
+    int32_t width, height;
+    int32_t pad_;
+    double pos[3], target[3], up[3];
+    double fov_y_deg, ortho_w, ortho_h;
+} nc_camera;
+
+/* Sampling: seed keys the random streams; sample s of pixel p uses stream
+ * (p, sample_offset + s), so a run with sample_offset = n continues one that
+ * took n samples per pixel. */
+typedef struct {
+    uint64_t seed;
+    uint64_t sample_offset;
+    int32_t spp;
+    int32_t flags;
+    double guide_frac;
+} nc_sampling;
+
+/* Per-call event counters (summed over all paths of the call). */
+typedef struct {
+    uint64_t paths;          /* paths completed */
+    uint64_t segments;       /* tracking steps: voxel visits + tentative collisions */
+    uint64_t tentative;      /* tentative collisions sampled in the majorant field */
+    uint64_t nulls;          /* rejected (null) collisions */
+    uint64_t reals;          /* accepted collisions (path and sun rays) */
+    uint64_t leaf_visits;    /* acceleration-grid voxels entered */
+    uint64_t gathers;        /* raw field reads for the null/real test */
+    uint64_t node_reads;     /* grid node reads from global memory */
+    uint64_t nee_rays;       /* sun rays traced */
+    uint64_t truncated;      /* paths stopped at max_segments */
+    uint64_t reserved[6];
+} nc_counters;
+
+/* Library ABI version (NC_ABI_VERSION). */
+uint32_t nc_abi_version(void);
+
+/* Create a context on HIP device `device`, enqueueing on `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  NC_ERR_DEVICE if the device
+ * is missing. */
+nc_status nc_ctx_create(int32_t device, void *hip_stream, nc_ctx **out);
+nc_status nc_ctx_set_stream(nc_ctx *ctx, void *hip_stream);
+void nc_ctx_destroy(nc_ctx *ctx);
+/* Text of the last error on this context (or of the last failed
+ * nc_ctx_create when ctx is NULL).  Valid until the next call. */
+const char *nc_last_error(const nc_ctx *ctx);
+
+/* Build the acceleration grid over d_kc (Section 3.1.1; Appendix C's
+ * power-of-two octree, with nodes wholly outside the field left out).
+ * Level 0 is the field itself; level l (1..L, L = ceil(log2 max(nx,ny,nz)))
+ * has ceil(n/2^l) nodes per axis, each holding the min and max of k_c over
+ * the cells it covers.  A cell's voxel is its coarsest ancestor that passes
+ * the merge criterion (the cell itself if none does).  The field is checked
+ * (finite and >= 0: else NC_ERR_RANGE).  The grid keeps no reference to
+ * d_kc; estimators take the field again and check its shape. */
+nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *desc, const nc_grid_params *params,
+                        nc_grid **out);
+void nc_grid_destroy(nc_grid *grid);
+/* Number of levels L above the cells, and the node counts of level l. */
+nc_status nc_grid_info(const nc_grid *grid, int32_t *levels, int32_t level, int32_t dims_out[3]);
+/* Copy level l (1..L) to caller buffers of dims[2]*dims[1]*dims[0] entries:
+ * kmin_c, kmax_c (float32) and the merged flag (uint8, 1 = voxel of the grid
+ * or inside one).  Any output pointer may be NULL. */
+nc_status nc_grid_export(nc_ctx *ctx, const nc_grid *grid, int32_t level, float *d_kmin, float *d_kmax,
+                         uint8_t *d_merged);
+/* Per-cell voxel level (uint8 [nz][ny][nx]). */
+nc_status nc_grid_leaf_levels(nc_ctx *ctx, const nc_grid *grid, uint8_t *d_leaf_level);
+
+/* Ordered crossing of the grid (Section 3.1.3): for each of n rays
+ * (d_rays: n x 6 float32, origin then unit direction) the voxels met inside
+ * the box, in order: d_leaf[n][max_visits][4] = (level, ix, iy, iz) of the
+ * voxel at that level, d_t[n][max_visits][2] = entry and exit parameters.
+ * d_count[n] = number of voxels (may exceed max_visits; only max_visits are
+ * written). */
+nc_status nc_trace_leaves(nc_ctx *ctx, const nc_grid *grid, const float *d_rays, int32_t n, int32_t max_visits,
+                          int32_t *d_leaf, float *d_t, int32_t *d_count);
+
+/* Direct transmissivity by the null-collision algorithm of Section 2.3
+ * (Eq. 2): for each ray, nsamples Bernoulli paths in the grid's
+ * piecewise-constant majorant; d_sum[n], d_sumsq[n] (float64) receive the
+ * sum and sum of squares of the path transmissivities.  The ground is not
+ * intersected (rays are cast through the field's box only). */
+nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                           const float *d_rays, int32_t n, const nc_sampling *sampling, double *d_sum,
+                           double *d_sumsq, nc_counters *d_counters);
+
+/* Radiance image by the backward algorithm with the local estimate of the
+ * sun (Section 4.1, Fig. 4a): per pixel, spp paths from the camera; at each
+ * real collision and ground hit the sun's transmissivity (null-collision
+ * shadow ray) times the phase function (or Lambertian BRDF) is added; the
+ * path then scatters (HG), reflects (cosine law) or is absorbed.  Output:
+ * d_sum, d_sumsq [height*width] float64 sum and sum of squares of the path
+ * radiances (units of sun_irradiance per steradian), ADDED to the buffers
+ * (zero them first).  d_counters (device, may be NULL) is added to. */
+nc_status nc_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                    const nc_camera *camera, const nc_sampling *sampling, double *d_sum, double *d_sumsq,
+                    nc_counters *d_counters);
+
+/* Counter-based random numbers (Salmon et al., SC'11): out[i] =
+ * Philox4x32-10(counter = d_ctr[4i..4i+3], key = d_key[2i..2i+1]) for i < n.
+ * All buffers are uint32 device arrays.  The path tracers draw their random
+ * numbers from this generator; the entry point exposes it for testing. */
+nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int32_t n);
+
+/* Launch-shape knobs of the path-tracing kernels (0 = library default). */
+typedef struct {
+    int32_t block;          /* threads per workgroup (multiple of 64) */
+    int32_t waves_per_cu;   /* resident waves per CU the persistent grid is sized for */
+    int32_t samples_per_item; /* samples of one pixel taken by one lane per queue item */
+    int32_t lds_levels;     /* top grid levels staged in LDS (-1: as many as fit) */
+} nc_launch;
+nc_status nc_set_launch(nc_ctx *ctx, const nc_launch *launch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NCTRACE_H */

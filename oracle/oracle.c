@@ -831,6 +831,7 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             for (a = 0; a < 3; ++a) x[a] = o[a] + tc * d[a];
             if (cnt) cnt[0]++;
             order++;
+            if (op->max_scatter >= 0 && order > op->max_scatter) break;
             mu_sun = d[0] * s[0] + d[1] * s[1] + d[2] * s[2];
             L += ssa * orc_hg_phase(op->g, mu_sun) * op->S * sun_transmissivity(f, x, s);
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
@@ -847,6 +848,7 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             x[2] = 0.0;
             if (cnt) cnt[1]++;
             order++;
+            if (op->max_scatter >= 0 && order > op->max_scatter) break;
             if (s[2] > 0.0)
                 L += (op->rho / ORC_PI) * op->S * s[2] * sun_transmissivity(f, x, s);
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;

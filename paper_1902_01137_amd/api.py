@@ -1,0 +1,193 @@
+"""Python binding of the C ABI (argument marshalling only).
+
+Every estimator runs in the HIP kernels of libnctrace.so; PyTorch provides
+device memory and the stream.  Names follow include/nctrace.h.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import asdict
+
+import torch
+
+from . import _lib
+from .inputs import Camera, FieldDesc, GridParams, Optics, Sampling
+
+
+def _check(status, ctx_handle=None):
+    if status != _lib.NC_OK:
+        msg = _lib.load().nc_last_error(ctx_handle)
+        raise _lib.NcError(status, msg.decode() if msg else "")
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _desc(d: FieldDesc):
+    return _lib.FieldDesc(d.nx, d.ny, d.nz, 0, d.x0, d.y0, d.z0, d.dx, d.dy, d.dz)
+
+
+def _optics(o: Optics):
+    return _lib.Optics(o.ssa, o.g, o.ground_albedo, o.sun_zenith_deg, o.sun_azimuth_deg, o.sun_irradiance,
+                       o.majorant_scale, o.max_scatter, o.max_segments)
+
+
+def _camera(c: Camera):
+    cc = _lib.Camera()
+    cc.type, cc.width, cc.height = c.type, c.width, c.height
+    for i in range(3):
+        cc.pos[i], cc.target[i], cc.up[i] = c.pos[i], c.target[i], c.up[i]
+    cc.fov_y_deg, cc.ortho_w, cc.ortho_h = c.fov_y_deg, c.ortho_w, c.ortho_h
+    return cc
+
+
+def _sampling(s: Sampling):
+    return _lib.Sampling(s.seed, s.sample_offset, s.spp, s.flags, s.guide_frac)
+
+
+def counters_dict(t: torch.Tensor):
+    v = t.cpu().numpy()
+    return {k: int(v[i]) for i, k in enumerate(_lib.COUNTER_NAMES)}
+
+
+class Context:
+    """A library context on one device, enqueueing on torch's current stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        L = _lib.load()
+        self.device = device
+        s = stream if stream is not None else torch.cuda.current_stream(device)
+        h = C.c_void_p()
+        st = L.nc_ctx_create(device, C.c_void_p(s.cuda_stream), C.byref(h))
+        _check(st, None)
+        self.handle = h
+        self.stream = s
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        _check(_lib.load().nc_ctx_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), self.handle)
+        self.stream = stream
+
+    def set_launch(self, block=0, waves_per_cu=0, samples_per_item=0, lds_levels=-1):
+        ln = _lib.Launch(block, waves_per_cu, samples_per_item, lds_levels)
+        _check(_lib.load().nc_set_launch(self.handle, C.byref(ln)), self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().nc_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def last_error(self):
+        m = _lib.load().nc_last_error(self.handle)
+        return m.decode() if m else ""
+
+
+class Grid:
+    """Hierarchical min/max extinction grid (library-owned device memory)."""
+
+    def __init__(self, ctx: Context, kc: torch.Tensor, desc: FieldDesc, params: GridParams):
+        assert kc.is_cuda and kc.dtype == torch.float32 and kc.is_contiguous()
+        assert tuple(kc.shape) == (desc.nz, desc.ny, desc.nx)
+        self.ctx, self.desc, self.params = ctx, desc, params
+        h = C.c_void_p()
+        d = _desc(desc)
+        p = _lib.GridParams(params.tau_tilde, params.k_gas, params.criterion, 0)
+        _check(_lib.load().nc_grid_build(ctx.handle, _ptr(kc), C.byref(d), C.byref(p), C.byref(h)), ctx.handle)
+        self.handle = h
+        lv = C.c_int32()
+        _check(_lib.load().nc_grid_info(self.handle, C.byref(lv), 0, None))
+        self.L = lv.value
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().nc_grid_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_dims(self, level):
+        d = (C.c_int32 * 3)()
+        _check(_lib.load().nc_grid_info(self.handle, None, level, C.cast(d, C.c_void_p)))
+        return tuple(int(v) for v in d)   # (nx, ny, nz)
+
+    def level(self, level):
+        nx, ny, nz = self.level_dims(level)
+        dev = torch.device("cuda", self.ctx.device)
+        kmin = torch.empty((nz, ny, nx), dtype=torch.float32, device=dev)
+        kmax = torch.empty_like(kmin)
+        mg = torch.empty((nz, ny, nx), dtype=torch.uint8, device=dev)
+        _check(_lib.load().nc_grid_export(self.ctx.handle, self.handle, level, _ptr(kmin), _ptr(kmax), _ptr(mg)),
+               self.ctx.handle)
+        return kmin, kmax, mg
+
+    def leaf_levels(self):
+        d = self.desc
+        out = torch.empty((d.nz, d.ny, d.nx), dtype=torch.uint8, device=torch.device("cuda", self.ctx.device))
+        _check(_lib.load().nc_grid_leaf_levels(self.ctx.handle, self.handle, _ptr(out)), self.ctx.handle)
+        return out
+
+
+def build_grid(ctx: Context, kc: torch.Tensor, desc: FieldDesc, params: GridParams) -> Grid:
+    return Grid(ctx, kc, desc, params)
+
+
+def trace_leaves(ctx: Context, grid: Grid, rays: torch.Tensor, max_visits: int):
+    n = rays.shape[0]
+    dev = rays.device
+    leaf = torch.zeros((n, max_visits, 4), dtype=torch.int32, device=dev)
+    t = torch.zeros((n, max_visits, 2), dtype=torch.float32, device=dev)
+    cnt = torch.zeros(n, dtype=torch.int32, device=dev)
+    _check(_lib.load().nc_trace_leaves(ctx.handle, grid.handle, _ptr(rays.contiguous()), n, max_visits, _ptr(leaf),
+                                       _ptr(t), _ptr(cnt)), ctx.handle)
+    return leaf, t, cnt
+
+
+def new_counters(device):
+    return torch.zeros(_lib.N_COUNTER_WORDS, dtype=torch.int64, device=device)
+
+
+def transmittance(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, rays: torch.Tensor,
+                  sampling: Sampling, counters: torch.Tensor | None = None):
+    n = rays.shape[0]
+    s = torch.zeros(n, dtype=torch.float64, device=rays.device)
+    s2 = torch.zeros_like(s)
+    o = _optics(optics)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_transmittance(ctx.handle, grid.handle, _ptr(kc), C.byref(o), _ptr(rays.contiguous()), n,
+                                        C.byref(sm), _ptr(s), _ptr(s2), _ptr(counters)), ctx.handle)
+    return s, s2
+
+
+def render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: Camera, sampling: Sampling,
+           out_sum: torch.Tensor | None = None, out_sumsq: torch.Tensor | None = None,
+           counters: torch.Tensor | None = None):
+    dev = kc.device
+    if out_sum is None:
+        out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    if out_sumsq is None:
+        out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    o = _optics(optics)
+    c = _camera(camera)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_render(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
+                                 _ptr(out_sum), _ptr(out_sumsq), _ptr(counters)), ctx.handle)
+    return out_sum, out_sumsq
+
+
+def philox4x32_10(ctx: Context, ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:
+    """ctr: (n, 4) int32 (bit patterns of uint32), key: (n, 2) int32 -> (n, 4) int32."""
+    n = ctr.shape[0]
+    out = torch.empty((n, 4), dtype=torch.int32, device=ctr.device)
+    _check(_lib.load().nc_philox4x32_10(ctx.handle, _ptr(ctr.contiguous()), _ptr(key.contiguous()), _ptr(out), n),
+           ctx.handle)
+    return out

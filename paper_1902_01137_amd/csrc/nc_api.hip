@@ -1,0 +1,421 @@
+// nc_api.hip -- host side of the C ABI: contexts, validation, grid storage,
+// and the estimator entry points.  See include/nctrace.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "nc_internal.hpp"
+
+namespace {
+
+thread_local std::string g_create_err;
+
+nc_status fail(nc_ctx *ctx, nc_status st, const std::string &msg)
+{
+    if (ctx)
+        ctx->err = msg;
+    else
+        g_create_err = msg;
+    return st;
+}
+
+nc_status hip_fail(nc_ctx *ctx, hipError_t e, const char *where)
+{
+    std::string m = std::string(where) + ": " + hipGetErrorString(e);
+    return fail(ctx, e == hipErrorOutOfMemory ? NC_ERR_OOM : NC_ERR_DEVICE, m);
+}
+
+bool finite_pos(double v) { return std::isfinite(v) && v > 0.0; }
+
+nc_status check_desc(nc_ctx *ctx, const nc_field_desc *d)
+{
+    if (!d) return fail(ctx, NC_ERR_INVALID_ARG, "field descriptor is NULL");
+    if (d->nx < 1 || d->ny < 1 || d->nz < 1) return fail(ctx, NC_ERR_INVALID_ARG, "field dimensions must be >= 1");
+    if ((long long)d->nx * d->ny * d->nz > (1ll << 33))
+        return fail(ctx, NC_ERR_INVALID_ARG, "field larger than 2^33 cells");
+    if (!finite_pos(d->dx) || !finite_pos(d->dy) || !finite_pos(d->dz))
+        return fail(ctx, NC_ERR_RANGE, "cell sizes must be finite and > 0");
+    if (!std::isfinite(d->x0) || !std::isfinite(d->y0) || !std::isfinite(d->z0))
+        return fail(ctx, NC_ERR_RANGE, "box origin must be finite");
+    if (d->z0 < 0.0) return fail(ctx, NC_ERR_RANGE, "box must lie above the ground (z0 >= 0)");
+    return NC_OK;
+}
+
+nc_status check_optics(nc_ctx *ctx, const nc_optics *o)
+{
+    if (!o) return fail(ctx, NC_ERR_INVALID_ARG, "optics is NULL");
+    if (!(o->ssa >= 0.0 && o->ssa <= 1.0)) return fail(ctx, NC_ERR_RANGE, "ssa must be in [0,1]");
+    if (!(o->g > -1.0 && o->g < 1.0)) return fail(ctx, NC_ERR_RANGE, "g must be in (-1,1)");
+    if (!(o->ground_albedo >= 0.0 && o->ground_albedo <= 1.0))
+        return fail(ctx, NC_ERR_RANGE, "ground albedo must be in [0,1]");
+    if (!std::isfinite(o->sun_zenith_deg) || !std::isfinite(o->sun_azimuth_deg) || !(o->sun_zenith_deg >= 0.0) ||
+        !(o->sun_zenith_deg < 90.0))
+        return fail(ctx, NC_ERR_RANGE, "sun zenith must be in [0,90) degrees");
+    if (!(o->sun_irradiance >= 0.0) || !std::isfinite(o->sun_irradiance))
+        return fail(ctx, NC_ERR_RANGE, "sun irradiance must be finite and >= 0");
+    if (!(o->majorant_scale >= 1.0) || !std::isfinite(o->majorant_scale))
+        return fail(ctx, NC_ERR_RANGE, "majorant_scale must be finite and >= 1");
+    if (o->max_segments < 1) return fail(ctx, NC_ERR_INVALID_ARG, "max_segments must be >= 1");
+    return NC_OK;
+}
+
+nc_status check_grid(nc_ctx *ctx, const nc_grid *g)
+{
+    if (!g) return fail(ctx, NC_ERR_INVALID_ARG, "grid is NULL");
+    if (g->device != ctx->device) return fail(ctx, NC_ERR_STATE, "grid lives on another device");
+    return NC_OK;
+}
+
+nc::OptView make_opt(const nc_optics *o, double k_gas)
+{
+    (void)k_gas;
+    nc::OptView v;
+    const double th = o->sun_zenith_deg * M_PI / 180.0, ph = o->sun_azimuth_deg * M_PI / 180.0;
+    v.ssa = (float)o->ssa;
+    v.g = (float)o->g;
+    v.rho = (float)o->ground_albedo;
+    v.S = (float)o->sun_irradiance;
+    v.mscale = (float)o->majorant_scale;
+    v.sun[0] = (float)(std::sin(th) * std::cos(ph));
+    v.sun[1] = (float)(std::sin(th) * std::sin(ph));
+    v.sun[2] = (float)std::cos(th);
+    v.ground_w = (float)(o->ground_albedo / M_PI * o->sun_irradiance * std::cos(th));
+    v.max_scatter = o->max_scatter;
+    v.max_segments = o->max_segments;
+    return v;
+}
+
+void norm3(double v[3])
+{
+    const double n = std::sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    v[0] /= n;
+    v[1] /= n;
+    v[2] /= n;
+}
+
+void cross3(const double a[3], const double b[3], double c[3])
+{
+    c[0] = a[1] * b[2] - a[2] * b[1];
+    c[1] = a[2] * b[0] - a[0] * b[2];
+    c[2] = a[0] * b[1] - a[1] * b[0];
+}
+
+nc_status make_cam(nc_ctx *ctx, const nc_camera *c, nc::CamView &v)
+{
+    if (!c) return fail(ctx, NC_ERR_INVALID_ARG, "camera is NULL");
+    if (c->type != 0 && c->type != 1) return fail(ctx, NC_ERR_INVALID_ARG, "camera type must be 0 or 1");
+    if (c->width < 1 || c->height < 1 || (long long)c->width * c->height > (1ll << 30))
+        return fail(ctx, NC_ERR_INVALID_ARG, "bad image size");
+    double f[3], r[3], u[3];
+    for (int a = 0; a < 3; ++a) f[a] = c->target[a] - c->pos[a];
+    const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
+    if (!(fn > 0.0) || !std::isfinite(fn)) return fail(ctx, NC_ERR_RANGE, "camera target equals position");
+    norm3(f);
+    cross3(f, c->up, r);
+    const double rn = std::sqrt(r[0] * r[0] + r[1] * r[1] + r[2] * r[2]);
+    if (!(rn > 1e-12)) return fail(ctx, NC_ERR_RANGE, "camera up vector is parallel to the view direction");
+    norm3(r);
+    cross3(r, f, u);
+    if (c->type == 0 && !(c->fov_y_deg > 0.0 && c->fov_y_deg < 180.0))
+        return fail(ctx, NC_ERR_RANGE, "fov_y_deg must be in (0,180)");
+    if (c->type == 1 && !(c->ortho_w > 0.0 && c->ortho_h > 0.0))
+        return fail(ctx, NC_ERR_RANGE, "orthographic extent must be > 0");
+    v.type = c->type;
+    v.W = c->width;
+    v.H = c->height;
+    for (int a = 0; a < 3; ++a) {
+        v.pos[a] = (float)c->pos[a];
+        v.f[a] = (float)f[a];
+        v.r[a] = (float)r[a];
+        v.u[a] = (float)u[a];
+    }
+    if (c->type == 0) {
+        const double t = std::tan(0.5 * c->fov_y_deg * M_PI / 180.0);
+        v.sx = (float)(t * (double)c->width / (double)c->height);
+        v.sy = (float)t;
+    } else {
+        v.sx = (float)c->ortho_w;
+        v.sy = (float)c->ortho_h;
+    }
+    return NC_OK;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+extern "C" {
+
+uint32_t nc_abi_version(void) { return NC_ABI_VERSION; }
+
+nc_status nc_ctx_create(int32_t device, void *hip_stream, nc_ctx **out)
+{
+    if (!out) return fail(nullptr, NC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(nullptr, NC_ERR_DEVICE, "no HIP device available");
+    if (device < 0 || device >= count) return fail(nullptr, NC_ERR_DEVICE, "device index out of range");
+    DeviceGuard guard(device);
+    nc_ctx *ctx = new (std::nothrow) nc_ctx();
+    if (!ctx) return fail(nullptr, NC_ERR_OOM, "host allocation failed");
+    ctx->device = device;
+    ctx->stream = (hipStream_t)hip_stream;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->num_cus = cus;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+        lds > 0)
+        ctx->lds_per_cu = (size_t)lds;
+    e = hipMalloc(&ctx->d_scratch, sizeof(unsigned long long) * nc::kScratchWords);
+    if (e != hipSuccess) {
+        delete ctx;
+        return hip_fail(nullptr, e, "hipMalloc(scratch)");
+    }
+    *out = ctx;
+    return NC_OK;
+}
+
+nc_status nc_ctx_set_stream(nc_ctx *ctx, void *hip_stream)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    ctx->stream = (hipStream_t)hip_stream;
+    return NC_OK;
+}
+
+void nc_ctx_destroy(nc_ctx *ctx)
+{
+    if (!ctx) return;
+    DeviceGuard guard(ctx->device);
+    if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    delete ctx;
+}
+
+const char *nc_last_error(const nc_ctx *ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
+
+nc_status nc_set_launch(nc_ctx *ctx, const nc_launch *launch)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!launch) {
+        ctx->launch = nc_launch{};
+        return NC_OK;
+    }
+    if (launch->block < 0 || launch->block > 1024 || (launch->block % 64) != 0)
+        return fail(ctx, NC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64,1024] (or 0)");
+    if (launch->waves_per_cu < 0 || launch->waves_per_cu > 32)
+        return fail(ctx, NC_ERR_INVALID_ARG, "waves_per_cu must be in [0,32]");
+    if (launch->samples_per_item < 0) return fail(ctx, NC_ERR_INVALID_ARG, "samples_per_item must be >= 0");
+    if (launch->lds_levels < -1 || launch->lds_levels > NC_MAX_LEVELS)
+        return fail(ctx, NC_ERR_INVALID_ARG, "lds_levels must be in [-1, NC_MAX_LEVELS]");
+    ctx->launch = *launch;
+    return NC_OK;
+}
+
+nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *desc, const nc_grid_params *params,
+                        nc_grid **out)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out) return fail(ctx, NC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (!d_kc) return fail(ctx, NC_ERR_INVALID_ARG, "field pointer is NULL");
+    nc_status st = check_desc(ctx, desc);
+    if (st != NC_OK) return st;
+    if (!params) return fail(ctx, NC_ERR_INVALID_ARG, "grid params is NULL");
+    if (!(params->tau_tilde >= 0.0)) return fail(ctx, NC_ERR_RANGE, "tau_tilde must be >= 0");
+    if (!(params->k_gas >= 0.0) || !std::isfinite(params->k_gas))
+        return fail(ctx, NC_ERR_RANGE, "k_gas must be finite and >= 0");
+    if (params->criterion != 0 && params->criterion != 1)
+        return fail(ctx, NC_ERR_INVALID_ARG, "criterion must be 0 or 1");
+    DeviceGuard guard(ctx->device);
+    nc_grid *g = new (std::nothrow) nc_grid();
+    if (!g) return fail(ctx, NC_ERR_OOM, "host allocation failed");
+    g->device = ctx->device;
+    g->n[0] = desc->nx;
+    g->n[1] = desc->ny;
+    g->n[2] = desc->nz;
+    g->lo[0] = desc->x0;
+    g->lo[1] = desc->y0;
+    g->lo[2] = desc->z0;
+    g->h[0] = desc->dx;
+    g->h[1] = desc->dy;
+    g->h[2] = desc->dz;
+    g->params = *params;
+    int nmax = std::max(desc->nx, std::max(desc->ny, desc->nz));
+    int L = 0;
+    while ((1 << L) < nmax) ++L;
+    if (L > NC_MAX_LEVELS - 1) {
+        delete g;
+        return fail(ctx, NC_ERR_INVALID_ARG, "field too large");
+    }
+    g->L = L;
+    size_t total = 0;
+    g->off[0] = 0;
+    for (int l = 1; l <= L; ++l) {
+        g->off[l] = (int)total;
+        total += (size_t)nc::level_dim(g->n[0], l) * nc::level_dim(g->n[1], l) * nc::level_dim(g->n[2], l);
+        if (total > (size_t)0x7fffffff) {
+            delete g;
+            return fail(ctx, NC_ERR_INVALID_ARG, "grid has more than 2^31 nodes");
+        }
+    }
+    g->off[L + 1] = (int)total;
+    for (int l = L + 2; l < NC_MAX_LEVELS + 2; ++l) g->off[l] = (int)total;
+    g->total_nodes = total;
+    hipError_t e = hipMalloc(&g->d_nodes, std::max<size_t>(total, 1) * sizeof(float2));
+    if (e == hipSuccess) e = hipMalloc(&g->d_off, sizeof(int) * (NC_MAX_LEVELS + 2));
+    if (e != hipSuccess) {
+        nc_grid_destroy(g);
+        return hip_fail(ctx, e, "hipMalloc(grid)");
+    }
+    e = hipMemcpyAsync(g->d_off, g->off, sizeof(int) * (NC_MAX_LEVELS + 2), hipMemcpyHostToDevice, ctx->stream);
+    unsigned int *d_bad = reinterpret_cast<unsigned int *>(ctx->d_scratch + 1);
+    unsigned int h_bad = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(d_bad, &h_bad, sizeof(unsigned int), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = nc::launch_build(ctx, g, d_kc, d_bad);
+    if (e == hipSuccess && L == 0) {
+        // a single cell: validate it on the host
+        float v = 0.0f;
+        e = hipMemcpyAsync(&v, d_kc, sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess && (!(v >= 0.0f) || std::isinf(v))) h_bad = 1;
+    }
+    if (e == hipSuccess && L > 0)
+        e = hipMemcpyAsync(&h_bad, d_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        nc_grid_destroy(g);
+        return hip_fail(ctx, e, "grid build");
+    }
+    if (h_bad) {
+        nc_grid_destroy(g);
+        return fail(ctx, NC_ERR_RANGE, "field holds NaN, Inf or negative extinction");
+    }
+    *out = g;
+    return NC_OK;
+}
+
+void nc_grid_destroy(nc_grid *g)
+{
+    if (!g) return;
+    DeviceGuard guard(g->device);
+    if (g->d_nodes) (void)hipFree(g->d_nodes);
+    if (g->d_off) (void)hipFree(g->d_off);
+    delete g;
+}
+
+nc_status nc_grid_info(const nc_grid *g, int32_t *levels, int32_t level, int32_t dims_out[3])
+{
+    if (!g) return fail(nullptr, NC_ERR_INVALID_ARG, "grid is NULL");
+    if (levels) *levels = g->L;
+    if (dims_out) {
+        if (level < 0 || level > g->L) return fail(nullptr, NC_ERR_INVALID_ARG, "level out of range");
+        for (int a = 0; a < 3; ++a) dims_out[a] = nc::level_dim(g->n[a], level);
+    }
+    return NC_OK;
+}
+
+nc_status nc_grid_export(nc_ctx *ctx, const nc_grid *g, int32_t level, float *d_kmin, float *d_kmax,
+                         uint8_t *d_merged)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if (level < 1 || level > g->L) return fail(ctx, NC_ERR_INVALID_ARG, "level must be in [1, L]");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_export(ctx, g, level, d_kmin, d_kmax, d_merged);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "grid export");
+}
+
+nc_status nc_grid_leaf_levels(nc_ctx *ctx, const nc_grid *g, uint8_t *d_leaf_level)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if (!d_leaf_level) return fail(ctx, NC_ERR_INVALID_ARG, "output is NULL");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_leaf_levels(ctx, g, d_leaf_level);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "leaf levels");
+}
+
+nc_status nc_trace_leaves(nc_ctx *ctx, const nc_grid *g, const float *d_rays, int32_t n, int32_t max_visits,
+                          int32_t *d_leaf, float *d_t, int32_t *d_count)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if (n < 0 || max_visits < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative size");
+    if (n == 0) return NC_OK;
+    if (!d_rays || !d_count || (max_visits > 0 && (!d_leaf || !d_t)))
+        return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_trace_leaves(ctx, g, d_rays, n, max_visits, d_leaf, d_t, d_count);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "trace leaves");
+}
+
+nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                           const float *d_rays, int32_t n, const nc_sampling *s, double *d_sum, double *d_sumsq,
+                           nc_counters *d_counters)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
+    if (n < 0 || s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative size");
+    if (n == 0 || s->spp == 0) return NC_OK;
+    if (!d_kc || !d_rays || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_transmittance(ctx, g, d_kc, make_opt(optics, g->params.k_gas), d_rays, n, *s, d_sum,
+                                            d_sumsq, d_counters);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "transmittance");
+}
+
+nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics, const nc_camera *camera,
+                    const nc_sampling *s, double *d_sum, double *d_sumsq, nc_counters *d_counters)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    nc::CamView cam;
+    if ((st = make_cam(ctx, camera, cam)) != NC_OK) return st;
+    if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
+    if (s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative spp");
+    if (s->spp == 0) return NC_OK;
+    if (s->sample_offset + (uint64_t)s->spp > 0xffffffffull)
+        return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + spp must fit in 32 bits");
+    if (!d_kc || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e =
+        nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), cam, *s, d_sum, d_sumsq, d_counters);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
+}
+
+nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int32_t n)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (n < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative size");
+    if (n == 0) return NC_OK;
+    if (!d_ctr || !d_key || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_philox(ctx, d_ctr, d_key, d_out, n);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "philox");
+}
+
+}  // extern "C"

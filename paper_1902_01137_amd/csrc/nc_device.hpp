@@ -1,0 +1,374 @@
+// nc_device.hpp -- device building blocks of the null-collision tracer (gfx950).
+//
+// Counter-based random numbers, ordered crossing of the hierarchical
+// majorant grid, collision sampling with null/real rejection, and the
+// scattering laws.  Everything here is FP32 except the merge criterion of the
+// grid build (FP64).  The whole library is compiled with -ffp-contract=off so
+// that every expression below rounds exactly as written: the traversal relies
+// on each face parameter being the same function of the face index wherever
+// it is evaluated.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nctrace.h"
+
+namespace nc {
+
+constexpr float kPi = 3.14159265358979f;
+constexpr float kInv4Pi = 0.0795774715459477f;
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon et al., SC'11): ten rounds of two 32x32->64-bit
+// multiplies mixed with the key, the key bumped by Weyl constants.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+#if defined(__HIP_DEVICE_COMPILE__)
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
+#else
+        const uint32_t hi0 = (uint32_t)(((uint64_t)0xD2511F53u * c.x) >> 32);
+        const uint32_t hi1 = (uint32_t)(((uint64_t)0xCD9E8D57u * c.z) >> 32);
+#endif
+        const uint32_t lo0 = 0xD2511F53u * c.x;
+        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return c;
+}
+
+// A path's random stream: counter = (a, b, draw, stream), key = seed.  Each
+// Philox call yields four uniforms, consumed in order.
+struct Rng {
+    uint32_t a, b, stream, draw;
+    uint32_t k0, k1;
+    uint32_t q0, q1, q2, q3;
+    int left;
+
+    __device__ void init(uint32_t a_, uint32_t b_, uint32_t stream_, uint64_t seed)
+    {
+        a = a_;
+        b = b_;
+        stream = stream_;
+        draw = 0;
+        k0 = (uint32_t)seed;
+        k1 = (uint32_t)(seed >> 32);
+        left = 0;
+    }
+    // uniform in [0, 1) with 24 random bits
+    __device__ float u01()
+    {
+        if (left == 0) {
+            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            ++draw;
+            q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
+            left = 4;
+        }
+        const uint32_t v = q0;
+        q0 = q1; q1 = q2; q2 = q3;
+        --left;
+        return (float)(v >> 8) * 5.9604644775390625e-08f;
+    }
+    // optical thickness ~ Exp(1)
+    __device__ float exp1() { return -__logf(1.0f - u01()); }
+};
+
+// ---------------------------------------------------------------------------
+// Grid as seen by the kernels.
+// Nodes of levels 1..L are stored level after level, each level [z][y][x]
+// with ceil(n/2^l) nodes per axis; a node is float2(kmin_c, kmax_c) with the
+// merged flag in the sign bit of kmin_c (k_c >= 0, so the bit is free).
+// ---------------------------------------------------------------------------
+struct GridView {
+    int n[3];
+    int L;
+    float lo[3];
+    float h[3];
+    float inv_h[3];
+    float k_gas;
+    const float *kc;
+    const float2 *nodes;
+    const int *off;      // device array: node offset of level l at index l, off[L+1] = total
+};
+
+__host__ __device__ inline int level_dim(int n, int l) { return (n + (1 << l) - 1) >> l; }
+
+__device__ inline bool node_merged(float2 v) { return (__float_as_uint(v.x) >> 31) != 0; }
+__device__ inline float node_kmin(float2 v) { return __uint_as_float(__float_as_uint(v.x) & 0x7fffffffu); }
+
+// Node access with the top levels (l >= lds_first) staged in LDS.
+struct NodeSrc {
+    const float2 *glob;
+    const float2 *lds;   // nodes of levels lds_first..L, same order
+    const int *off;      // per-level offsets (LDS copy)
+    int lds_first;
+    int lds_base;        // off[lds_first]
+    int n0, n1;
+};
+
+__device__ inline float2 fetch_node(const NodeSrc &s, int l, int c0, int c1, int c2, uint32_t &gcount)
+{
+    const int d0 = level_dim(s.n0, l), d1 = level_dim(s.n1, l);
+    const int idx = s.off[l] + ((c2 >> l) * d1 + (c1 >> l)) * d0 + (c0 >> l);
+    if (l >= s.lds_first) return s.lds[idx - s.lds_base];
+    ++gcount;
+    return s.glob[idx];
+}
+
+// ---------------------------------------------------------------------------
+// Ray state for the ordered crossing of the grid (Section 3.1.3).
+//
+// Face j of axis a lies at lo[a] + j h[a]; the ray meets it at
+//   tf(a, j) = ((float)j * h[a] + lo[a] - o[a]) * inv[a]
+// which is monotone in j.  The cell index of axis a at parameter t is defined
+// from the same function (the last face crossed), so a leaf's exit parameter
+// and the next cell are always consistent: every step strictly advances the
+// cell index along its exit axis, and the walk visits at most nx+ny+nz
+// voxels.
+// ---------------------------------------------------------------------------
+struct Ray {
+    float o[3], d[3], inv[3];
+    float t, tend;       // current parameter, exit from the box
+    int c[3];            // current cell
+    int lev;             // current voxel: level and node indices (c >> lev)
+    float khat;          // voxel majorant m (kmax_c + k_gas)
+    float kmin;          // voxel minimum of k_c (for a level-0 voxel: k_c of the cell)
+    float texit;         // voxel exit parameter
+};
+
+__device__ inline float face_t(const GridView &g, const Ray &r, int a, int j)
+{
+    return ((float)j * g.h[a] + g.lo[a] - r.o[a]) * r.inv[a];
+}
+
+__device__ inline int axis_cell(const GridView &g, const Ray &r, int a, float t)
+{
+    const int nmax = g.n[a] - 1;
+    float p = (r.o[a] + t * r.d[a] - g.lo[a]) * g.inv_h[a];
+    int j = (int)floorf(p);
+    j = j < 0 ? 0 : (j > nmax ? nmax : j);
+    if (r.d[a] > 0.0f) {
+        while (j < nmax && face_t(g, r, a, j + 1) <= t) ++j;
+        while (j > 0 && face_t(g, r, a, j) > t) --j;
+    } else {
+        while (j > 0 && face_t(g, r, a, j) <= t) --j;
+        while (j < nmax && face_t(g, r, a, j + 1) > t) ++j;
+    }
+    return j;
+}
+
+// Clip o + t d (t >= tmin) to the box; false if it misses.
+__device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], const float d[3], float tmin)
+{
+    float tin = tmin, tout = INFINITY;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = o[a];
+        r.d[a] = d[a];
+        if (d[a] == 0.0f) {
+            r.inv[a] = INFINITY;
+            const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
+            if (o[a] < b0 || o[a] > b1) return false;
+        } else {
+            r.inv[a] = 1.0f / d[a];
+            float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
+            if (t0 > t1) { float s = t0; t0 = t1; t1 = s; }
+            tin = fmaxf(tin, t0);
+            tout = fminf(tout, t1);
+        }
+    }
+    if (!(tin < tout)) return false;
+    r.t = tin;
+    r.tend = tout;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (d[a] == 0.0f) {
+            int j = (int)floorf((o[a] - g.lo[a]) * g.inv_h[a]);
+            r.c[a] = j < 0 ? 0 : (j > g.n[a] - 1 ? g.n[a] - 1 : j);
+        } else {
+            r.c[a] = axis_cell(g, r, a, tin);
+        }
+    }
+    return true;
+}
+
+// Voxel of the current cell: its coarsest merged ancestor (the cell itself
+// when no ancestor is merged).  Starts at level `hint` and moves up or down;
+// the merged flag is monotone along the ancestry, so the first unmerged
+// parent above a merged node (or the first merged node below an unmerged
+// one) decides.
+__device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, int hint, float mscale,
+                                 uint32_t &node_reads)
+{
+    int l = hint < 0 ? 0 : (hint > g.L ? g.L : hint);
+    float2 nd = make_float2(0.0f, 0.0f);
+    bool found = false;
+    if (l == 0 && g.L >= 1) l = 1;
+    if (l >= 1) {
+        nd = fetch_node(ns, l, r.c[0], r.c[1], r.c[2], node_reads);
+        if (node_merged(nd)) {
+            while (l < g.L) {
+                float2 p = fetch_node(ns, l + 1, r.c[0], r.c[1], r.c[2], node_reads);
+                if (!node_merged(p)) break;
+                nd = p;
+                ++l;
+            }
+            found = true;
+        } else {
+            for (--l; l >= 1; --l) {
+                nd = fetch_node(ns, l, r.c[0], r.c[1], r.c[2], node_reads);
+                if (node_merged(nd)) { found = true; break; }
+            }
+        }
+    }
+    float kmin, kmax;
+    if (found) {
+        kmin = node_kmin(nd);
+        kmax = nd.y;
+    } else {
+        l = 0;
+        kmin = kmax = g.kc[((size_t)r.c[2] * g.n[1] + r.c[1]) * g.n[0] + r.c[0]];
+        ++node_reads;
+    }
+    r.lev = l;
+    r.khat = mscale * (kmax + g.k_gas);
+    r.kmin = kmin;
+    // exit parameter of the voxel (faces clipped to the field)
+    float te = r.tend;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const int i = r.c[a] >> l;
+        if (r.d[a] > 0.0f) {
+            const int e = min((i + 1) << l, g.n[a]);
+            if (e < g.n[a]) te = fminf(te, face_t(g, r, a, e));
+        } else if (r.d[a] < 0.0f) {
+            const int s = i << l;
+            if (s > 0) te = fminf(te, face_t(g, r, a, s));
+        }
+    }
+    r.texit = te < r.t ? r.t : te;
+}
+
+// Move to the voxel after the current one; false when the ray leaves the box.
+__device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale, uint32_t &node_reads)
+{
+    r.t = r.texit;
+    if (!(r.t < r.tend)) return false;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+        if (r.d[a] != 0.0f) r.c[a] = axis_cell(g, r, a, r.t);
+    find_leaf(g, ns, r, r.lev, mscale, node_reads);
+    return true;
+}
+
+// Cell holding the point at parameter t, kept inside the current voxel so
+// that the gathered k never exceeds the voxel's majorant.
+__device__ inline size_t collision_cell(const GridView &g, const Ray &r, float t)
+{
+    const int l = r.lev;
+    int cc[3];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        if (l == 0) {
+            cc[a] = r.c[a];
+        } else {
+            const int base = (r.c[a] >> l) << l;
+            const int top = min(base + (1 << l), g.n[a]) - 1;
+            int j = (int)floorf((r.o[a] + t * r.d[a] - g.lo[a]) * g.inv_h[a]);
+            cc[a] = j < base ? base : (j > top ? top : j);
+        }
+    }
+    return ((size_t)cc[2] * g.n[1] + cc[1]) * g.n[0] + cc[0];
+}
+
+// ---------------------------------------------------------------------------
+// Scattering
+// ---------------------------------------------------------------------------
+__device__ inline float hg_phase(float g, float mu)
+{
+    const float den = 1.0f + g * g - 2.0f * g * mu;
+    return (1.0f - g * g) * kInv4Pi / (den * sqrtf(den));
+}
+
+// Inverse-CDF sample of the HG cosine.
+__device__ inline float hg_sample_mu(float g, float xi)
+{
+    if (fabsf(g) < 1e-4f) return 2.0f * xi - 1.0f;
+    const float s = (1.0f - g * g) / (1.0f - g + 2.0f * g * xi);
+    const float mu = (1.0f + g * g - s * s) / (2.0f * g);
+    return fminf(1.0f, fmaxf(-1.0f, mu));
+}
+
+// Orthonormal basis around unit n (Duff et al., "Building an orthonormal
+// basis, revisited", JCGT 2017), then the direction at cosine mu, azimuth
+// 2 pi u about n.
+__device__ inline void turn(float d[3], float mu, float u)
+{
+    const float sgn = copysignf(1.0f, d[2]);
+    const float a = -1.0f / (sgn + d[2]);
+    const float b = d[0] * d[1] * a;
+    const float b1[3] = {1.0f + sgn * d[0] * d[0] * a, sgn * b, -sgn * d[0]};
+    const float b2[3] = {b, sgn + d[1] * d[1] * a, -d[1]};
+    float sp, cp;
+    sincospif(2.0f * u, &sp, &cp);
+    const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+    float n[3];
+#pragma unroll
+    for (int k = 0; k < 3; ++k) n[k] = mu * d[k] + st * (cp * b1[k] + sp * b2[k]);
+    const float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k) d[k] = n[k] * inv;
+}
+
+// Cosine-weighted direction about +z (Lambertian reflection).
+__device__ inline void lambert(float d[3], float u1, float u2)
+{
+    float sp, cp;
+    sincospif(2.0f * u2, &sp, &cp);
+    const float r = sqrtf(u1);
+    d[0] = r * cp;
+    d[1] = r * sp;
+    d[2] = sqrtf(fmaxf(0.0f, 1.0f - u1));
+}
+
+// ---------------------------------------------------------------------------
+// Per-lane event counters, reduced once per wave at the end of a launch.
+// ---------------------------------------------------------------------------
+struct Counters {
+    uint32_t paths, segments, tentative, nulls, reals, leaf_visits, gathers, node_reads, nee_rays, truncated;
+};
+
+__device__ inline unsigned long long wave_sum(uint32_t v)
+{
+    unsigned long long s = v;
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off);
+    return s;
+}
+
+__device__ inline void flush_counters(const Counters &c, nc_counters *out)
+{
+    if (!out) return;
+    const unsigned long long v[10] = {wave_sum(c.paths), wave_sum(c.segments), wave_sum(c.tentative),
+                                      wave_sum(c.nulls), wave_sum(c.reals), wave_sum(c.leaf_visits),
+                                      wave_sum(c.gathers), wave_sum(c.node_reads), wave_sum(c.nee_rays),
+                                      wave_sum(c.truncated)};
+    if (__lane_id() == 0) {
+        unsigned long long *o = reinterpret_cast<unsigned long long *>(out);
+#pragma unroll
+        for (int k = 0; k < 10; ++k)
+            if (v[k]) atomicAdd(o + k, v[k]);
+    }
+}
+
+}  // namespace nc

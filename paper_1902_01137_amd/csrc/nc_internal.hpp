@@ -1,0 +1,74 @@
+// nc_internal.hpp -- host-side objects of the library and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "nc_device.hpp"
+#include "nctrace.h"
+
+struct nc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    unsigned long long *d_scratch = nullptr;   // work-queue heads and flags (kScratchWords words)
+    nc_launch launch{};
+    int num_cus = 256;
+    size_t lds_per_cu = 160 * 1024;
+};
+
+struct nc_grid {
+    int device = 0;
+    int n[3] = {0, 0, 0};
+    double lo[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+    nc_grid_params params{};
+    int L = 0;
+    int off[NC_MAX_LEVELS + 2] = {};
+    size_t total_nodes = 0;
+    float2 *d_nodes = nullptr;
+    int *d_off = nullptr;
+};
+
+namespace nc {
+
+constexpr int kScratchWords = 64;
+
+// Camera, optics and launch records as the kernels see them (FP32).
+struct CamView {
+    int type, W, H;
+    float pos[3], f[3], r[3], u[3];
+    float sx, sy;        // pinhole: tan(fov/2)*aspect, tan(fov/2); ortho: width, height
+};
+
+struct OptView {
+    float ssa, g, rho, S, mscale;
+    float sun[3];
+    float ground_w;      // rho / pi * S * cos(theta_sun): ground local estimate before transmissivity
+    int max_scatter, max_segments;
+};
+
+struct Shape {
+    int block;
+    int wgs;
+    int spi;             // samples per queue item
+    int lds_first;       // first grid level staged in LDS (L+1: none)
+    int lds_nodes;
+};
+
+GridView grid_view(const nc_grid *g, const float *d_kc);
+Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default);
+
+hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad);
+hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int level, float *kmin, float *kmax, uint8_t *mg);
+hipError_t launch_leaf_levels(const nc_ctx *ctx, const nc_grid *g, uint8_t *out);
+hipError_t launch_trace_leaves(const nc_ctx *ctx, const nc_grid *g, const float *rays, int n, int maxv, int *leaf,
+                               float *t, int *count);
+hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
+                                const float *rays, int n, const nc_sampling &s, double *sum, double *sumsq,
+                                nc_counters *counters);
+hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
+hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
+                         const CamView &cam, const nc_sampling &s, double *sum, double *sumsq, nc_counters *counters);
+
+}  // namespace nc

@@ -1,0 +1,26 @@
+"""Philox4x32-10 on the GPU against the oracle's implementation (bit-exact)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import ctx
+from paper_1902_01137_amd import api
+
+pytestmark = pytest.mark.gpu
+
+
+def test_philox_bit_exact():
+    rng = np.random.default_rng(5)
+    n = 4099
+    ctr = rng.integers(0, 2 ** 32, size=(n, 4), dtype=np.uint64).astype(np.uint32)
+    key = rng.integers(0, 2 ** 32, size=(n, 2), dtype=np.uint64).astype(np.uint32)
+    ctr[0] = 0
+    key[0] = 0
+    ctr[1] = 0xffffffff
+    key[1] = 0xffffffff
+    c = ctx()
+    out = api.philox4x32_10(c, torch.from_numpy(ctr.view(np.int32)).cuda(), torch.from_numpy(key.view(np.int32)).cuda())
+    got = out.cpu().numpy().view(np.uint32)
+    for i in range(n):
+        assert np.array_equal(got[i], oracle.philox4x32_10(ctr[i], key[i])), i
