@@ -192,6 +192,49 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const n
                     const nc_camera *camera, const nc_sampling *sampling, double *d_sum, double *d_sumsq,
                     nc_counters *d_counters);
 
+/* Ground transmissivity under the field by forward photons, with its
+ * sensitivities to the extinction scale s and to the HG asymmetry g
+ * (Section 5.1; derivative of the integral formulation, Eq. 3).
+ *
+ * The sun (optics) lights the top face of the box uniformly: n_photons
+ * photons start at uniform points of the top face going along -omega_sun,
+ * photon i using random stream sampling->sample_offset + i.  The medium's
+ * droplet extinction is extinction_scale * k_c; photons are tracked by
+ * null-collision tracking in the grid's majorant
+ * majorant_scale * (extinction_scale * kmax_c + k_gas) with analog
+ * absorption and HG scattering; at the ground (z = 0) an arrival inside the
+ * box footprint is tallied in ground pixel (i, j) of a px_nx x px_ny grid
+ * over the footprint (i along x, index j*px_nx + i), then the photon is
+ * reflected (Lambertian, probability ground_albedo) or stops.
+ *
+ * Each arrival adds, in pixel order [k][px_ny][px_nx] of d_tally (float64,
+ * ADDED to the buffer):
+ *   k=0: 1, k=1: 1 (sum of squares), k=2: 1 if the photon was never
+ *   scattered or reflected (direct), k=3: sigma_s, k=4: sigma_s^2,
+ *   k=5: sigma_g, k=6: sigma_g^2,
+ * where sigma_s and sigma_g are the path's accumulated scores: real
+ * collision + k_c/k, null collision - k_c/(k_hat - k), scattering
+ * + k_gas/(s k); HG scattering of cosine mu + d ln p(mu)/dg.  The
+ * transmissivity of pixel p is T_p = tally[0][p] * px_nx*px_ny / n_photons
+ * (ground flux over the flux through the top, per unit area), and
+ * dT_p/ds, dT_p/dg are tally[3][p], tally[5][p] times the same factor.
+ * d_global[4] (float64, added): photons escaping upward, absorbed by the
+ * ground inside / outside the footprint, absorbed in the volume; they sum to
+ * n_photons. */
+nc_status nc_flux(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                  double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,
+                  const nc_sampling *sampling, double *d_tally, double *d_global, nc_counters *d_counters);
+
+/* Derivative-path replay of nc_flux: the same photons (same sampling and
+ * n_photons) are traced again and, at every arrival in pixel p, d_grad[p]
+ * times the path's scores is accumulated: d_out[0] += sum grad[p] sigma_s,
+ * d_out[1] += sum grad[p] sigma_g (float64).  Multiplied by
+ * px_nx*px_ny / n_photons this is dL/ds and dL/dg for L = sum_p grad[p] T_p.
+ * d_grad is float64 [px_ny][px_nx]. */
+nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                          double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,
+                          const nc_sampling *sampling, const double *d_grad, double *d_out);
+
 /* Counter-based random numbers (Salmon et al., SC'11): out[i] =
  * Philox4x32-10(counter = d_ctr[4i..4i+3], key = d_key[2i..2i+1]) for i < n.
  * All buffers are uint32 device arrays.  The path tracers draw their random

@@ -35,7 +35,7 @@ class Field(C.Structure):
     _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32), ("pad_", C.c_int32),
                 ("x0", C.c_double), ("y0", C.c_double), ("z0", C.c_double),
                 ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
-                ("k_gas", C.c_double), ("kc", C.POINTER(C.c_float))]
+                ("k_gas", C.c_double), ("kc", C.POINTER(C.c_float)), ("kscale", C.c_double)]
 
 
 class OpticsC(C.Structure):
@@ -82,6 +82,12 @@ def lib():
         L.orc_camera_ray.argtypes = [C.POINTER(CameraC), C.c_int, C.c_int, C.c_double, C.c_double, _P]
         L.orc_render.argtypes = [C.POINTER(Field), C.POINTER(OpticsC), C.POINTER(CameraC), C.c_int32, C.c_uint64,
                                  _P, C.c_int32, _P, _P, _P]
+        L.orc_hg_dlng.argtypes = [C.c_double, C.c_double]
+        L.orc_hg_dlng.restype = C.c_double
+        L.orc_flux.argtypes = [C.POINTER(Field), _P, C.POINTER(OpticsC), C.c_int32, C.c_int32, C.c_int32,
+                               C.c_int64, C.c_uint64, C.c_uint64, _P, _P]
+        L.orc_flux_fd.argtypes = [C.POINTER(Field), C.POINTER(OpticsC), C.c_int32, C.c_double, C.c_int32, C.c_int32,
+                                  C.c_int64, C.c_uint64, C.c_uint64, _P, _P]
         _lib = L
     return _lib
 
@@ -90,11 +96,11 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(C.c_void_p)
 
 
-def make_field(desc, kc: np.ndarray, k_gas: float = 0.0):
+def make_field(desc, kc: np.ndarray, k_gas: float = 0.0, kscale: float = 1.0):
     """Field record pointing at a contiguous float32 (nz, ny, nx) array (kept alive on the record)."""
     kc = np.ascontiguousarray(kc, dtype=np.float32)
     f = Field(desc.nx, desc.ny, desc.nz, 0, desc.x0, desc.y0, desc.z0, desc.dx, desc.dy, desc.dz, float(k_gas),
-              kc.ctypes.data_as(C.POINTER(C.c_float)))
+              kc.ctypes.data_as(C.POINTER(C.c_float)), float(kscale))
     f._keep = kc
     return f
 
@@ -232,3 +238,74 @@ def render(desc, kc, k_gas, optics, cam, spp, seed, pixels=None):
     lib().orc_render(C.byref(f), C.byref(op), C.byref(c), int(spp), int(seed), _ptr(pixels), len(pixels),
                      _ptr(s), _ptr(s2), _ptr(cnt))
     return s, s2, cnt
+
+
+def hg_dlng(g, mu):
+    return lib().orc_hg_dlng(float(g), float(mu))
+
+
+def flux(desc, kc, k_gas, optics, px, n_photons, seed, mode=0, kscale=1.0, grid=None, photon_offset=0):
+    """Forward photons: (tally[7, py, px], glob[4]) as raw sums over arrivals.
+
+    mode 0: exact free paths (transmissivity only); mode 2: delta tracking in
+    `grid` (an OracleGrid over the same kc) with the scale and g scores."""
+    f = make_field(desc, kc, k_gas, kscale)
+    op = make_optics(optics)
+    nx, ny = px
+    tally = np.zeros((7, ny, nx))
+    glob = np.zeros(4)
+    lib().orc_flux(C.byref(f), grid.handle if grid is not None else None, C.byref(op), int(mode), nx, ny,
+                   int(n_photons), int(seed), int(photon_offset), _ptr(tally), _ptr(glob))
+    return tally, glob
+
+
+def flux_fd(desc, kc, k_gas, optics, px, n_photons, seed, which, h=1e-3, kscale=1.0, photon_offset=0,
+            with_total=False):
+    """CRN central differences: out[2, py, px] = sum and sum of squares of the
+    per-photon quotient; with_total also returns (sum, sumsq) of its sum over pixels."""
+    f = make_field(desc, kc, k_gas, kscale)
+    op = make_optics(optics)
+    nx, ny = px
+    out = np.zeros((2, ny, nx))
+    tot = np.zeros(2)
+    lib().orc_flux_fd(C.byref(f), C.byref(op), int(which), float(h), nx, ny, int(n_photons), int(seed),
+                      int(photon_offset), _ptr(out), _ptr(tot))
+    return (out, tot) if with_total else out
+
+
+# ---------------------------------------------------------------------------
+# Independent photon chunks in worker processes (the oracle itself stays
+# serial; chunks use disjoint photon streams).
+# ---------------------------------------------------------------------------
+
+def _flux_chunk(args):
+    kind, desc, kc, k_gas, optics, px, n, seed, off, extra = args
+    if kind == "flux":
+        mode, kscale, tau_tilde = extra
+        grid = OracleGrid(desc, kc, tau_tilde=tau_tilde, k_gas=k_gas) if mode == 2 else None
+        return flux(desc, kc, k_gas, optics, px, n, seed, mode=mode, kscale=kscale, grid=grid, photon_offset=off)
+    which, h = extra
+    return flux_fd(desc, kc, k_gas, optics, px, n, seed, which, h=h, photon_offset=off, with_total=True)
+
+
+def _pool_map(jobs, workers):
+    import multiprocessing as mp
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(workers) as pool:
+        return pool.map(_flux_chunk, jobs)
+
+
+def parallel_flux(desc, kc, k_gas, optics, px, n_photons, seed, mode=0, kscale=1.0, tau_tilde=1.0, workers=8):
+    step = -(-n_photons // workers)
+    jobs = [("flux", desc, kc, k_gas, optics, px, min(step, n_photons - i * step), seed, i * step,
+             (mode, kscale, tau_tilde)) for i in range(workers) if i * step < n_photons]
+    res = _pool_map(jobs, workers)
+    return sum(r[0] for r in res), sum(r[1] for r in res)
+
+
+def parallel_flux_fd(desc, kc, k_gas, optics, px, n_photons, seed, which, h=1e-3, workers=8):
+    step = -(-n_photons // workers)
+    jobs = [("fd", desc, kc, k_gas, optics, px, min(step, n_photons - i * step), seed, i * step, (which, h))
+            for i in range(workers) if i * step < n_photons]
+    res = _pool_map(jobs, workers)
+    return sum(r[0] for r in res), sum(r[1] for r in res)

@@ -103,6 +103,7 @@ typedef struct {
     double x0, y0, z0, dx, dy, dz;
     double k_gas;
     const float *kc;   /* [nz][ny][nx] */
+    double kscale;     /* the medium's droplet extinction is kscale * kc (the grid is built on kc) */
 } orc_field;
 
 typedef struct {
@@ -126,6 +127,12 @@ static void field_arrays(const orc_field *f, int n[3], double lo[3], double h[3]
 static double cell_kc(const orc_field *f, int i, int j, int m)
 {
     return (double)f->kc[((size_t)m * f->ny + j) * f->nx + i];
+}
+
+/* droplet extinction of a cell as the transport sees it */
+static double cell_kd(const orc_field *f, int i, int j, int m)
+{
+    return f->kscale * cell_kc(f, i, j, m);
 }
 
 /* ========================================================================
@@ -516,7 +523,7 @@ static int walker_advance(walker *w, double te, int axis)
 
 static double walker_k(const walker *w)
 {
-    return cell_kc(w->f, w->idx[0], w->idx[1], w->idx[2]) + w->f->k_gas;
+    return cell_kd(w->f, w->idx[0], w->idx[1], w->idx[2]) + w->f->k_gas;
 }
 
 /* Optical depth of k along the ray from t0 to t1 (t1 = INFINITY: to the box
@@ -556,7 +563,7 @@ static int regular_free_path(const orc_field *f, const double o[3], const double
         double te = walker_exit(&w, &axis), k = walker_k(&w), len = te - w.t;
         if (len > 0 && tau_s < k * len) {
             *tcoll = w.t + tau_s / k;
-            *kc_at = cell_kc(f, w.idx[0], w.idx[1], w.idx[2]);
+            *kc_at = cell_kd(f, w.idx[0], w.idx[1], w.idx[2]);
             return 1;
         }
         if (len > 0) tau_s -= k * len;
@@ -587,7 +594,7 @@ static double field_max_kc(const orc_field *f)
     double m = 0.0;
     for (i = 0; i < n; ++i)
         if ((double)f->kc[i] > m) m = (double)f->kc[i];
-    return m;
+    return f->kscale * m;
 }
 
 static double kc_at_point(const orc_field *f, const double x[3])
@@ -601,7 +608,7 @@ static double kc_at_point(const orc_field *f, const double x[3])
         if (p > n[a] - 1) p = n[a] - 1;
         c[a] = (int)p;
     }
-    return cell_kc(f, c[0], c[1], c[2]);
+    return cell_kd(f, c[0], c[1], c[2]);
 }
 
 /* Delta tracking with one homogeneous majorant khat over B. */
@@ -640,7 +647,7 @@ static int delta_hier(const orc_field *f, const orc_grid *g, double m, const dou
         int axis, lev, id[3];
         double te = walker_exit(&w, &axis);
         double kmc = leaf_kmax_c(f, g, w.idx[0], w.idx[1], w.idx[2], &lev, id);
-        double khat = m * (kmc + f->k_gas);
+        double khat = m * (f->kscale * kmc + f->k_gas);
         if (lev != prev[0] || id[0] != prev[1] || id[1] != prev[2] || id[2] != prev[3]) {
             if (cnt) cnt[2]++;
             prev[0] = lev; prev[1] = id[0]; prev[2] = id[1]; prev[3] = id[2];
@@ -893,4 +900,222 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
         sum[i] = acc;
         sumsq[i] = acc2;
     }
+}
+
+/* ========================================================================
+ * Forward photons and the ground transmissivity under a cloud, with its
+ * parametric sensitivities (Section 5.1; the derivative of the integral
+ * formulation, Eq. 3, generalised from the direct transmissivity to paths
+ * with scattering).
+ *
+ * The sun lights the top of the box uniformly: photons start at a uniform
+ * point of the top face going along -omega_sun.  They are tracked with
+ * analog absorption (probability 1 - ssa(x)) and HG scattering; at the
+ * ground an arrival inside the box's footprint is tallied in its ground
+ * pixel (px_nx x px_ny pixels over the footprint, pixel (i, j) = index
+ * j px_nx + i, i along x), then the photon is reflected with probability
+ * rho (Lambertian) or stops.  Every photon ends in exactly one of: escape
+ * upward, absorption by the ground inside / outside the footprint,
+ * absorption in the volume.
+ *
+ * Per arrival the tallies receive 1 (transmissivity; "direct" if the photon
+ * was never scattered or reflected) and the accumulated scores
+ *   sigma_s = sum over tentative collisions of d ln(probability)/d s, with
+ *             k = s k_c + k_g and a majorant that does not depend on s:
+ *             real: k_c / k;  null: -k_c / (k_hat - k);  and, at each
+ *             scattering, d ln ssa(x) / d s = k_g / (s k),
+ *   sigma_g = sum over HG scatterings of d ln p(mu) / d g,
+ * so that the derivative estimates are the means of (arrival) x sigma.
+ * The scores need the tentative collisions of null-collision tracking
+ * (mode 2: the grid's majorant m (s kmax_c + k_g)); mode 0 tracks with exact
+ * free paths and reports the transmissivity only.
+ *
+ * tally[7][px_ny][px_nx]: T sum, T sum of squares, direct-T sum,
+ *   dT/ds sum, dT/ds sum of squares, dT/dg sum, dT/dg sum of squares
+ *   (per-arrival values; the caller scales by A_top / (N a_pixel)).
+ * glob[4]: up-escapes, ground absorptions in / out of the footprint,
+ *   volume absorptions.
+ * ======================================================================== */
+double orc_hg_dlng(double g, double mu)
+{
+    return -2.0 * g / (1.0 - g * g) - 3.0 * (g - mu) / (1.0 + g * g - 2.0 * g * mu);
+}
+
+/* Next real collision by hierarchical delta tracking, accumulating the
+ * scale score of every tentative collision into *sig_s. */
+static int delta_hier_scored(const orc_field *f, const orc_grid *g, double m, const double o[3], const double d[3],
+                             orc_rng *r, double *tcoll, double *kd_at, double *sig_s)
+{
+    walker w;
+    double tau_s;
+    if (!walker_init(&w, f, o, d, 0.0)) return 0;
+    tau_s = -log(1.0 - rng_u01(r));
+    for (;;) {
+        int axis;
+        double te = walker_exit(&w, &axis);
+        double khat = m * (f->kscale * leaf_kmax_c(f, g, w.idx[0], w.idx[1], w.idx[2], NULL, NULL) + f->k_gas);
+        while (te > w.t && khat > 0.0 && tau_s < khat * (te - w.t)) {
+            double kc, k;
+            w.t += tau_s / khat;
+            kc = cell_kc(f, w.idx[0], w.idx[1], w.idx[2]);
+            k = f->kscale * kc + f->k_gas;
+            if (rng_u01(r) * khat < k) {
+                *sig_s += kc / k;
+                *tcoll = w.t;
+                *kd_at = f->kscale * kc;
+                return 1;
+            }
+            *sig_s -= kc / (khat - k);
+            tau_s = -log(1.0 - rng_u01(r));
+        }
+        if (te > w.t) tau_s -= khat * (te - w.t);
+        if (!walker_advance(&w, te, axis)) return 0;
+    }
+}
+
+typedef struct { int pix; int direct; double ss, sg; } orc_arrival;
+
+/* One photon; returns the number of arrivals stored (at most cap). */
+static int photon_walk(const orc_field *f, const orc_grid *g, const orc_optics *op, int mode, orc_rng *r,
+                       int px_nx, int px_ny, orc_arrival *arr, int cap, double *glob)
+{
+    double s[3], o[3], d[3], sig_s = 0.0, sig_g = 0.0;
+    double Lx = f->nx * f->dx, Ly = f->ny * f->dy;
+    int a, scattered = 0, n = 0, segs = 0;
+    sun_dir(op, s);
+    o[0] = f->x0 + rng_u01(r) * Lx;
+    o[1] = f->y0 + rng_u01(r) * Ly;
+    o[2] = f->z0 + f->nz * f->dz;
+    for (a = 0; a < 3; ++a) d[a] = -s[a];
+    for (;;) {
+        double tc = 0.0, kd = 0.0;
+        int hit;
+        if (++segs > op->max_segments) return n;
+        if (mode == 0)
+            hit = regular_free_path(f, o, d, 0.0, -log(1.0 - rng_u01(r)), &tc, &kd);
+        else
+            hit = delta_hier_scored(f, g, op->majorant_scale, o, d, r, &tc, &kd, &sig_s);
+        if (hit) {
+            double k = kd + f->k_gas, ssa = op->ssa * kd / k, nd[3];
+            for (a = 0; a < 3; ++a) o[a] = o[a] + tc * d[a];
+            if (rng_u01(r) >= ssa) { glob[3] += 1.0; return n; }
+            if (f->k_gas > 0.0) sig_s += f->k_gas / (f->kscale * k);
+            {
+                double mu = orc_hg_sample_mu(op->g, rng_u01(r));
+                double phi = 2.0 * ORC_PI * rng_u01(r);
+                rotate_about(d, mu, phi, nd);
+                sig_g += orc_hg_dlng(op->g, mu);
+            }
+            for (a = 0; a < 3; ++a) d[a] = nd[a];
+            scattered = 1;
+        } else if (d[2] < 0.0) {
+            double tg = -o[2] / d[2], x[3];
+            int inside;
+            for (a = 0; a < 3; ++a) x[a] = o[a] + tg * d[a];
+            x[2] = 0.0;
+            inside = x[0] >= f->x0 && x[0] < f->x0 + Lx && x[1] >= f->y0 && x[1] < f->y0 + Ly;
+            if (inside) {
+                int i = (int)floor((x[0] - f->x0) / Lx * px_nx), j = (int)floor((x[1] - f->y0) / Ly * px_ny);
+                if (i > px_nx - 1) i = px_nx - 1;
+                if (j > px_ny - 1) j = px_ny - 1;
+                if (n < cap) {
+                    arr[n].pix = j * px_nx + i;
+                    arr[n].direct = !scattered;
+                    arr[n].ss = sig_s;
+                    arr[n].sg = sig_g;
+                    n++;
+                }
+            }
+            if (rng_u01(r) >= op->rho) { glob[inside ? 1 : 2] += 1.0; return n; }
+            {
+                double u1 = rng_u01(r), u2 = rng_u01(r), rr = sqrt(u1), phi = 2.0 * ORC_PI * u2;
+                d[0] = rr * cos(phi);
+                d[1] = rr * sin(phi);
+                d[2] = sqrt(fmax(0.0, 1.0 - u1));
+            }
+            for (a = 0; a < 3; ++a) o[a] = x[a];
+            scattered = 1;
+        } else {
+            glob[0] += 1.0;
+            return n;
+        }
+    }
+}
+
+#define ORC_MAX_ARRIVALS 4096
+
+void orc_flux(const orc_field *f, const orc_grid *g, const orc_optics *op, int32_t mode, int32_t px_nx,
+              int32_t px_ny, int64_t n_photons, uint64_t seed, uint64_t photon_offset, double *tally, double *glob)
+{
+    size_t np = (size_t)px_nx * px_ny;
+    int64_t p;
+    orc_arrival *arr = (orc_arrival *)malloc(sizeof(orc_arrival) * ORC_MAX_ARRIVALS);
+    for (p = 0; p < n_photons; ++p) {
+        orc_rng r;
+        int n, i;
+        rng_init(&r, seed, (uint64_t)(photon_offset + p));
+        n = photon_walk(f, g, op, mode, &r, px_nx, px_ny, arr, ORC_MAX_ARRIVALS, glob);
+        for (i = 0; i < n; ++i) {
+            size_t q = (size_t)arr[i].pix;
+            tally[0 * np + q] += 1.0;
+            tally[1 * np + q] += 1.0;
+            tally[2 * np + q] += arr[i].direct;
+            tally[3 * np + q] += arr[i].ss;
+            tally[4 * np + q] += arr[i].ss * arr[i].ss;
+            tally[5 * np + q] += arr[i].sg;
+            tally[6 * np + q] += arr[i].sg * arr[i].sg;
+        }
+    }
+    free(arr);
+}
+
+/* Central finite differences with common random numbers: each photon is
+ * traced twice with identical random streams and exact free paths (path
+ * tracking), at parameter + h and - h (which = 0: extinction scale s,
+ * which = 1: asymmetry g).  With exact free-path inversion and inverse-CDF
+ * HG sampling the trajectories move continuously with the parameter.
+ * out[2][px_ny][px_nx]: sum and sum of squares over photons of the
+ * per-photon quotient (arrivals(+h) - arrivals(-h)) / (2h) in each pixel;
+ * tot[2]: the same for the quotient summed over all pixels. */
+void orc_flux_fd(const orc_field *f_in, const orc_optics *op_in, int32_t which, double h, int32_t px_nx,
+                 int32_t px_ny, int64_t n_photons, uint64_t seed, uint64_t photon_offset, double *out, double *tot)
+{
+    size_t np = (size_t)px_nx * px_ny;
+    int64_t p;
+    orc_arrival *ap = (orc_arrival *)malloc(sizeof(orc_arrival) * ORC_MAX_ARRIVALS);
+    orc_arrival *am = (orc_arrival *)malloc(sizeof(orc_arrival) * ORC_MAX_ARRIVALS);
+    double glob[4];
+    for (p = 0; p < n_photons; ++p) {
+        orc_field fp = *f_in, fm = *f_in;
+        orc_optics opp = *op_in, opm = *op_in;
+        orc_rng r;
+        int np_, nm_, i, j;
+        if (which == 0) { fp.kscale += h; fm.kscale -= h; }
+        else { opp.g += h; opm.g -= h; }
+        rng_init(&r, seed, (uint64_t)(photon_offset + p));
+        np_ = photon_walk(&fp, NULL, &opp, 0, &r, px_nx, px_ny, ap, ORC_MAX_ARRIVALS, glob);
+        rng_init(&r, seed, (uint64_t)(photon_offset + p));
+        nm_ = photon_walk(&fm, NULL, &opm, 0, &r, px_nx, px_ny, am, ORC_MAX_ARRIVALS, glob);
+        if (tot) {
+            double q = (np_ - nm_) / (2.0 * h);
+            tot[0] += q;
+            tot[1] += q * q;
+        }
+        /* net arrival difference per pixel touched by this photon */
+        for (i = 0; i < np_ + nm_; ++i) {
+            int pix = i < np_ ? ap[i].pix : am[i - np_].pix, seen = 0, cnt = 0;
+            for (j = 0; j < i; ++j)
+                if ((j < np_ ? ap[j].pix : am[j - np_].pix) == pix) { seen = 1; break; }
+            if (seen) continue;
+            for (j = 0; j < np_; ++j) cnt += ap[j].pix == pix;
+            for (j = 0; j < nm_; ++j) cnt -= am[j].pix == pix;
+            if (cnt != 0) {
+                double q = cnt / (2.0 * h);
+                out[pix] += q;
+                out[np + pix] += q * q;
+            }
+        }
+    }
+    free(ap);
+    free(am);
 }

@@ -78,6 +78,10 @@ _SIGS = [
     ("nc_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P, _P]),
     ("nc_set_launch", C.c_int32, [_P, C.POINTER(Launch)]),
     ("nc_philox4x32_10", C.c_int32, [_P, _P, _P, _P, C.c_int32]),
+    ("nc_flux", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.c_double, C.c_int32, C.c_int32, C.c_uint64,
+                            C.POINTER(Sampling), _P, _P, _P]),
+    ("nc_flux_adjoint", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.c_double, C.c_int32, C.c_int32, C.c_uint64,
+                                    C.POINTER(Sampling), _P, _P]),
 ]
 
 EXPORTED = [s[0] for s in _SIGS]

@@ -191,3 +191,56 @@ def philox4x32_10(ctx: Context, ctr: torch.Tensor, key: torch.Tensor) -> torch.T
     _check(_lib.load().nc_philox4x32_10(ctx.handle, _ptr(ctr.contiguous()), _ptr(key.contiguous()), _ptr(out), n),
            ctx.handle)
     return out
+
+
+def flux(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, n_photons: int,
+         sampling: Sampling, extinction_scale: float = 1.0, counters: torch.Tensor | None = None):
+    """Forward photons (nc_flux): raw tallies [7, py, px] and terminal counts [4], float64 on the device."""
+    nx, ny = px
+    tally = torch.zeros((7, ny, nx), dtype=torch.float64, device=kc.device)
+    glob = torch.zeros(4, dtype=torch.float64, device=kc.device)
+    o = _optics(optics)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_flux(ctx.handle, grid.handle, _ptr(kc), C.byref(o), float(extinction_scale), nx, ny,
+                               int(n_photons), C.byref(sm), _ptr(tally), _ptr(glob), _ptr(counters)), ctx.handle)
+    return tally, glob
+
+
+def flux_adjoint(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, n_photons: int,
+                 sampling: Sampling, grad: torch.Tensor, extinction_scale: float = 1.0):
+    """Derivative-path replay (nc_flux_adjoint): raw [sum grad*sigma_s, sum grad*sigma_g], float64."""
+    nx, ny = px
+    assert tuple(grad.shape) == (ny, nx)
+    out = torch.zeros(2, dtype=torch.float64, device=kc.device)
+    g64 = grad.to(dtype=torch.float64).contiguous()
+    o = _optics(optics)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_flux_adjoint(ctx.handle, grid.handle, _ptr(kc), C.byref(o), float(extinction_scale), nx, ny,
+                                       int(n_photons), C.byref(sm), _ptr(g64), _ptr(out)), ctx.handle)
+    return out
+
+
+class TransmissionFn(torch.autograd.Function):
+    """Ground transmissivity map T(s, g) with gradients through the adjoint kernel.
+
+    forward: photons traced by nc_flux; T_p = arrivals_p * n_pixels / n_photons.
+    backward: nc_flux_adjoint replays the same photons weighting each arrival
+    by grad_T[p], giving dL/ds and dL/dg for the same samples."""
+
+    @staticmethod
+    def forward(fctx, scale, g, lib_ctx, grid, kc, optics, px, n_photons, sampling):
+        import dataclasses
+        op = dataclasses.replace(optics, g=float(g))
+        tally, _ = flux(lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale))
+        f = px[0] * px[1] / float(n_photons)
+        fctx.args = (lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale), f)
+        fctx.dev = scale.device if torch.is_tensor(scale) else kc.device
+        return tally[0] * f
+
+    @staticmethod
+    def backward(fctx, grad_T):
+        lib_ctx, grid, kc, op, px, n_photons, sampling, s, f = fctx.args
+        out = flux_adjoint(lib_ctx, grid, kc, op, px, n_photons, sampling, grad_T, s) * f
+        ds = out[0].to(fctx.dev)
+        dg = out[1].to(fctx.dev)
+        return ds, dg, None, None, None, None, None, None, None

@@ -407,6 +407,49 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_o
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
 }
 
+static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                             double scale, int32_t px_nx, int32_t px_ny, const nc_sampling *s)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
+    if (!(scale > 0.0) || !std::isfinite(scale)) return fail(ctx, NC_ERR_RANGE, "extinction_scale must be > 0");
+    if (px_nx < 1 || px_ny < 1 || (long long)px_nx * px_ny > (1ll << 28))
+        return fail(ctx, NC_ERR_INVALID_ARG, "bad ground pixel grid");
+    if (!d_kc) return fail(ctx, NC_ERR_INVALID_ARG, "field pointer is NULL");
+    return NC_OK;
+}
+
+nc_status nc_flux(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics, double extinction_scale,
+                  int32_t px_nx, int32_t px_ny, uint64_t n_photons, const nc_sampling *s, double *d_tally,
+                  double *d_global, nc_counters *d_counters)
+{
+    nc_status st = flux_common(ctx, g, d_kc, optics, extinction_scale, px_nx, px_ny, s);
+    if (st != NC_OK) return st;
+    if (!d_tally || !d_global) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    if (n_photons == 0) return NC_OK;
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_flux(ctx, g, d_kc, make_opt(optics, g->params.k_gas), (float)extinction_scale, px_nx,
+                                   px_ny, n_photons, *s, d_tally, d_global, nullptr, nullptr, d_counters);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "flux");
+}
+
+nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                          double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,
+                          const nc_sampling *s, const double *d_grad, double *d_out)
+{
+    nc_status st = flux_common(ctx, g, d_kc, optics, extinction_scale, px_nx, px_ny, s);
+    if (st != NC_OK) return st;
+    if (!d_grad || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    if (n_photons == 0) return NC_OK;
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::launch_flux(ctx, g, d_kc, make_opt(optics, g->params.k_gas), (float)extinction_scale, px_nx,
+                                   px_ny, n_photons, *s, nullptr, nullptr, d_grad, d_out, nullptr);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "flux adjoint");
+}
+
 nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int32_t n)
 {
     if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");

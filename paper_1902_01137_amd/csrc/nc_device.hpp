@@ -96,6 +96,7 @@ struct GridView {
     float h[3];
     float inv_h[3];
     float k_gas;
+    float kscale;        // droplet extinction is kscale * kc (the grid holds kc's min and max)
     const float *kc;
     const float2 *nodes;
     const int *off;      // device array: node offset of level l at index l, off[L+1] = total
@@ -141,7 +142,7 @@ struct Ray {
     float t, tend;       // current parameter, exit from the box
     int c[3];            // current cell
     int lev;             // current voxel: level and node indices (c >> lev)
-    float khat;          // voxel majorant m (kmax_c + k_gas)
+    float khat;          // voxel majorant m (kscale kmax_c + k_gas)
     float kmin;          // voxel minimum of k_c (for a level-0 voxel: k_c of the cell)
     float texit;         // voxel exit parameter
 };
@@ -241,7 +242,7 @@ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, i
         ++node_reads;
     }
     r.lev = l;
-    r.khat = mscale * (kmax + g.k_gas);
+    r.khat = mscale * (g.kscale * kmax + g.k_gas);
     r.kmin = kmin;
     // exit parameter of the voxel (faces clipped to the field)
     float te = r.tend;
@@ -369,6 +370,78 @@ __device__ inline void flush_counters(const Counters &c, nc_counters *out)
         for (int k = 0; k < 10; ++k)
             if (v[k]) atomicAdd(o + k, v[k]);
     }
+}
+
+// ===========================================================================
+// One step of null-collision tracking in the piecewise-constant majorant
+// (Section 2.3 and Eq. 2, with the optical thickness tau carried from voxel
+// to voxel): either a tentative collision inside the current voxel, tested
+// against the true k gathered from the field, or a move to the next voxel.
+// ===========================================================================
+enum StepResult { kContinue = 0, kReal = 1, kExit = 2 };
+
+__device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, float &tau, Rng &rng, float mscale,
+                                 bool shadow, float &kc_hit, Counters &cnt)
+{
+    ++cnt.segments;
+    const float ktau = r.khat * (r.texit - r.t);
+    if (r.khat > 0.0f && tau < ktau) {
+        r.t = fminf(r.t + tau / r.khat, r.texit);
+        ++cnt.tentative;
+        const float thr = rng.u01() * r.khat;
+        bool real;
+        if (shadow && thr < g.kscale * r.kmin + g.k_gas) {
+            real = true;                      // below the voxel's minimum: real without reading k
+        } else if (r.lev == 0) {
+            kc_hit = r.kmin;                  // a level-0 voxel is one cell: k is known
+            real = thr < g.kscale * kc_hit + g.k_gas;
+        } else {
+            kc_hit = g.kc[collision_cell(g, r, r.t)];
+            ++cnt.gathers;
+            real = thr < g.kscale * kc_hit + g.k_gas;
+        }
+        if (real) {
+            ++cnt.reals;
+            return kReal;
+        }
+        ++cnt.nulls;
+        tau = rng.exp1();
+        return kContinue;
+    }
+    tau -= ktau;
+    if (!next_leaf(g, ns, r, mscale, cnt.node_reads)) return kExit;
+    ++cnt.leaf_visits;
+    return kContinue;
+}
+
+// Start a ray; a ray that misses the box is set up to exit on its first step.
+__device__ inline void start_ray(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3], const float d[3],
+                                 int hint, float mscale, Counters &cnt)
+{
+    if (ray_setup(g, r, o, d, 0.0f)) {
+        find_leaf(g, ns, r, hint, mscale, cnt.node_reads);
+        ++cnt.leaf_visits;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.o[a] = o[a];
+            r.d[a] = d[a];
+        }
+        r.t = r.tend = r.texit = 0.0f;
+        r.khat = 0.0f;
+        r.kmin = 0.0f;
+        r.lev = hint;
+    }
+}
+
+__device__ inline void stage_levels(const GridView &g, int lds_first, int lds_nodes, float2 *s_nodes, int *s_off)
+{
+    for (int i = threadIdx.x; i < NC_MAX_LEVELS + 2; i += blockDim.x) s_off[i] = i <= g.L + 1 ? g.off[i] : 0;
+    if (lds_nodes > 0) {
+        const int base = g.off[lds_first];
+        for (int i = threadIdx.x; i < lds_nodes; i += blockDim.x) s_nodes[i] = g.nodes[base + i];
+    }
+    __syncthreads();
 }
 
 }  // namespace nc

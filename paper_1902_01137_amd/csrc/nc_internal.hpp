@@ -67,6 +67,9 @@ hipError_t launch_trace_leaves(const nc_ctx *ctx, const nc_grid *g, const float 
 hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                                 const float *rays, int n, const nc_sampling &s, double *sum, double *sumsq,
                                 nc_counters *counters);
+hipError_t launch_flux(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op, float kscale,
+                       int px_nx, int px_ny, unsigned long long n_photons, const nc_sampling &s, double *tally,
+                       double *glob, const double *grad, double *out, nc_counters *counters);
 hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const CamView &cam, const nc_sampling &s, double *sum, double *sumsq, nc_counters *counters);

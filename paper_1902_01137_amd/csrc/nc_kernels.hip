@@ -214,78 +214,6 @@ hipError_t launch_trace_leaves(const nc_ctx *ctx, const nc_grid *g, const float 
 }
 
 // ===========================================================================
-// One step of null-collision tracking in the piecewise-constant majorant
-// (Section 2.3 and Eq. 2, with the optical thickness tau carried from voxel
-// to voxel): either a tentative collision inside the current voxel, tested
-// against the true k gathered from the field, or a move to the next voxel.
-// ===========================================================================
-enum StepResult { kContinue = 0, kReal = 1, kExit = 2 };
-
-__device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, float &tau, Rng &rng, float mscale,
-                                 bool shadow, float &kc_hit, Counters &cnt)
-{
-    ++cnt.segments;
-    const float ktau = r.khat * (r.texit - r.t);
-    if (r.khat > 0.0f && tau < ktau) {
-        r.t = fminf(r.t + tau / r.khat, r.texit);
-        ++cnt.tentative;
-        const float thr = rng.u01() * r.khat;
-        bool real;
-        if (shadow && thr < r.kmin + g.k_gas) {
-            real = true;                      // below the voxel's minimum: real without reading k
-        } else if (r.lev == 0) {
-            kc_hit = r.kmin;                  // a level-0 voxel is one cell: k is known
-            real = thr < kc_hit + g.k_gas;
-        } else {
-            kc_hit = g.kc[collision_cell(g, r, r.t)];
-            ++cnt.gathers;
-            real = thr < kc_hit + g.k_gas;
-        }
-        if (real) {
-            ++cnt.reals;
-            return kReal;
-        }
-        ++cnt.nulls;
-        tau = rng.exp1();
-        return kContinue;
-    }
-    tau -= ktau;
-    if (!next_leaf(g, ns, r, mscale, cnt.node_reads)) return kExit;
-    ++cnt.leaf_visits;
-    return kContinue;
-}
-
-// Start a ray; a ray that misses the box is set up to exit on its first step.
-__device__ inline void start_ray(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3], const float d[3],
-                                 int hint, float mscale, Counters &cnt)
-{
-    if (ray_setup(g, r, o, d, 0.0f)) {
-        find_leaf(g, ns, r, hint, mscale, cnt.node_reads);
-        ++cnt.leaf_visits;
-    } else {
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            r.o[a] = o[a];
-            r.d[a] = d[a];
-        }
-        r.t = r.tend = r.texit = 0.0f;
-        r.khat = 0.0f;
-        r.kmin = 0.0f;
-        r.lev = hint;
-    }
-}
-
-__device__ inline void stage_levels(const GridView &g, int lds_first, int lds_nodes, float2 *s_nodes, int *s_off)
-{
-    for (int i = threadIdx.x; i < NC_MAX_LEVELS + 2; i += blockDim.x) s_off[i] = i <= g.L + 1 ? g.off[i] : 0;
-    if (lds_nodes > 0) {
-        const int base = g.off[lds_first];
-        for (int i = threadIdx.x; i < lds_nodes; i += blockDim.x) s_nodes[i] = g.nodes[base + i];
-    }
-    __syncthreads();
-}
-
-// ===========================================================================
 // Direct transmissivity (Section 2.3): Bernoulli paths, t = 1 if the ray
 // leaves the box before a real collision.
 // ===========================================================================
@@ -504,8 +432,8 @@ __global__ __launch_bounds__(256) void render_kernel(RenderArgs A)
                         ex[a] = r.o[a] + r.t * r.d[a];
                         pd[a] = r.d[a];
                     }
-                    const float k = kc_hit + g.k_gas;
-                    const float ssa = A.op.ssa * kc_hit / k;
+                    const float kd = g.kscale * kc_hit;
+                    const float ssa = A.op.ssa * kd / (kd + g.k_gas);
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
                     w_nee = ssa * hg_phase(A.op.g, mu) * A.op.S;
                     p_cont = ssa;
@@ -675,6 +603,7 @@ GridView grid_view(const nc_grid *g, const float *d_kc)
     }
     v.L = g->L;
     v.k_gas = (float)g->params.k_gas;
+    v.kscale = 1.0f;
     v.kc = d_kc;
     v.nodes = g->d_nodes;
     v.off = g->d_off;

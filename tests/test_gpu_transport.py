@@ -69,7 +69,7 @@ def test_counter_expectations_match_oracle():
     og = oracle.OracleGrid(desc, k, tau_tilde=1.0, k_gas=0.02)
     _, _, oc = og.transmittance(rays, spp, seed=5, mode=2, majorant_scale=2.0)
     n = len(rays) * spp
-    for name, o in (("tentative", oc[0]), ("nulls", oc[1]), ("leaf_visits", oc[2])):
+    for name, o in (("tentative", int(oc[0])), ("nulls", int(oc[1])), ("leaf_visits", int(oc[2]))):
         g = gc[name]
         assert abs(g - o) / max(o, 1) < 0.02, (name, g, o)
     assert gc["paths"] == n
