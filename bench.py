@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "paths/s + time to 1% rel. std err radiance, plain vs guided, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 GRANULE = 64  # bytes moved by one random 4- or 8-byte read from HBM
+PHASES = ("cross", "collide", "event", "ray", "sample")
 
 
 def parse():
@@ -33,6 +34,10 @@ def parse():
     p.add_argument("--spp", type=int, default=None)
     p.add_argument("--no-cpu-baseline", action="store_true")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
+    p.add_argument("--block", type=int, default=0, help="launch knob (0: library default)")
+    p.add_argument("--waves-per-cu", type=int, default=0, help="launch knob (0: library default)")
+    p.add_argument("--spi", type=int, default=0, help="samples per queue item (0: library default)")
+    p.add_argument("--lds-levels", type=int, default=-1, help="grid levels staged in LDS (-1: auto)")
     return p.parse_args()
 
 
@@ -58,6 +63,7 @@ def main():
     paths_per_step = npix * spp
 
     ctx = api.Context(0)
+    ctx.set_launch(args.block, args.waves_per_cu, args.spi, args.lds_levels)
     kc = torch.from_numpy(sc.kc).cuda()
     torch.cuda.synchronize()
     cnt = api.new_counters("cuda")
@@ -121,6 +127,9 @@ def main():
         "per_path": {k: c[k] / max(c["paths"], 1) for k in ("segments", "tentative", "nulls", "reals",
                                                             "leaf_visits", "gathers", "node_reads", "nee_rays")},
         "truncated": c["truncated"],
+        "sched": {"trips": {k: c["trips_" + k] for k in PHASES},
+                  "lanes_per_trip": {k: round(c["lanes_" + k] / max(c["trips_" + k], 1), 2) for k in PHASES},
+                  "ticks_per_trip": {k: round(c["ticks_" + k] / max(c["trips_" + k], 1), 1) for k in PHASES}},
         "rel_std_err": eps,
         "time_to_1pct_s": {"plain": t_1pct, "guided": None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

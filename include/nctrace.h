@@ -125,7 +125,9 @@ typedef struct {
     uint64_t node_reads;     /* grid node reads from global memory */
     uint64_t nee_rays;       /* sun rays traced */
     uint64_t truncated;      /* paths stopped at max_segments */
-    uint64_t reserved[6];
+    uint64_t sched[16];      /* renderer scheduling, per phase (voxel crossing, collision, event, ray
+                                start, sample): [0..4] wave trips, [5..9] active lanes summed over the
+                                trips, [10..14] wave wall-clock ticks spent in the phase */
 } nc_counters;
 
 /* Library ABI version (NC_ABI_VERSION). */

@@ -57,8 +57,9 @@ class Launch(C.Structure):
 
 
 COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visits", "gathers", "node_reads",
-                 "nee_rays", "truncated"]
-N_COUNTER_WORDS = 16
+                 "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
+                                              for b in ("cross", "collide", "event", "ray", "sample")] + ["sched_pad"]
+N_COUNTER_WORDS = 26
 
 # (name, restype, argtypes)
 _P = C.c_void_p

@@ -259,7 +259,7 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
     int nmax = std::max(desc->nx, std::max(desc->ny, desc->nz));
     int L = 0;
     while ((1 << L) < nmax) ++L;
-    if (L > NC_MAX_LEVELS - 1) {
+    if (L > 15) {   // the per-node ancestry mask holds levels 1..15
         delete g;
         return fail(ctx, NC_ERR_INVALID_ARG, "field too large");
     }
@@ -279,6 +279,9 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
     g->total_nodes = total;
     hipError_t e = hipMalloc(&g->d_nodes, std::max<size_t>(total, 1) * sizeof(float2));
     if (e == hipSuccess) e = hipMalloc(&g->d_off, sizeof(int) * (NC_MAX_LEVELS + 2));
+    if (e == hipSuccess && L >= 1)
+        e = hipMalloc(&g->d_mask, sizeof(uint16_t) * (size_t)nc::level_dim(desc->nx, 1) *
+                                      nc::level_dim(desc->ny, 1) * nc::level_dim(desc->nz, 1));
     if (e != hipSuccess) {
         nc_grid_destroy(g);
         return hip_fail(ctx, e, "hipMalloc(grid)");
@@ -316,6 +319,7 @@ void nc_grid_destroy(nc_grid *g)
     DeviceGuard guard(g->device);
     if (g->d_nodes) (void)hipFree(g->d_nodes);
     if (g->d_off) (void)hipFree(g->d_off);
+    if (g->d_mask) (void)hipFree(g->d_mask);
     delete g;
 }
 

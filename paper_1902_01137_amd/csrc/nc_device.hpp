@@ -31,15 +31,11 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-#if defined(__HIP_DEVICE_COMPILE__)
-        const uint32_t hi0 = __umulhi(0xD2511F53u, c.x);
-        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c.z);
-#else
-        const uint32_t hi0 = (uint32_t)(((uint64_t)0xD2511F53u * c.x) >> 32);
-        const uint32_t hi1 = (uint32_t)(((uint64_t)0xCD9E8D57u * c.z) >> 32);
-#endif
-        const uint32_t lo0 = 0xD2511F53u * c.x;
-        const uint32_t lo1 = 0xCD9E8D57u * c.z;
+        // one 32x32->64-bit product per multiplier (a single v_mad_u64_u32)
+        const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c.x;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c.z;
+        const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
         c = U4{hi1 ^ c.y ^ k0, lo1, hi0 ^ c.w ^ k1, lo0};
         k0 += 0x9E3779B9u;
         k1 += 0xBB67AE85u;
@@ -81,6 +77,28 @@ struct Rng {
     }
     // optical thickness ~ Exp(1)
     __device__ float exp1() { return -__logf(1.0f - u01()); }
+
+    // Batched draws: need(k) makes sure k uniforms are buffered (a fresh
+    // Philox block replaces a buffer holding fewer), take() consumes one
+    // without a check.  One refill site per caller keeps the Philox rounds
+    // out of divergent branches.
+    __device__ void need(int k)
+    {
+        if (left < k) {
+            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            ++draw;
+            q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
+            left = 4;
+        }
+    }
+    __device__ float take()
+    {
+        const uint32_t v = q0;
+        q0 = q1; q1 = q2; q2 = q3;
+        --left;
+        return (float)(v >> 8) * 5.9604644775390625e-08f;
+    }
+    __device__ float take_exp1() { return -__logf(1.0f - take()); }
 };
 
 // ---------------------------------------------------------------------------
@@ -100,6 +118,7 @@ struct GridView {
     const float *kc;
     const float2 *nodes;
     const int *off;      // device array: node offset of level l at index l, off[L+1] = total
+    const uint16_t *mask;  // per level-1 node [z][y][x]: bit l (1..L) set if the level-l ancestor is merged
 };
 
 __host__ __device__ inline int level_dim(int n, int l) { return (n + (1 << l) - 1) >> l; }
@@ -130,12 +149,14 @@ __device__ inline float2 fetch_node(const NodeSrc &s, int l, int c0, int c1, int
 // Ray state for the ordered crossing of the grid (Section 3.1.3).
 //
 // Face j of axis a lies at lo[a] + j h[a]; the ray meets it at
-//   tf(a, j) = ((float)j * h[a] + lo[a] - o[a]) * inv[a]
-// which is monotone in j.  The cell index of axis a at parameter t is defined
-// from the same function (the last face crossed), so a leaf's exit parameter
-// and the next cell are always consistent: every step strictly advances the
-// cell index along its exit axis, and the walk visits at most nx+ny+nz
-// voxels.
+//   tf(a, j) = ((float)j * h[a] + lo[a] - o[a]) * inv[a],
+// monotone in j.  A voxel's exit parameter is the smallest tf over its faces
+// (clipped to the box), and every axis whose face attains it is stepped
+// across exactly; the other axes keep a cell inside the voxel's slab (the
+// floor of the position, clamped).  Only the voxel matters to the walk, the
+// exit axes always move forward and no axis steps back across a voxel face,
+// so the walk visits each voxel at most once and ends after at most
+// nx + ny + nz voxels.
 // ---------------------------------------------------------------------------
 struct Ray {
     float o[3], d[3], inv[3];
@@ -145,27 +166,12 @@ struct Ray {
     float khat;          // voxel majorant m (kscale kmax_c + k_gas)
     float kmin;          // voxel minimum of k_c (for a level-0 voxel: k_c of the cell)
     float texit;         // voxel exit parameter
+    int xmask;           // axes whose voxel face is met at texit (bit a)
 };
 
 __device__ inline float face_t(const GridView &g, const Ray &r, int a, int j)
 {
     return ((float)j * g.h[a] + g.lo[a] - r.o[a]) * r.inv[a];
-}
-
-__device__ inline int axis_cell(const GridView &g, const Ray &r, int a, float t)
-{
-    const int nmax = g.n[a] - 1;
-    float p = (r.o[a] + t * r.d[a] - g.lo[a]) * g.inv_h[a];
-    int j = (int)floorf(p);
-    j = j < 0 ? 0 : (j > nmax ? nmax : j);
-    if (r.d[a] > 0.0f) {
-        while (j < nmax && face_t(g, r, a, j + 1) <= t) ++j;
-        while (j > 0 && face_t(g, r, a, j) > t) --j;
-    } else {
-        while (j > 0 && face_t(g, r, a, j) <= t) --j;
-        while (j < nmax && face_t(g, r, a, j + 1) > t) ++j;
-    }
-    return j;
 }
 
 // Clip o + t d (t >= tmin) to the box; false if it misses.
@@ -181,7 +187,7 @@ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], co
             const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
             if (o[a] < b0 || o[a] > b1) return false;
         } else {
-            r.inv[a] = 1.0f / d[a];
+            r.inv[a] = __builtin_amdgcn_rcpf(d[a]);
             float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
             if (t0 > t1) { float s = t0; t0 = t1; t1 = s; }
             tin = fmaxf(tin, t0);
@@ -191,25 +197,61 @@ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], co
     if (!(tin < tout)) return false;
     r.t = tin;
     r.tend = tout;
+    // starting cell: exact on the axis through whose face the ray enters the
+    // box, the floor of the position (clamped) on the others; only the voxel
+    // matters for the walk, and the walk never steps back across a face
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (d[a] == 0.0f) {
-            int j = (int)floorf((o[a] - g.lo[a]) * g.inv_h[a]);
-            r.c[a] = j < 0 ? 0 : (j > g.n[a] - 1 ? g.n[a] - 1 : j);
-        } else {
-            r.c[a] = axis_cell(g, r, a, tin);
-        }
+        int j = (int)floorf((o[a] + tin * d[a] - g.lo[a]) * g.inv_h[a]);
+        j = j < 0 ? 0 : (j > g.n[a] - 1 ? g.n[a] - 1 : j);
+        if (d[a] > 0.0f && tin > tmin && face_t(g, r, a, 0) == tin) j = 0;
+        if (d[a] < 0.0f && tin > tmin && face_t(g, r, a, g.n[a]) == tin) j = g.n[a] - 1;
+        r.c[a] = j;
     }
     return true;
 }
 
+__device__ inline void leaf_exit(const GridView &g, Ray &r);
+
 // Voxel of the current cell: its coarsest merged ancestor (the cell itself
-// when no ancestor is merged).  Starts at level `hint` and moves up or down;
-// the merged flag is monotone along the ancestry, so the first unmerged
-// parent above a merged node (or the first merged node below an unmerged
-// one) decides.
+// when no ancestor is merged).  The ancestry mask of the cell's level-1 node
+// gives the level in one read (highest set bit); the cell's own value is
+// read at the same time, so a level-0 voxel costs one round trip to memory
+// and a coarser one at most two (none when its level is staged in LDS).
 __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, int hint, float mscale,
                                  uint32_t &node_reads)
+{
+    (void)hint;
+    float kmin, kmax;
+    int l = 0;
+    const size_t cell = ((size_t)r.c[2] * g.n[1] + r.c[1]) * g.n[0] + r.c[0];
+    const float kcell = g.kc[cell];
+    ++node_reads;
+    if (g.L >= 1) {
+        const int d0 = level_dim(g.n[0], 1), d1 = level_dim(g.n[1], 1);
+        const uint32_t m = g.mask[((size_t)(r.c[2] >> 1) * d1 + (r.c[1] >> 1)) * d0 + (r.c[0] >> 1)];
+        ++node_reads;
+        l = m ? 31 - __clz(m) : 0;
+    }
+    if (l == 0) {
+        kmin = kmax = kcell;
+    } else {
+        const float2 nd = fetch_node(ns, l, r.c[0], r.c[1], r.c[2], node_reads);
+        kmin = node_kmin(nd);
+        kmax = nd.y;
+    }
+    r.lev = l;
+    r.khat = mscale * (g.kscale * kmax + g.k_gas);
+    r.kmin = kmin;
+    leaf_exit(g, r);
+}
+
+// Reference walk over the levels (kept for the crossing checks): starts at
+// level `hint` and moves up or down; the merged flag is monotone along the
+// ancestry, so the first unmerged parent above a merged node (or the first
+// merged node below an unmerged one) decides.
+__device__ inline void find_leaf_walk(const GridView &g, const NodeSrc &ns, Ray &r, int hint, float mscale,
+                                      uint32_t &node_reads)
 {
     int l = hint < 0 ? 0 : (hint > g.L ? g.L : hint);
     float2 nd = make_float2(0.0f, 0.0f);
@@ -244,19 +286,28 @@ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, i
     r.lev = l;
     r.khat = mscale * (g.kscale * kmax + g.k_gas);
     r.kmin = kmin;
-    // exit parameter of the voxel (faces clipped to the field)
+    leaf_exit(g, r);
+}
+
+// Exit parameter of the current voxel (its faces clipped to the field).
+__device__ inline void leaf_exit(const GridView &g, Ray &r)
+{
+    const int l = r.lev;
     float te = r.tend;
+    float tf[3] = {INFINITY, INFINITY, INFINITY};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int i = r.c[a] >> l;
         if (r.d[a] > 0.0f) {
             const int e = min((i + 1) << l, g.n[a]);
-            if (e < g.n[a]) te = fminf(te, face_t(g, r, a, e));
+            if (e < g.n[a]) tf[a] = face_t(g, r, a, e);
         } else if (r.d[a] < 0.0f) {
             const int s = i << l;
-            if (s > 0) te = fminf(te, face_t(g, r, a, s));
+            if (s > 0) tf[a] = face_t(g, r, a, s);
         }
+        te = fminf(te, tf[a]);
     }
+    r.xmask = (tf[0] == te ? 1 : 0) | (tf[1] == te ? 2 : 0) | (tf[2] == te ? 4 : 0);
     r.texit = te < r.t ? r.t : te;
 }
 
@@ -265,9 +316,19 @@ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, f
 {
     r.t = r.texit;
     if (!(r.t < r.tend)) return false;
+    const int l = r.lev;
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
-        if (r.d[a] != 0.0f) r.c[a] = axis_cell(g, r, a, r.t);
+    for (int a = 0; a < 3; ++a) {
+        if (r.d[a] == 0.0f) continue;
+        const int vlo = (r.c[a] >> l) << l;
+        const int vhi = min(vlo + (1 << l), g.n[a]) - 1;
+        if (r.xmask & (1 << a)) {
+            r.c[a] = r.d[a] > 0.0f ? vhi + 1 : vlo - 1;       // across the exit face
+        } else {
+            int j = (int)floorf((r.o[a] + r.t * r.d[a] - g.lo[a]) * g.inv_h[a]);
+            r.c[a] = j < vlo ? vlo : (j > vhi ? vhi : j);   // still inside the voxel's slab
+        }
+    }
     find_leaf(g, ns, r, r.lev, mscale, node_reads);
     return true;
 }
@@ -320,9 +381,8 @@ __device__ inline void turn(float d[3], float mu, float u)
     const float b = d[0] * d[1] * a;
     const float b1[3] = {1.0f + sgn * d[0] * d[0] * a, sgn * b, -sgn * d[0]};
     const float b2[3] = {b, sgn + d[1] * d[1] * a, -d[1]};
-    float sp, cp;
-    sincospif(2.0f * u, &sp, &cp);
-    const float st = sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
+    const float sp = __builtin_amdgcn_sinf(u), cp = __builtin_amdgcn_cosf(u);   // sin, cos of 2 pi u
+    const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
     float n[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) n[k] = mu * d[k] + st * (cp * b1[k] + sp * b2[k]);
@@ -334,12 +394,11 @@ __device__ inline void turn(float d[3], float mu, float u)
 // Cosine-weighted direction about +z (Lambertian reflection).
 __device__ inline void lambert(float d[3], float u1, float u2)
 {
-    float sp, cp;
-    sincospif(2.0f * u2, &sp, &cp);
-    const float r = sqrtf(u1);
+    const float sp = __builtin_amdgcn_sinf(u2), cp = __builtin_amdgcn_cosf(u2);   // sin, cos of 2 pi u2
+    const float r = __builtin_amdgcn_sqrtf(u1);
     d[0] = r * cp;
     d[1] = r * sp;
-    d[2] = sqrtf(fmaxf(0.0f, 1.0f - u1));
+    d[2] = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - u1));
 }
 
 // ---------------------------------------------------------------------------
@@ -380,16 +439,19 @@ __device__ inline void flush_counters(const Counters &c, nc_counters *out)
 // ===========================================================================
 enum StepResult { kContinue = 0, kReal = 1, kExit = 2 };
 
-__device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, float &tau, Rng &rng, float mscale,
-                                 bool shadow, float &kc_hit, Counters &cnt)
+// Step outcome flags (for wave-level event counting).
+enum StepFlags : uint32_t { kFTentative = 1, kFReal = 2, kFNull = 4, kFGather = 8, kFLeaf = 16 };
+
+// One step; `reads` counts global grid/field reads, `flags` what happened.
+__device__ inline int track_step_f(const GridView &g, const NodeSrc &ns, Ray &r, float &tau, Rng &rng, float mscale,
+                                   bool shadow, float &kc_hit, uint32_t &reads, uint32_t &flags)
 {
-    ++cnt.segments;
     const float ktau = r.khat * (r.texit - r.t);
     if (r.khat > 0.0f && tau < ktau) {
         r.t = fminf(r.t + tau / r.khat, r.texit);
-        ++cnt.tentative;
         const float thr = rng.u01() * r.khat;
         bool real;
+        flags = kFTentative;
         if (shadow && thr < g.kscale * r.kmin + g.k_gas) {
             real = true;                      // below the voxel's minimum: real without reading k
         } else if (r.lev == 0) {
@@ -397,21 +459,38 @@ __device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, f
             real = thr < g.kscale * kc_hit + g.k_gas;
         } else {
             kc_hit = g.kc[collision_cell(g, r, r.t)];
-            ++cnt.gathers;
+            ++reads;
+            flags |= kFGather;
             real = thr < g.kscale * kc_hit + g.k_gas;
         }
         if (real) {
-            ++cnt.reals;
+            flags |= kFReal;
             return kReal;
         }
-        ++cnt.nulls;
+        flags |= kFNull;
         tau = rng.exp1();
         return kContinue;
     }
     tau -= ktau;
-    if (!next_leaf(g, ns, r, mscale, cnt.node_reads)) return kExit;
-    ++cnt.leaf_visits;
+    flags = 0;
+    if (!next_leaf(g, ns, r, mscale, reads)) return kExit;
+    flags = kFLeaf;
     return kContinue;
+}
+
+__device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, float &tau, Rng &rng, float mscale,
+                                 bool shadow, float &kc_hit, Counters &cnt)
+{
+    uint32_t flags = 0, rd = 0;
+    ++cnt.segments;
+    const int res = track_step_f(g, ns, r, tau, rng, mscale, shadow, kc_hit, rd, flags);
+    cnt.node_reads += rd - ((flags & kFGather) ? 1u : 0u);
+    cnt.tentative += (flags & kFTentative) ? 1 : 0;
+    cnt.reals += (flags & kFReal) ? 1 : 0;
+    cnt.nulls += (flags & kFNull) ? 1 : 0;
+    cnt.gathers += (flags & kFGather) ? 1 : 0;
+    cnt.leaf_visits += (flags & kFLeaf) ? 1 : 0;
+    return res;
 }
 
 // Start a ray; a ray that misses the box is set up to exit on its first step.
@@ -432,6 +511,71 @@ __device__ inline void start_ray(const GridView &g, const NodeSrc &ns, Ray &r, c
         r.kmin = 0.0f;
         r.lev = hint;
     }
+}
+
+// The voxel a ray was in when it stopped at an event; a new ray leaving the
+// event point starts in the same voxel unless rounding put its origin in a
+// neighbouring cell, which the check below detects.
+struct VoxelCache {
+    int lev, i0, i1, i2;
+    float khat, kmin;
+};
+
+__device__ inline VoxelCache voxel_of(const Ray &r)
+{
+    return VoxelCache{r.lev, r.c[0] >> r.lev, r.c[1] >> r.lev, r.c[2] >> r.lev, r.khat, r.kmin};
+}
+
+__device__ inline void start_ray_cached(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3],
+                                        const float d[3], const VoxelCache &vc, float mscale, Counters &cnt)
+{
+    if (ray_setup(g, r, o, d, 0.0f)) {
+        if ((r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 && (r.c[2] >> vc.lev) == vc.i2) {
+            r.lev = vc.lev;
+            r.khat = vc.khat;
+            r.kmin = vc.kmin;
+            leaf_exit(g, r);
+        } else {
+            find_leaf(g, ns, r, vc.lev, mscale, cnt.node_reads);
+        }
+        ++cnt.leaf_visits;
+    } else {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            r.o[a] = o[a];
+            r.d[a] = d[a];
+        }
+        r.t = r.tend = r.texit = 0.0f;
+        r.khat = 0.0f;
+        r.kmin = 0.0f;
+        r.lev = vc.lev;
+    }
+}
+
+__device__ inline bool start_ray_cached_r(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3],
+                                          const float d[3], const VoxelCache &vc, float mscale, uint32_t &reads)
+{
+    if (ray_setup(g, r, o, d, 0.0f)) {
+        if ((r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 && (r.c[2] >> vc.lev) == vc.i2) {
+            r.lev = vc.lev;
+            r.khat = vc.khat;
+            r.kmin = vc.kmin;
+            leaf_exit(g, r);
+        } else {
+            find_leaf(g, ns, r, vc.lev, mscale, reads);
+        }
+        return true;
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        r.o[a] = o[a];
+        r.d[a] = d[a];
+    }
+    r.t = r.tend = r.texit = 0.0f;
+    r.khat = 0.0f;
+    r.kmin = 0.0f;
+    r.lev = vc.lev;
+    return false;
 }
 
 __device__ inline void stage_levels(const GridView &g, int lds_first, int lds_nodes, float2 *s_nodes, int *s_off)

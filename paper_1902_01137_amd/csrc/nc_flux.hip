@@ -132,7 +132,8 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                 sig_g += hg_dlng(A.op.g, mu);
                 float nd[3] = {r.d[0], r.d[1], r.d[2]};
                 turn(nd, mu, rng.u01());
-                start_ray(g, ns, r, x, nd, r.lev, A.op.mscale, cnt);
+                const VoxelCache vc = voxel_of(r);
+                start_ray_cached(g, ns, r, x, nd, vc, A.op.mscale, cnt);
                 tau = rng.exp1();
                 scattered = true;
             } else if (r.d[2] < 0.0f) {

@@ -28,11 +28,13 @@ struct nc_grid {
     size_t total_nodes = 0;
     float2 *d_nodes = nullptr;
     int *d_off = nullptr;
+    uint16_t *d_mask = nullptr;   // per level-1 node: bit l set if its level-l ancestor is merged
 };
 
 namespace nc {
 
-constexpr int kScratchWords = 64;
+constexpr int kScratchWords = 256;   // [0] queue head, [1] validation flag, [8..] launch parameters
+constexpr int kScratchRare = 8;
 
 // Camera, optics and launch records as the kernels see them (FP32).
 struct CamView {

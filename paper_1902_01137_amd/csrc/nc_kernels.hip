@@ -92,6 +92,29 @@ __global__ void build_level_kernel(const float2 *__restrict__ child, int c0, int
     }
 }
 
+// Ancestry mask of every level-1 node: bit l set if its level-l ancestor
+// (l = 1..L) is merged.
+__global__ void build_mask_kernel(const float2 *__restrict__ nodes, const int *__restrict__ off, int n0, int n1,
+                                  int n2, int L, uint16_t *__restrict__ mask)
+{
+    const int d0 = level_dim(n0, 1), d1 = level_dim(n1, 1), d2 = level_dim(n2, 1);
+    const long long total = (long long)d0 * d1 * d2;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
+         id += (long long)gridDim.x * blockDim.x) {
+        const int i = (int)(id % d0);
+        const int j = (int)((id / d0) % d1);
+        const int m = (int)(id / ((long long)d0 * d1));
+        uint32_t bits = 0;
+        for (int l = 1; l <= L; ++l) {
+            const int e0 = level_dim(n0, l), e1 = level_dim(n1, l);
+            const int sh = l - 1;
+            const float2 v = nodes[off[l] + ((m >> sh) * e1 + (j >> sh)) * e0 + (i >> sh)];
+            if (node_merged(v)) bits |= 1u << l;
+        }
+        mask[id] = (uint16_t)bits;
+    }
+}
+
 __global__ void export_level_kernel(const float2 *__restrict__ nodes, long long total, float *kmin, float *kmax,
                                     uint8_t *mg)
 {
@@ -148,6 +171,14 @@ hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsign
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
+    }
+    if (g->L >= 1) {
+        const long long total =
+            (long long)level_dim(g->n[0], 1) * level_dim(g->n[1], 1) * level_dim(g->n[2], 1);
+        hipLaunchKernelGGL(build_mask_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream,
+                           (const float2 *)g->d_nodes, (const int *)g->d_off, g->n[0], g->n[1], g->n[2], g->L,
+                           g->d_mask);
+        return hipGetLastError();
     }
     return hipSuccess;
 }
@@ -306,21 +337,10 @@ hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float
 // code whatever their state.  Idle lanes are refilled from the queue with a
 // wave ballot and a prefix count (one atomic per wave refill).
 // ===========================================================================
-struct RenderArgs {
-    GridView g;
-    CamView cam;
-    OptView op;
-    uint64_t seed, sample_offset;
-    int spp, spi;
-    int tiles_x, tiles_y;
-    unsigned long long items;
-    double *sum, *sumsq;
-    nc_counters *counters;
-    unsigned long long *queue;
-    int lds_first, lds_nodes;
-};
+
 
 enum LaneState { kIdle = 0, kPath = 1, kShadow = 2 };
+constexpr int kChunk = 256;   // queue items a wave takes per global atomic
 
 __device__ inline void camera_ray(const CamView &c, int px, int py, float u1, float u2, float o[3], float d[3])
 {
@@ -352,85 +372,210 @@ __device__ inline unsigned int lanes_below(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__global__ __launch_bounds__(256) void render_kernel(RenderArgs A)
+// Parameters of the renderer that only the sample phase needs.  They live in
+// device memory and are read with volatile loads when used, so that they do
+// not occupy scalar registers across the whole loop.
+struct RenderRare {
+    CamView cam;
+    uint64_t seed, sample_offset;
+    unsigned long long items;
+    double *sum, *sumsq;
+    int spp, spi;
+    int tiles_x, tiles_y;
+};
+
+struct RenderArgs {
+    GridView g;
+    OptView op;
+    const RenderRare *rare;
+    nc_counters *counters;
+    unsigned long long *queue;
+    unsigned long long items;
+    int lds_first, lds_nodes;
+};
+
+// Lane phases.  Each loop trip the wave runs the phase that the most lanes
+// are waiting in (ballot counts); the other lanes wait.  Expensive code
+// (events, ray starts, new samples) thus runs for many lanes at once instead
+// of diverging inside every traversal step.
+enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhIdle = 5 };
+
+// After the optical thickness tau has been drawn or carried: a tentative
+// collision inside the current voxel, or a move to the next voxel.
+__device__ inline int voxel_phase(const Ray &r, float tau)
+{
+    return (r.khat > 0.0f && tau < r.khat * (r.texit - r.t)) ? kPhCollide : kPhCross;
+}
+
+// block-level event counters in LDS (same order as nc_counters)
+enum BlockCounter {
+    kCPaths = 0, kCSegments, kCTentative, kCNulls, kCReals, kCLeaf, kCGathers, kCReads, kCNee, kCTrunc,
+    kCTrips0, kCTrips1, kCTrips2, kCTrips3, kCTrips4, kCLanes0, kCLanes1, kCLanes2, kCLanes3, kCLanes4,
+    kCCycles0, kCCycles1, kCCycles2, kCCycles3, kCCycles4, kNumBlockCounters
+};
+
+__device__ inline void wave_count(unsigned long long *s_cnt, int k, bool pred)
+{
+    const unsigned long long m = __ballot(pred);
+    if (m && __lane_id() == 0) atomicAdd(s_cnt + k, (unsigned long long)__popcll(m));
+}
+
+__device__ inline void camera_ray_v(const volatile CamView &c, int px, int py, float u1, float u2, float o[3],
+                                    float d[3])
+{
+    const float W = (float)c.W, H = (float)c.H;
+    if (c.type == 0) {
+        const float sx = (2.0f * ((float)px + u1) / W - 1.0f) * c.sx;
+        const float sy = (1.0f - 2.0f * ((float)py + u2) / H) * c.sy;
+        float v[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = c.pos[a];
+            v[a] = c.f[a] + sx * c.r[a] + sy * c.u[a];
+        }
+        const float inv = rsqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) d[a] = v[a] * inv;
+    } else {
+        const float sx = (((float)px + u1) / W - 0.5f) * c.sx;
+        const float sy = (0.5f - ((float)py + u2) / H) * c.sy;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            o[a] = c.pos[a] + sx * c.r[a] + sy * c.u[a];
+            d[a] = c.f[a];
+        }
+    }
+}
+
+template <int kWavesPerEU>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
     extern __shared__ float2 s_nodes[];
     __shared__ int s_off[NC_MAX_LEVELS + 2];
+    __shared__ unsigned long long s_cnt[kNumBlockCounters];
+    for (int i = threadIdx.x; i < kNumBlockCounters; i += blockDim.x) s_cnt[i] = 0ull;
     stage_levels(A.g, A.lds_first, A.lds_nodes, s_nodes, s_off);
     const GridView &g = A.g;
     const NodeSrc ns{g.nodes, s_nodes, s_off, A.lds_first, s_off[A.lds_first <= g.L ? A.lds_first : 0], g.n[0],
                      g.n[1]};
+    const volatile RenderRare &R = *A.rare;
     const int lane = __lane_id();
-    const int tile_px = A.tiles_x * A.tiles_y * 64;
     const float sun[3] = {A.op.sun[0], A.op.sun[1], A.op.sun[2]};
 
-    Counters cnt = {};
-    int state = kIdle;
-    bool exhausted = false;
+    uint32_t reads = 0;        // global grid and field reads of this lane
+    int phase = kPhSample;
+    bool shadow = false;       // the current ray is a sun ray
+    bool have_item = false;    // the lane holds a queue item with samples left
+    bool traced = false;       // a path has been traced since the last sample phase
+    int res = kContinue;       // outcome of the last step (for the event phase)
+    float kc_hit = 0.0f;
     int pix = 0, s = 0, s_end = 0;
-    double acc = 0.0, acc2 = 0.0;
+    float acc = 0.0f, acc2 = 0.0f;
     float Lp = 0.0f;
-    Ray r;
+    Ray r;                     // at an event, r.o holds the event position (origin of the next ray)
     float tau = 0.0f;
     Rng rng;
-    float ex[3] = {0, 0, 0};   // position of the current event
-    float pd[3] = {0, 0, 0};   // path direction at the current event
+    float pd[3] = {0, 0, 0};   // path direction / direction of the next path ray
     float w_nee = 0.0f;        // sun contribution of the current event if its sun ray gets through
     float p_cont = 0.0f;       // probability that the path goes on after the event
     bool ground_ev = false;
-    int order = 0, segs = 0, hint = g.L;
+    int order = 0, segs = 0;
+    VoxelCache vc{g.L, -1, 0, 0, 0.0f, 0.0f};
+    unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
+    int chunk_left = 0;
+    bool queue_done = false;
 
     for (;;) {
-        bool do_start = false;
-        // ---- refill idle lanes (ballot + prefix count, one atomic per wave)
-        const bool want = state == kIdle && !exhausted;
-        const unsigned long long need = __ballot(want);
-        if (need) {
-            const int leader = __ffsll((unsigned long long)need) - 1;
-            unsigned long long base = 0;
-            if (lane == leader) base = atomicAdd(A.queue, (unsigned long long)__popcll(need));
-            base = __shfl(base, leader);
-            if (want) {
-                const unsigned long long w = base + lanes_below(need);
-                if (w >= A.items) {
-                    exhausted = true;
+        const int n_cross = __popcll(__ballot(phase == kPhCross));
+        const int n_coll = __popcll(__ballot(phase == kPhCollide));
+        const int n_event = __popcll(__ballot(phase == kPhEvent));
+        const int n_ray = __popcll(__ballot(phase == kPhRay));
+        const int n_sample = __popcll(__ballot(phase == kPhSample));
+        if (n_cross + n_coll + n_event + n_ray + n_sample == 0) break;
+        int run = kPhCross, best = n_cross;
+        if (n_coll >= best) { run = kPhCollide; best = n_coll; }
+        if (n_event >= best) { run = kPhEvent; best = n_event; }
+        if (n_ray >= best) { run = kPhRay; best = n_ray; }
+        if (n_sample > best) { run = kPhSample; best = n_sample; }
+        if (lane == 0) {
+            atomicAdd(s_cnt + kCTrips0 + run, 1ull);
+            atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
+        }
+        const long long t_trip = wall_clock64();
+
+        if (run == kPhCross) {
+            // ---- move to the next voxel, carrying the optical thickness
+            const bool active = phase == kPhCross;
+            bool leaf = false, trunc = false;
+            if (active) {
+                tau -= r.khat * (r.texit - r.t);
+                if (!next_leaf(g, ns, r, A.op.mscale, reads)) {
+                    res = kExit;
+                    phase = kPhEvent;
                 } else {
-                    const int blk = (int)(w / (unsigned long long)tile_px);
-                    const int rem = (int)(w % (unsigned long long)tile_px);
-                    const int tile = rem >> 6, within = rem & 63;
-                    const int px = (tile % A.tiles_x) * 8 + (within & 7);
-                    const int py = (tile / A.tiles_x) * 8 + (within >> 3);
-                    s = blk * A.spi;
-                    s_end = min(s + A.spi, A.spp);
-                    if (px < A.cam.W && py < A.cam.H && s < s_end) {
-                        pix = py * A.cam.W + px;
-                        acc = 0.0;
-                        acc2 = 0.0;
-                        do_start = true;
-                        state = kPath;
+                    leaf = true;
+                    phase = voxel_phase(r, tau);
+                    if (++segs >= A.op.max_segments) {
+                        trunc = true;
+                        phase = kPhSample;      // stop the path
                     }
                 }
             }
-        }
-        if (__all(state == kIdle && exhausted)) break;
-
-        bool do_cont = false, do_finish = false;
-        if (state != kIdle && !do_start) {
-            float kc_hit = 0.0f;
-            const bool shadow = state == kShadow;
-            const int res = track_step(g, ns, r, tau, rng, A.op.mscale, shadow, kc_hit, cnt);
-            if (++segs >= A.op.max_segments && res == kContinue) {
-                ++cnt.truncated;
-                do_finish = true;
-            } else if (res == kReal) {
-                if (shadow) {
-                    do_cont = true;                       // sun ray blocked
+            wave_count(s_cnt, kCSegments, active);
+            wave_count(s_cnt, kCLeaf, leaf);
+            wave_count(s_cnt, kCTrunc, trunc);
+        } else if (run == kPhCollide) {
+            // ---- tentative collision in the current voxel: real or null
+            const bool active = phase == kPhCollide;
+            bool real = false, gathered = false, trunc = false;
+            if (active) {
+                rng.need(2);
+                r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
+                const float thr = rng.take() * r.khat;
+                if (shadow && thr < g.kscale * r.kmin + g.k_gas) {
+                    real = true;                // below the voxel's minimum: real without reading k
                 } else {
-                    // volume event: local estimate, then scatter or absorb
+                    if (r.lev == 0) {
+                        kc_hit = r.kmin;        // a level-0 voxel is one cell: k is known
+                    } else {
+                        kc_hit = g.kc[collision_cell(g, r, r.t)];
+                        ++reads;
+                        gathered = true;
+                    }
+                    real = thr < g.kscale * kc_hit + g.k_gas;
+                }
+                if (real) {
+                    res = kReal;
+                    phase = kPhEvent;
+                } else {
+                    tau = rng.take_exp1();
+                    phase = voxel_phase(r, tau);
+                    if (++segs >= A.op.max_segments) {
+                        trunc = true;
+                        phase = kPhSample;
+                    }
+                }
+            }
+            wave_count(s_cnt, kCSegments, active);
+            wave_count(s_cnt, kCTentative, active);
+            wave_count(s_cnt, kCReals, real);
+            wave_count(s_cnt, kCNulls, active && !real);
+            wave_count(s_cnt, kCGathers, gathered);
+            wave_count(s_cnt, kCTrunc, trunc);
+        } else if (run == kPhEvent) {
+            if (phase == kPhEvent) {
+                rng.need(3);
+                bool cont = false;               // go on to the scatter / reflect decision
+                if (shadow) {
+                    if (res == kExit) Lp += w_nee;   // the sun ray got through
+                    cont = true;
+                } else if (res == kReal) {
+                    // volume event: local estimate of the sun, then scatter or absorb
+                    vc = voxel_of(r);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
-                        ex[a] = r.o[a] + r.t * r.d[a];
                         pd[a] = r.d[a];
+                        r.o[a] = r.o[a] + r.t * r.d[a];
                     }
                     const float kd = g.kscale * kc_hit;
                     const float ssa = A.op.ssa * kd / (kd + g.k_gas);
@@ -439,94 +584,176 @@ __global__ __launch_bounds__(256) void render_kernel(RenderArgs A)
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
-                    hint = r.lev;
                     if (A.op.max_scatter >= 0 && order > A.op.max_scatter) {
-                        do_finish = true;
+                        phase = kPhSample;
                     } else if (w_nee > 0.0f) {
-                        ++cnt.nee_rays;
-                        start_ray(g, ns, r, ex, sun, hint, A.op.mscale, cnt);
-                        tau = rng.exp1();
-                        state = kShadow;
+                        shadow = true;
+                        phase = kPhRay;
                     } else {
-                        do_cont = true;
+                        cont = true;
                     }
-                }
-            } else if (res == kExit) {
-                if (shadow) {
-                    Lp += w_nee;                          // sun ray got through
-                    do_cont = true;
                 } else if (r.d[2] < 0.0f) {
                     // ground hit: Lambertian local estimate
                     const float tg = -r.o[2] / r.d[2];
 #pragma unroll
                     for (int a = 0; a < 3; ++a) pd[a] = r.d[a];
-                    ex[0] = r.o[0] + tg * r.d[0];
-                    ex[1] = r.o[1] + tg * r.d[1];
-                    ex[2] = 0.0f;
+                    r.o[0] = r.o[0] + tg * r.d[0];
+                    r.o[1] = r.o[1] + tg * r.d[1];
+                    r.o[2] = 0.0f;
                     w_nee = A.op.ground_w;
                     p_cont = A.op.rho;
                     ground_ev = true;
+                    vc.lev = g.L;
+                    vc.i0 = -1;                  // outside the field: no voxel to reuse
                     ++order;
                     if (A.op.max_scatter >= 0 && order > A.op.max_scatter) {
-                        do_finish = true;
+                        phase = kPhSample;
                     } else if (w_nee > 0.0f) {
-                        ++cnt.nee_rays;
-                        start_ray(g, ns, r, ex, sun, hint, A.op.mscale, cnt);
-                        tau = rng.exp1();
-                        state = kShadow;
+                        shadow = true;
+                        phase = kPhRay;
                     } else {
-                        do_cont = true;
+                        cont = true;
                     }
                 } else {
-                    do_finish = true;                     // escaped upward
+                    phase = kPhSample;           // escaped upward
+                }
+                if (cont) {
+                    shadow = false;
+                    if (A.op.max_scatter >= 0 && order >= A.op.max_scatter) {
+                        phase = kPhSample;
+                    } else if (rng.take() >= p_cont) {
+                        phase = kPhSample;       // absorbed (volume) or not reflected (ground)
+                    } else {
+                        const float u1 = rng.take(), u2 = rng.take();
+                        if (ground_ev)
+                            lambert(pd, u1, u2);
+                        else
+                            turn(pd, hg_sample_mu(A.op.g, u1), u2);
+                        phase = kPhRay;
+                    }
                 }
             }
-        }
-        if (do_cont) {
-            state = kPath;
-            if (A.op.max_scatter >= 0 && order >= A.op.max_scatter) {
-                do_finish = true;
-            } else if (rng.u01() >= p_cont) {
-                do_finish = true;                         // absorbed (volume) or not reflected (ground)
-            } else {
-                const float u1 = rng.u01(), u2 = rng.u01();
-                float nd[3] = {pd[0], pd[1], pd[2]};
-                if (ground_ev)
-                    lambert(nd, u1, u2);
-                else
-                    turn(nd, hg_sample_mu(A.op.g, u1), u2);
-                start_ray(g, ns, r, ex, nd, hint, A.op.mscale, cnt);
-                tau = rng.exp1();
+        } else if (run == kPhRay) {
+            // ---- start the next ray at r.o along pd (path) or towards the sun
+            const bool active = phase == kPhRay;
+            bool hit = false;
+            if (active) {
+                const float o[3] = {r.o[0], r.o[1], r.o[2]};
+                const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
+                hit = start_ray_cached_r(g, ns, r, o, rd, vc, A.op.mscale, reads);
+                rng.need(1);
+                tau = rng.take_exp1();
+                phase = voxel_phase(r, tau);
+            }
+            wave_count(s_cnt, kCNee, active && shadow);
+            wave_count(s_cnt, kCLeaf, hit);
+        } else {
+            // ---- finish the lane's path, then start its next sample or item
+            bool need_item = false;
+            if (phase == kPhSample) {
+                if (have_item) {
+                    if (traced) {
+                        acc += Lp;
+                        acc2 += Lp * Lp;
+                        ++s;
+                    }
+                    if (s >= s_end) {
+                        unsafeAtomicAdd(R.sum + pix, (double)acc);
+                        unsafeAtomicAdd(R.sumsq + pix, (double)acc2);
+                        have_item = false;
+                        need_item = true;
+                    }
+                } else {
+                    need_item = true;
+                }
+            }
+            const bool finished = phase == kPhSample && traced;
+            wave_count(s_cnt, kCPaths, finished);
+            if (phase == kPhSample) traced = false;   // only lanes in this phase: others are mid-path
+            // queue refill in uniform control flow: ballot + prefix count over
+            // the wave's chunk, one global atomic per kChunk items
+            const unsigned long long need = __ballot(need_item);
+            if (need) {
+                const int n_need = __popcll(need);
+                const int rank = (int)lanes_below(need);
+                const int take_new = n_need - chunk_left;
+                unsigned long long nb = A.items;
+                if (take_new > 0 && !queue_done) {
+                    const int leader = __ffsll((unsigned long long)need) - 1;
+                    if (lane == leader) nb = atomicAdd(A.queue, (unsigned long long)kChunk);
+                    nb = __shfl(nb, leader);
+                    if (nb >= A.items) queue_done = true;
+                }
+                if (need_item) {
+                    const unsigned long long w = rank < chunk_left ? chunk_base + (unsigned long long)rank
+                                                                   : nb + (unsigned long long)(rank - chunk_left);
+                    if (w >= A.items) {
+                        phase = kPhIdle;
+                    } else {
+                        const int tx = R.tiles_x, ty = R.tiles_y, spi = R.spi, spp = R.spp;
+                        const int W = R.cam.W, H = R.cam.H;
+                        const unsigned long long tile_px = (unsigned long long)tx * ty * 64ull;
+                        const int blk = (int)(w / tile_px);
+                        const int rem = (int)(w - (unsigned long long)blk * tile_px);
+                        const int tile = rem >> 6, within = rem & 63;
+                        const int px = (tile % tx) * 8 + (within & 7);
+                        const int py = (tile / tx) * 8 + (within >> 3);
+                        s = blk * spi;
+                        s_end = min(s + spi, spp);
+                        if (px < W && py < H && s < s_end) {
+                            pix = py * W + px;
+                            acc = 0.0f;
+                            acc2 = 0.0f;
+                            have_item = true;
+                        }
+                    }
+                }
+                if (take_new > 0) {
+                    chunk_base = nb + (unsigned long long)take_new;
+                    chunk_left = kChunk - take_new;
+                } else {
+                    chunk_base += (unsigned long long)n_need;
+                    chunk_left -= n_need;
+                }
+            }
+            if (phase == kPhSample && have_item) {
+                const uint64_t seed = R.seed, off = R.sample_offset;
+                rng.init((uint32_t)pix, (uint32_t)(off + (uint64_t)s), 0u, seed);
+                const int W = R.cam.W;
+                const int py = pix / W, px = pix - py * W;
+                rng.need(2);
+                const float u1 = rng.take(), u2 = rng.take();
+                float o[3];
+                camera_ray_v(R.cam, px, py, u1, u2, o, pd);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) r.o[a] = o[a];
+                Lp = 0.0f;
+                order = 0;
+                segs = 0;
+                shadow = false;
+                traced = true;
+                vc.lev = g.L;
+                vc.i0 = -1;
+                phase = kPhRay;
             }
         }
-        if (do_finish) {
-            ++cnt.paths;
-            acc += (double)Lp;
-            acc2 += (double)Lp * (double)Lp;
-            if (++s < s_end) {
-                do_start = true;
-            } else {
-                unsafeAtomicAdd(A.sum + pix, acc);
-                unsafeAtomicAdd(A.sumsq + pix, acc2);
-                state = kIdle;
-            }
-        }
-        if (do_start) {
-            rng.init((uint32_t)pix, (uint32_t)(A.sample_offset + (uint64_t)s), 0u, A.seed);
-            const int px = pix % A.cam.W, py = pix / A.cam.W;
-            const float u1 = rng.u01(), u2 = rng.u01();
-            float o[3], d[3];
-            camera_ray(A.cam, px, py, u1, u2, o, d);
-            Lp = 0.0f;
-            order = 0;
-            segs = 0;
-            hint = g.L;
-            state = kPath;
-            start_ray(g, ns, r, o, d, hint, A.op.mscale, cnt);
-            tau = rng.exp1();
-        }
+        if (lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
     }
-    flush_counters(cnt, A.counters);
+    // per-lane reads, then the block's counters to global memory
+    const unsigned long long rsum = wave_sum(reads);
+    if (lane == 0) atomicAdd(s_cnt + kCReads, rsum);
+    __syncthreads();
+    if (A.counters && threadIdx.x == 0) {
+        unsigned long long *o = reinterpret_cast<unsigned long long *>(A.counters);
+        const unsigned long long v[10] = {s_cnt[kCPaths], s_cnt[kCSegments], s_cnt[kCTentative], s_cnt[kCNulls],
+                                          s_cnt[kCReals], s_cnt[kCLeaf], s_cnt[kCGathers],
+                                          s_cnt[kCReads] - s_cnt[kCGathers], s_cnt[kCNee], s_cnt[kCTrunc]};
+        for (int k = 0; k < 10; ++k)
+            if (v[k]) atomicAdd(o + k, v[k]);
+        unsigned long long *sch = reinterpret_cast<unsigned long long *>(A.counters->sched);
+        for (int k = 0; k < 15; ++k)
+            if (s_cnt[kCTrips0 + k]) atomicAdd(sch + k, s_cnt[kCTrips0 + k]);
+    }
 }
 
 __global__ void zero_u64_kernel(unsigned long long *p, int n)
@@ -539,37 +766,47 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
                          const nc_sampling &s, double *sum, double *sumsq, nc_counters *counters)
 {
     Shape sh = choose_shape(ctx, g, 256);
+    RenderRare rare;
+    rare.cam = cam;
+    rare.seed = s.seed;
+    rare.sample_offset = s.sample_offset;
+    rare.spp = s.spp;
+    rare.spi = std::max(1, std::min(sh.spi, s.spp));
+    rare.tiles_x = (cam.W + 7) / 8;
+    rare.tiles_y = (cam.H + 7) / 8;
+    const unsigned long long blocks = (unsigned long long)((s.spp + rare.spi - 1) / rare.spi);
+    rare.items = (unsigned long long)rare.tiles_x * rare.tiles_y * 64ull * blocks;
+    rare.sum = sum;
+    rare.sumsq = sumsq;
     RenderArgs A;
     A.g = grid_view(g, d_kc);
-    A.cam = cam;
     A.op = op;
-    A.seed = s.seed;
-    A.sample_offset = s.sample_offset;
-    A.spp = s.spp;
-    A.spi = std::max(1, std::min(sh.spi, s.spp));
-    A.tiles_x = (cam.W + 7) / 8;
-    A.tiles_y = (cam.H + 7) / 8;
-    const unsigned long long blocks = (unsigned long long)((s.spp + A.spi - 1) / A.spi);
-    A.items = (unsigned long long)A.tiles_x * A.tiles_y * 64ull * blocks;
-    A.sum = sum;
-    A.sumsq = sumsq;
+    A.rare = reinterpret_cast<const RenderRare *>(ctx->d_scratch + kScratchRare);
+    A.items = rare.items;
     A.counters = counters;
     A.queue = ctx->d_scratch;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
+    static_assert(sizeof(RenderRare) <= (kScratchWords - kScratchRare) * sizeof(unsigned long long),
+                  "scratch too small for the renderer parameters");
+    hipError_t e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_scratch, 1);
-    // persistent grid: as many workgroups as can be resident at once
+    // register budget: waves per SIMD the kernel is compiled for (3..6)
+    const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 3;
+    const void *fn = wpe == 3   ? (const void *)render_kernel<3>
+                     : wpe == 4 ? (const void *)render_kernel<4>
+                     : wpe == 5 ? (const void *)render_kernel<5>
+                                : (const void *)render_kernel<6>;
     int resident = 0;
-    if (ctx->launch.waves_per_cu <= 0 &&
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, render_kernel, sh.block,
-                                                     (size_t)sh.lds_nodes * sizeof(float2)) == hipSuccess &&
-        resident > 0)
+    const size_t lds = (size_t)sh.lds_nodes * sizeof(float2);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, fn, sh.block, lds) == hipSuccess && resident > 0)
         sh.wgs = ctx->num_cus * resident;
-    const long long max_wgs = (long long)((A.items + sh.block - 1) / sh.block);
+    const long long max_wgs = (long long)((rare.items + sh.block - 1) / sh.block);
     const int wgs = (int)std::max<long long>(1, std::min<long long>(max_wgs, sh.wgs));
-    hipLaunchKernelGGL(render_kernel, dim3(wgs), dim3(sh.block), (size_t)sh.lds_nodes * sizeof(float2), ctx->stream,
-                       A);
-    return hipGetLastError();
+    void *args[] = {&A};
+    return hipLaunchKernel(fn, dim3(wgs), dim3(sh.block), args, lds, ctx->stream);
 }
 
 __global__ void philox_kernel(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n)
@@ -607,6 +844,7 @@ GridView grid_view(const nc_grid *g, const float *d_kc)
     v.kc = d_kc;
     v.nodes = g->d_nodes;
     v.off = g->d_off;
+    v.mask = g->d_mask;
     return v;
 }
 
