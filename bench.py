@@ -25,6 +25,27 @@ GRANULE = 64  # bytes moved by one random 4- or 8-byte read from HBM
 PHASES = ("cross", "collide", "event", "ray", "sample")
 
 
+def kernel_sources_digest():
+    """SHA-256 over the HIP sources: measured HBM traffic is only reported for the build it was measured on."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    for f in sorted(glob.glob(os.path.join(ROOT, "paper_1902_01137_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed rocprofv3 counter runs, or None if stale."""
+    path = os.path.join(ROOT, "profiles", "render_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    return rec["bytes_per_launch"] if rec.get("sources_sha256") == kernel_sources_digest() else None
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -133,7 +154,8 @@ def main():
         "rel_std_err": eps,
         "time_to_1pct_s": {"plain": t_1pct, "guided": None},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None},
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None},
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
