@@ -59,6 +59,8 @@ def parse():
     p.add_argument("--waves-per-cu", type=int, default=0, help="launch knob (0: library default)")
     p.add_argument("--spi", type=int, default=0, help="samples per queue item (0: library default)")
     p.add_argument("--lds-levels", type=int, default=-1, help="grid levels staged in LDS (-1: auto)")
+    p.add_argument("--no-batch", action="store_true", help="skip the 48-view x 4-sun batched launch")
+    p.add_argument("--batch-spp", type=int, default=4)
     return p.parse_args()
 
 
@@ -157,9 +159,31 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None},
     }
+    if args.workload == "cumulus" and not args.no_batch:
+        out["batch"] = batch_run(ctx, sc, kc, args.batch_spp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def batch_run(ctx, sc, kc, spp):
+    """48 views (256^2 .. 1024^2) x 4 sun zeniths of the same field in one persistent launch."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    views = inputs.batch_views()
+    jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})) for cam, sz in views]
+    px = sum(c.width * c.height for c, _ in jobs)
+    smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp)
+    api.render_batch(ctx, g, kc, jobs, smp)                       # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "ms": dt * 1e3,
+            "paths_per_s": px * spp / dt}
 
 
 def cpu_baseline(sc, spp, budget_s):

@@ -102,15 +102,18 @@ typedef struct {
     double fov_y_deg, ortho_w, ortho_h;
 } nc_camera;
 
-/* Sampling: seed keys the random streams; sample s of pixel p uses stream
- * (p, sample_offset + s), so a run with sample_offset = n continues one that
- * took n samples per pixel. */
+/* Sampling: seed keys the random streams; sample s of pixel p of job j uses
+ * the Philox counter (p, sample_offset + s, draw, stream + j), so a run with
+ * sample_offset = n continues one that took n samples per pixel, and runs
+ * with different `stream` values are independent. */
 typedef struct {
     uint64_t seed;
     uint64_t sample_offset;
     int32_t spp;
     int32_t flags;
     double guide_frac;
+    uint32_t stream;
+    uint32_t pad_;
 } nc_sampling;
 
 /* Per-call event counters (summed over all paths of the call). */
@@ -243,6 +246,18 @@ nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, c
  * numbers from this generator; the entry point exposes it for testing. */
 nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int32_t n);
 
+/* Many views and suns in one persistent launch: job j renders camera cams[j]
+ * under optics[j] into d_sum/d_sumsq starting at element out_offsets[j]
+ * (host array; image j occupies cams[j].height * cams[j].width elements).
+ * The medium's parameters (ssa, g, majorant_scale, max_scatter,
+ * max_segments) must be equal across jobs; the sun (zenith, azimuth,
+ * irradiance) and the ground albedo may differ.  Queue items of all jobs are
+ * drawn from one work queue, so views of uneven size balance across the
+ * GPU.  Random streams: job j uses stream sampling->stream + j. */
+nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
+                          const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *sampling,
+                          double *d_sum, double *d_sumsq, nc_counters *d_counters);
+
 /* Launch-shape knobs of the path-tracing kernels (0 = library default). */
 typedef struct {
     int32_t block;          /* threads per workgroup (multiple of 64) */
@@ -251,6 +266,17 @@ typedef struct {
     int32_t lds_levels;     /* top grid levels staged in LDS (-1: as many as fit) */
 } nc_launch;
 nc_status nc_set_launch(nc_ctx *ctx, const nc_launch *launch);
+nc_status nc_get_launch(const nc_ctx *ctx, nc_launch *launch);
+
+/* Autotuner: renders the given view with a few spp under candidate launch
+ * shapes (samples per queue item, workgroup size, register budget, LDS-staged
+ * levels), timing each with HIP events on the context's stream, and leaves
+ * the fastest in the context (nc_get_launch reads it back).  d_sum/d_sumsq
+ * are scratch images of the camera's size (overwritten).  *best_ms receives
+ * the fastest time (may be NULL).  Synchronises the stream. */
+nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                             const nc_camera *camera, const nc_sampling *sampling, double *d_sum, double *d_sumsq,
+                             double *best_ms);
 
 #ifdef __cplusplus
 }

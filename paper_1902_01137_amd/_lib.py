@@ -48,7 +48,7 @@ class Camera(C.Structure):
 
 class Sampling(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("sample_offset", C.c_uint64), ("spp", C.c_int32), ("flags", C.c_int32),
-                ("guide_frac", C.c_double)]
+                ("guide_frac", C.c_double), ("stream", C.c_uint32), ("pad_", C.c_uint32)]
 
 
 class Launch(C.Structure):
@@ -78,6 +78,10 @@ _SIGS = [
     ("nc_transmittance", C.c_int32, [_P, _P, _P, C.POINTER(Optics), _P, C.c_int32, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P, _P]),
     ("nc_set_launch", C.c_int32, [_P, C.POINTER(Launch)]),
+    ("nc_get_launch", C.c_int32, [_P, C.POINTER(Launch)]),
+    ("nc_render_batch", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
+    ("nc_autotune_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
+                                       C.POINTER(C.c_double)]),
     ("nc_philox4x32_10", C.c_int32, [_P, _P, _P, _P, C.c_int32]),
     ("nc_flux", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.c_double, C.c_int32, C.c_int32, C.c_uint64,
                             C.POINTER(Sampling), _P, _P, _P]),

@@ -43,7 +43,7 @@ def _camera(c: Camera):
 
 
 def _sampling(s: Sampling):
-    return _lib.Sampling(s.seed, s.sample_offset, s.spp, s.flags, s.guide_frac)
+    return _lib.Sampling(s.seed, s.sample_offset, s.spp, s.flags, s.guide_frac, s.stream, 0)
 
 
 def counters_dict(t: torch.Tensor):
@@ -71,6 +71,12 @@ class Context:
     def set_launch(self, block=0, waves_per_cu=0, samples_per_item=0, lds_levels=-1):
         ln = _lib.Launch(block, waves_per_cu, samples_per_item, lds_levels)
         _check(_lib.load().nc_set_launch(self.handle, C.byref(ln)), self.handle)
+
+    def get_launch(self):
+        ln = _lib.Launch()
+        _check(_lib.load().nc_get_launch(self.handle, C.byref(ln)), self.handle)
+        return dict(block=ln.block, waves_per_cu=ln.waves_per_cu, samples_per_item=ln.samples_per_item,
+                    lds_levels=ln.lds_levels)
 
     def close(self):
         if getattr(self, "handle", None):
@@ -244,3 +250,37 @@ class TransmissionFn(torch.autograd.Function):
         ds = out[0].to(fctx.dev)
         dg = out[1].to(fctx.dev)
         return ds, dg, None, None, None, None, None, None, None
+
+
+def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, sampling: Sampling,
+                 counters: torch.Tensor | None = None):
+    """Render many (camera, optics) jobs in one persistent launch (nc_render_batch).
+
+    Returns (sum, sumsq, offsets): flat float64 buffers holding the images one
+    after the other, and each image's first element."""
+    n = len(jobs)
+    cams = (_lib.Camera * n)(*[_camera(c) for c, _ in jobs])
+    opts = (_lib.Optics * n)(*[_optics(o) for _, o in jobs])
+    offs, total = [], 0
+    for c, _ in jobs:
+        offs.append(total)
+        total += c.width * c.height
+    off_arr = (C.c_uint64 * n)(*offs)
+    s = torch.zeros(total, dtype=torch.float64, device=kc.device)
+    s2 = torch.zeros_like(s)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_render_batch(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
+                                       C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm), _ptr(s),
+                                       _ptr(s2), _ptr(counters)), ctx.handle)
+    return s, s2, offs
+
+
+def autotune_render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: Camera, sampling: Sampling):
+    """Pick the fastest launch shape for this view (nc_autotune_render); returns (launch dict, best ms)."""
+    s = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=kc.device)
+    s2 = torch.zeros_like(s)
+    best = C.c_double()
+    _check(_lib.load().nc_autotune_render(ctx.handle, grid.handle, _ptr(kc), C.byref(_optics(optics)),
+                                          C.byref(_camera(camera)), C.byref(_sampling(sampling)), _ptr(s), _ptr(s2),
+                                          C.byref(best)), ctx.handle)
+    return ctx.get_launch(), best.value

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <vector>
 
 #include "nc_internal.hpp"
 
@@ -144,6 +145,35 @@ nc_status make_cam(nc_ctx *ctx, const nc_camera *c, nc::CamView &v)
     return NC_OK;
 }
 
+nc::JobView make_job(const nc::CamView &cam, const nc_optics *o, unsigned long long out_off)
+{
+    nc::JobView j{};
+    const double th = o->sun_zenith_deg * M_PI / 180.0, ph = o->sun_azimuth_deg * M_PI / 180.0;
+    j.cam = cam;
+    j.sun[0] = (float)(std::sin(th) * std::cos(ph));
+    j.sun[1] = (float)(std::sin(th) * std::sin(ph));
+    j.sun[2] = (float)std::cos(th);
+    j.S = (float)o->sun_irradiance;
+    j.rho = (float)o->ground_albedo;
+    j.out_off = out_off;
+    return j;
+}
+
+hipError_t ensure_jobs(nc_ctx *ctx, size_t n)
+{
+    if (ctx->jobs_cap >= n) return hipSuccess;
+    if (ctx->d_jobs) {
+        hipError_t e = hipFree(ctx->d_jobs);
+        ctx->d_jobs = nullptr;
+        ctx->jobs_cap = 0;
+        if (e != hipSuccess) return e;
+    }
+    const size_t cap = (n + 63) / 64 * 64;
+    hipError_t e = hipMalloc(&ctx->d_jobs, cap * sizeof(nc::JobView));
+    if (e == hipSuccess) ctx->jobs_cap = cap;
+    return e;
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -204,6 +234,7 @@ void nc_ctx_destroy(nc_ctx *ctx)
     if (!ctx) return;
     DeviceGuard guard(ctx->device);
     if (ctx->d_scratch) (void)hipFree(ctx->d_scratch);
+    if (ctx->d_jobs) (void)hipFree(ctx->d_jobs);
     delete ctx;
 }
 
@@ -406,9 +437,113 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_o
         return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + spp must fit in 32 bits");
     if (!d_kc || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     DeviceGuard guard(ctx->device);
-    hipError_t e =
-        nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), cam, *s, d_sum, d_sumsq, d_counters);
+    const nc::JobView job = make_job(cam, optics, 0);
+    hipError_t e = ensure_jobs(ctx, 1);
+    if (e == hipSuccess)
+        e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), &job, 1, *s, d_sum, d_sumsq,
+                              d_counters, (nc::JobView *)ctx->d_jobs);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
+}
+
+nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
+                          const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *s, double *d_sum,
+                          double *d_sumsq, nc_counters *d_counters)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    nc_status st = check_grid(ctx, g);
+    if (st != NC_OK) return st;
+    if (n_jobs < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative job count");
+    if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
+    if (s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative spp");
+    if (n_jobs == 0 || s->spp == 0) return NC_OK;
+    if (!cams || !optics || !out_offsets || !d_kc || !d_sum || !d_sumsq)
+        return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    if (s->sample_offset + (uint64_t)s->spp > 0xffffffffull)
+        return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + spp must fit in 32 bits");
+    std::vector<nc::JobView> jobs((size_t)n_jobs);
+    for (int j = 0; j < n_jobs; ++j) {
+        if ((st = check_optics(ctx, optics + j)) != NC_OK) return st;
+        const nc_optics &a = optics[0], &b = optics[j];
+        if (a.ssa != b.ssa || a.g != b.g || a.majorant_scale != b.majorant_scale || a.max_scatter != b.max_scatter ||
+            a.max_segments != b.max_segments)
+            return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
+        nc::CamView cam;
+        if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;
+        jobs[j] = make_job(cam, optics + j, out_offsets[j]);
+    }
+    DeviceGuard guard(ctx->device);
+    hipError_t e = ensure_jobs(ctx, (size_t)n_jobs);
+    if (e == hipSuccess)
+        e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), jobs.data(), n_jobs, *s, d_sum,
+                              d_sumsq, d_counters, (nc::JobView *)ctx->d_jobs);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render batch");
+}
+
+nc_status nc_get_launch(const nc_ctx *ctx, nc_launch *launch)
+{
+    if (!ctx || !launch) return fail(nullptr, NC_ERR_INVALID_ARG, "NULL argument");
+    *launch = ctx->launch;
+    return NC_OK;
+}
+
+nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                             const nc_camera *camera, const nc_sampling *s, double *d_sum, double *d_sumsq,
+                             double *best_ms)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!s || s->spp < 1) return fail(ctx, NC_ERR_INVALID_ARG, "autotuning needs spp >= 1");
+    // coordinate descent over the knobs, starting from the library defaults
+    const int spis[] = {1, 2, 4, 8, 16};
+    const int blocks[] = {64, 128, 256};
+    const int waves[] = {12, 16};
+    const int ldsl[] = {0, 2, -1};
+    nc_launch cur{256, 12, 4, -1};
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    DeviceGuard guard(ctx->device);
+    hipError_t he = hipEventCreate(&e0);
+    if (he == hipSuccess) he = hipEventCreate(&e1);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipEventCreate");
+    const size_t npix = (size_t)std::max(1, camera ? camera->width : 1) * std::max(1, camera ? camera->height : 1);
+    auto time_one = [&](const nc_launch &ln, float &ms) -> nc_status {
+        ctx->launch = ln;
+        hipError_t e = hipMemsetAsync(d_sum, 0, npix * sizeof(double), ctx->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(d_sumsq, 0, npix * sizeof(double), ctx->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "autotune clear");
+        nc_status r = nc_render(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, nullptr);   // warm-up
+        if (r != NC_OK) return r;
+        (void)hipEventRecord(e0, ctx->stream);
+        r = nc_render(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, nullptr);
+        if (r != NC_OK) return r;
+        (void)hipEventRecord(e1, ctx->stream);
+        e = hipEventSynchronize(e1);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "autotune timing");
+    };
+    float best = 0.0f;
+    nc_status st = time_one(cur, best);
+    for (int pass = 0; pass < 4 && st == NC_OK; ++pass) {
+        const int n = pass == 0 ? 5 : pass == 1 ? 3 : pass == 2 ? 2 : 3;
+        for (int k = 0; k < n && st == NC_OK; ++k) {
+            nc_launch cand = cur;
+            if (pass == 0) cand.samples_per_item = spis[k];
+            if (pass == 1) cand.block = blocks[k];
+            if (pass == 2) cand.waves_per_cu = waves[k];
+            if (pass == 3) cand.lds_levels = ldsl[k];
+            if (std::memcmp(&cand, &cur, sizeof(cand)) == 0) continue;
+            float ms = 0.0f;
+            st = time_one(cand, ms);
+            if (st == NC_OK && ms < best) {
+                best = ms;
+                cur = cand;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->launch = cur;
+    if (st != NC_OK) return st;
+    if (best_ms) *best_ms = best;
+    return NC_OK;
 }
 
 static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,

@@ -101,6 +101,38 @@ struct Rng {
     __device__ float take_exp1() { return -__logf(1.0f - take()); }
 };
 
+// The same stream with its counter words supplied by the caller at each
+// refill (the renderer rebuilds them from its pixel, sample and job), so a
+// lane keeps only the draw index and the four buffered words.
+struct RngBuf {
+    uint32_t draw;
+    uint32_t q0, q1, q2, q3;
+    int left;
+
+    __device__ void reset()
+    {
+        draw = 0;
+        left = 0;
+    }
+    __device__ void need(int k, uint32_t a, uint32_t b, uint32_t stream, uint32_t k0, uint32_t k1)
+    {
+        if (left < k) {
+            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            ++draw;
+            q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
+            left = 4;
+        }
+    }
+    __device__ float take()
+    {
+        const uint32_t v = q0;
+        q0 = q1; q1 = q2; q2 = q3;
+        --left;
+        return (float)(v >> 8) * 5.9604644775390625e-08f;
+    }
+    __device__ float take_exp1() { return -__logf(1.0f - take()); }
+};
+
 // ---------------------------------------------------------------------------
 // Grid as seen by the kernels.
 // Nodes of levels 1..L are stored level after level, each level [z][y][x]

@@ -14,6 +14,8 @@ struct nc_ctx {
     std::string err;
     unsigned long long *d_scratch = nullptr;   // work-queue heads and flags (kScratchWords words)
     nc_launch launch{};
+    void *d_jobs = nullptr;        // device job table of batched renders
+    size_t jobs_cap = 0;
     int num_cus = 256;
     size_t lds_per_cu = 160 * 1024;
 };
@@ -50,6 +52,17 @@ struct OptView {
     int max_scatter, max_segments;
 };
 
+// One job of a batched render: a view and its sun (device memory).
+struct JobView {
+    CamView cam;
+    float sun[3];
+    float S, rho;
+    int tiles_x, tiles_y;
+    int pad_;
+    unsigned long long item_begin;   // first queue item of the job (set by the launcher)
+    unsigned long long out_off;      // first output element of the job's image
+};
+
 struct Shape {
     int block;
     int wgs;
@@ -74,6 +87,7 @@ hipError_t launch_flux(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
                        double *glob, const double *grad, double *out, nc_counters *counters);
 hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
-                         const CamView &cam, const nc_sampling &s, double *sum, double *sumsq, nc_counters *counters);
+                         const JobView *jobs, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
+                         nc_counters *counters, JobView *jobs_dev);
 
 }  // namespace nc

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "nc_internal.hpp"
 
@@ -376,17 +377,20 @@ __device__ inline unsigned int lanes_below(unsigned long long mask)
 // device memory and are read with volatile loads when used, so that they do
 // not occupy scalar registers across the whole loop.
 struct RenderRare {
-    CamView cam;
     uint64_t seed, sample_offset;
-    unsigned long long items;
     double *sum, *sumsq;
+    const JobView *jobs;
+    int n_jobs;
     int spp, spi;
-    int tiles_x, tiles_y;
+    uint32_t stream_base;
 };
 
 struct RenderArgs {
     GridView g;
     OptView op;
+    uint32_t key0, key1;        // Philox key (the seed)
+    uint32_t sample_base;       // sample_offset (fits 32 bits)
+    uint32_t stream_base;
     const RenderRare *rare;
     nc_counters *counters;
     unsigned long long *queue;
@@ -460,7 +464,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                      g.n[1]};
     const volatile RenderRare &R = *A.rare;
     const int lane = __lane_id();
-    const float sun[3] = {A.op.sun[0], A.op.sun[1], A.op.sun[2]};
+    int job = 0;                           // the lane's current view x sun
+    float sun[3] = {0.0f, 0.0f, 1.0f};     // that job's sun direction (its irradiance is applied at the flush)
 
     uint32_t reads = 0;        // global grid and field reads of this lane
     int phase = kPhSample;
@@ -474,7 +479,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     float Lp = 0.0f;
     Ray r;                     // at an event, r.o holds the event position (origin of the next ray)
     float tau = 0.0f;
-    Rng rng;
+    RngBuf rng;
+    rng.reset();
     float pd[3] = {0, 0, 0};   // path direction / direction of the next path ray
     float w_nee = 0.0f;        // sun contribution of the current event if its sun ray gets through
     float p_cont = 0.0f;       // probability that the path goes on after the event
@@ -529,7 +535,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             const bool active = phase == kPhCollide;
             bool real = false, gathered = false, trunc = false;
             if (active) {
-                rng.need(2);
+                rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
                 const float thr = rng.take() * r.khat;
                 if (shadow && thr < g.kscale * r.kmin + g.k_gas) {
@@ -564,7 +570,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             wave_count(s_cnt, kCTrunc, trunc);
         } else if (run == kPhEvent) {
             if (phase == kPhEvent) {
-                rng.need(3);
+                rng.need(3, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 bool cont = false;               // go on to the scatter / reflect decision
                 if (shadow) {
                     if (res == kExit) Lp += w_nee;   // the sun ray got through
@@ -580,7 +586,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     const float kd = g.kscale * kc_hit;
                     const float ssa = A.op.ssa * kd / (kd + g.k_gas);
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * hg_phase(A.op.g, mu) * A.op.S;
+                    w_nee = ssa * hg_phase(A.op.g, mu);
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
@@ -600,8 +606,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     r.o[0] = r.o[0] + tg * r.d[0];
                     r.o[1] = r.o[1] + tg * r.d[1];
                     r.o[2] = 0.0f;
-                    w_nee = A.op.ground_w;
-                    p_cont = A.op.rho;
+                    const float rho = R.jobs[job].rho;
+                    w_nee = rho * (1.0f / kPi) * sun[2];
+                    p_cont = rho;
                     ground_ev = true;
                     vc.lev = g.L;
                     vc.i0 = -1;                  // outside the field: no voxel to reuse
@@ -641,7 +648,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const float o[3] = {r.o[0], r.o[1], r.o[2]};
                 const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
                 hit = start_ray_cached_r(g, ns, r, o, rd, vc, A.op.mscale, reads);
-                rng.need(1);
+                rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 tau = rng.take_exp1();
                 phase = voxel_phase(r, tau);
             }
@@ -658,8 +665,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         ++s;
                     }
                     if (s >= s_end) {
-                        unsafeAtomicAdd(R.sum + pix, (double)acc);
-                        unsafeAtomicAdd(R.sumsq + pix, (double)acc2);
+                        const unsigned long long q = R.jobs[job].out_off + (unsigned long long)pix;
+                        const double S = (double)R.jobs[job].S;   // radiances are in units of the sun irradiance
+                        unsafeAtomicAdd(R.sum + q, S * (double)acc);
+                        unsafeAtomicAdd(R.sumsq + q, S * S * (double)acc2);
                         have_item = false;
                         need_item = true;
                     }
@@ -690,11 +699,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     if (w >= A.items) {
                         phase = kPhIdle;
                     } else {
-                        const int tx = R.tiles_x, ty = R.tiles_y, spi = R.spi, spp = R.spp;
-                        const int W = R.cam.W, H = R.cam.H;
+                        // the job holding item w: last job whose first item is <= w
+                        int lo = 0, hi = R.n_jobs - 1;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (R.jobs[mid].item_begin <= w)
+                                lo = mid;
+                            else
+                                hi = mid - 1;
+                        }
+                        job = lo;
+                        const volatile JobView &J = R.jobs[job];
+                        const int tx = J.tiles_x, ty = J.tiles_y, spi = R.spi, spp = R.spp;
+                        const int W = J.cam.W, H = J.cam.H;
+                        const unsigned long long lw = w - J.item_begin;
                         const unsigned long long tile_px = (unsigned long long)tx * ty * 64ull;
-                        const int blk = (int)(w / tile_px);
-                        const int rem = (int)(w - (unsigned long long)blk * tile_px);
+                        const int blk = (int)(lw / tile_px);
+                        const int rem = (int)(lw - (unsigned long long)blk * tile_px);
                         const int tile = rem >> 6, within = rem & 63;
                         const int px = (tile % tx) * 8 + (within & 7);
                         const int py = (tile / tx) * 8 + (within >> 3);
@@ -717,14 +738,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 }
             }
             if (phase == kPhSample && have_item) {
-                const uint64_t seed = R.seed, off = R.sample_offset;
-                rng.init((uint32_t)pix, (uint32_t)(off + (uint64_t)s), 0u, seed);
-                const int W = R.cam.W;
+                rng.reset();
+                const volatile JobView &J = R.jobs[job];
+                const int W = J.cam.W;
                 const int py = pix / W, px = pix - py * W;
-                rng.need(2);
+                rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 const float u1 = rng.take(), u2 = rng.take();
                 float o[3];
-                camera_ray_v(R.cam, px, py, u1, u2, o, pd);
+                camera_ray_v(J.cam, px, py, u1, u2, o, pd);
+                sun[0] = J.sun[0];
+                sun[1] = J.sun[1];
+                sun[2] = J.sun[2];
 #pragma unroll
                 for (int a = 0; a < 3; ++a) r.o[a] = o[a];
                 Lp = 0.0f;
@@ -762,35 +786,50 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n)
     if (i < n) p[i] = 0ull;
 }
 
-hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op, const CamView &cam,
-                         const nc_sampling &s, double *sum, double *sumsq, nc_counters *counters)
+hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
+                         const JobView *jobs_host, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
+                         nc_counters *counters, JobView *jobs_dev)
 {
     Shape sh = choose_shape(ctx, g, 256);
     RenderRare rare;
-    rare.cam = cam;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
     rare.spp = s.spp;
     rare.spi = std::max(1, std::min(sh.spi, s.spp));
-    rare.tiles_x = (cam.W + 7) / 8;
-    rare.tiles_y = (cam.H + 7) / 8;
-    const unsigned long long blocks = (unsigned long long)((s.spp + rare.spi - 1) / rare.spi);
-    rare.items = (unsigned long long)rare.tiles_x * rare.tiles_y * 64ull * blocks;
     rare.sum = sum;
     rare.sumsq = sumsq;
+    rare.jobs = jobs_dev;
+    rare.n_jobs = n_jobs;
+    rare.stream_base = s.stream;
+    const unsigned long long blocks = (unsigned long long)((s.spp + rare.spi - 1) / rare.spi);
+    // queue items of each job: tiles of 8x8 pixels times sample blocks
+    std::vector<JobView> jobs(jobs_host, jobs_host + n_jobs);
+    unsigned long long items = 0;
+    for (int j = 0; j < n_jobs; ++j) {
+        jobs[j].tiles_x = (jobs[j].cam.W + 7) / 8;
+        jobs[j].tiles_y = (jobs[j].cam.H + 7) / 8;
+        jobs[j].item_begin = items;
+        items += (unsigned long long)jobs[j].tiles_x * jobs[j].tiles_y * 64ull * blocks;
+    }
     RenderArgs A;
     A.g = grid_view(g, d_kc);
     A.op = op;
     A.rare = reinterpret_cast<const RenderRare *>(ctx->d_scratch + kScratchRare);
-    A.items = rare.items;
+    A.key0 = (uint32_t)s.seed;
+    A.key1 = (uint32_t)(s.seed >> 32);
+    A.sample_base = (uint32_t)s.sample_offset;
+    A.stream_base = s.stream;
+    A.items = items;
     A.counters = counters;
     A.queue = ctx->d_scratch;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
     static_assert(sizeof(RenderRare) <= (kScratchWords - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
-    hipError_t e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice,
+    hipError_t e = hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
                                   ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_scratch, 1);
     // register budget: waves per SIMD the kernel is compiled for (3..6)
@@ -803,7 +842,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const size_t lds = (size_t)sh.lds_nodes * sizeof(float2);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, fn, sh.block, lds) == hipSuccess && resident > 0)
         sh.wgs = ctx->num_cus * resident;
-    const long long max_wgs = (long long)((rare.items + sh.block - 1) / sh.block);
+    const long long max_wgs = (long long)((items + sh.block - 1) / sh.block);
     const int wgs = (int)std::max<long long>(1, std::min<long long>(max_wgs, sh.wgs));
     void *args[] = {&A};
     return hipLaunchKernel(fn, dim3(wgs), dim3(sh.block), args, lds, ctx->stream);

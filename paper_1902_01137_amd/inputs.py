@@ -89,6 +89,7 @@ class Sampling:
     spp: int = 16
     flags: int = 0
     guide_frac: float = 0.5
+    stream: int = 0
 
 
 @dataclass

@@ -36,7 +36,7 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.GridParams) == 24
     assert C.sizeof(_lib.Optics) == 7 * 8 + 8
     assert C.sizeof(_lib.Camera) == 16 + 12 * 8
-    assert C.sizeof(_lib.Sampling) == 32
+    assert C.sizeof(_lib.Sampling) == 40
     assert C.sizeof(_lib.Launch) == 16
 
 
