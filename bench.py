@@ -61,6 +61,16 @@ def parse():
     p.add_argument("--lds-levels", type=int, default=-1, help="grid levels staged in LDS (-1: auto)")
     p.add_argument("--no-batch", action="store_true", help="skip the 48-view x 4-sun batched launch")
     p.add_argument("--batch-spp", type=int, default=4)
+    p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
+    p.add_argument("--collect-spp", type=int, default=4, help="plain samples per pixel whose vertices train the guide")
+    p.add_argument("--train-steps", type=int, default=1000)
+    p.add_argument("--train-batch", type=int, default=8192)
+    p.add_argument("--lr", type=float, default=3e-3)
+    p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
+    p.add_argument("--no-variants", action="store_true", help="skip the grid variants (flat supercells, tau 0, global)")
+    p.add_argument("--no-refinement", action="store_true", help="skip the refinement sweep (fields 128^2x40..1024^2x320)")
+    p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
+    p.add_argument("--max-spp", type=int, default=16384, help="cap of the progressive runs")
     return p.parse_args()
 
 
@@ -74,9 +84,14 @@ def main():
 
     from paper_1902_01137_amd import api, inputs
 
+    fine = None
     if args.workload == "cumulus":
-        sc = inputs.scene_cumulus()
+        # the 12.5 m field (1024^2 x 320) is generated once; the workload field is its 2x2x2 regional average
+        fine = inputs.cumulus_field(pool=1)
+        sc = inputs.scene_cumulus(field=inputs.pool_field(*fine, 2))
         name = "cumulus_512x512x160_25m_view1024x1024"
+        if args.no_refinement:
+            fine = None
     else:
         sc = inputs.scene_small()
         name = "blob_32x32x32_100m_nadir64x64"
@@ -155,15 +170,187 @@ def main():
                   "ticks_per_trip": {k: round(c["ticks_" + k] / max(c["trips_" + k], 1), 1) for k in PHASES}},
         "rel_std_err": eps,
         "time_to_1pct_s": {"plain": t_1pct, "guided": None},
+        "time_to_1pct_definition": "RMS over pixels of the per-pixel standard error, relative to the mean radiance; "
+                                   "step time x (err / 0.01)^2, plus the guide's collection and training time",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
                      "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None},
     }
+    gd = None
+    if not args.no_guided:
+        out["guided"], gd = guided_run(ctx, sc, kc, spp, args, build_ms=ms_step - render_ms)
+        out["time_to_1pct_s"]["guided"] = out["guided"]["time_to_1pct_s"]
+    out["gather_ceiling"] = gather_ceiling(ctx)
+    out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
+    if not args.no_progressive:
+        out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
+    if args.workload == "cumulus" and not args.no_variants:
+        out["grid_variants"] = grid_variants(ctx, sc, kc, spp)
+    if fine is not None:
+        out["refinement"] = refinement_sweep(ctx, sc, fine)
+        del fine
     if args.workload == "cumulus" and not args.no_batch:
         out["batch"] = batch_run(ctx, sc, kc, args.batch_spp)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
     print(json.dumps(out))
+
+
+def gather_ceiling(ctx):
+    """Measured random 4-byte read rate over a 2 GiB buffer (larger than the 256 MB last-level cache)."""
+    import torch
+
+    from paper_1902_01137_amd import api
+    buf = torch.rand(1 << 29, device="cuda")
+    rate = api.gather_rate(ctx, buf, threads=1 << 20, loads=64)
+    del buf
+    torch.cuda.empty_cache()
+    return {"loads_per_s": rate, "GB_per_s_at_64B": rate * GRANULE / 1e9, "buffer_bytes": 1 << 31}
+
+
+def progressive_run(ctx, sc, kc, gd, args):
+    """Rounds of samples until the 8x8-block relative standard error is 1 % (plain, then guided)."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    out = {}
+    for name, guide in (("plain", None), ("guided", gd)):
+        if name == "guided" and guide is None:
+            continue
+        smp = inputs.Sampling(seed=sc.sampling.seed + 31, spp=0, guide_frac=args.guide_frac)
+        _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, 0.01, first_spp=16,
+                                           max_spp=args.max_spp, block=8, guide=guide)
+        torch.cuda.synchronize()
+        out[name] = rep
+    return out
+
+
+def grid_variants(ctx, sc, kc, spp):
+    """The same render over other majorant grids: the flat grid of 8^3-cell
+    supercells, tau_tilde = 0 (every cell a voxel) and one global voxel."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    cam = sc.camera
+    res = {}
+    for name, gp in (("hier_tau1", sc.grid),
+                     ("flat_8cube", inputs.GridParams(0.0, sc.grid.k_gas, 2, 3)),
+                     ("tau0", inputs.GridParams(0.0, sc.grid.k_gas, 0)),
+                     ("global", inputs.GridParams(math.inf, sc.grid.k_gas, 0))):
+        g = api.build_grid(ctx, kc, sc.desc, gp)
+        cnt = api.new_counters("cuda")
+        smp = inputs.Sampling(seed=sc.sampling.seed + 41, spp=spp)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp, counters=cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        c = api.counters_dict(cnt)
+        paths = cam.width * cam.height * spp
+        res[name] = {"render_ms": ms, "paths_per_s": paths / (ms / 1e3), "mean_radiance": float(s.sum()) / paths,
+                     "per_path": {k: c[k] / paths for k in ("segments", "tentative", "nulls", "leaf_visits",
+                                                            "gathers", "node_reads")}}
+        del g
+    return res
+
+
+def refinement_sweep(ctx, sc, fine):
+    """Grid build time and render rate against the voxel count: the 12.5 m
+    field and its 2, 4 and 8 regional averages, tau_tilde = 1 and 0; the
+    workload's camera at 512^2, 32 spp."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    out = []
+    cam = inputs.Camera(**{**vars(sc.camera), "width": 512, "height": 512})
+    spp = 32
+    for f in (8, 4, 2, 1):
+        desc, k = inputs.pool_field(*fine, f) if f > 1 else fine
+        kc = torch.from_numpy(k).cuda()
+        row = {"field": [desc.nx, desc.ny, desc.nz], "cell_km": desc.dx, "voxels": desc.nx * desc.ny * desc.nz}
+        for tau in (1.0, 0.0):
+            gp = inputs.GridParams(tau, sc.grid.k_gas, 0)
+            api.build_grid(ctx, kc, desc, gp)                     # warm-up
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            reps = 5
+            for _ in range(reps):
+                g = api.build_grid(ctx, kc, desc, gp)
+            torch.cuda.synchronize()
+            build_ms = (time.perf_counter() - t0) * 1e3 / reps
+            smp = inputs.Sampling(seed=sc.sampling.seed + 51, spp=spp)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            api.render(ctx, g, kc, sc.optics, cam, smp)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            row["tau%g" % tau] = {"build_ms": build_ms, "render_ms": ms, "paths_per_s": 512 * 512 * spp / (ms / 1e3)}
+            del g
+        out.append(row)
+        del kc
+        torch.cuda.empty_cache()
+    return out
+
+
+def rel_err(s, s2, spp):
+    sm = s.cpu().numpy().ravel() / spp
+    var = np.maximum(s2.cpu().numpy().ravel() / spp - sm ** 2, 0) * spp / (spp - 1)
+    return float(np.sqrt(np.mean(var / spp)) / np.mean(sm))
+
+
+def guided_run(ctx, sc, kc, spp, args, build_ms):
+    """The guided leg: record the scattering vertices of a short plain render,
+    fit the guide to them (Adam on random minibatches), then render the same
+    view guided at the same spp.  Time to 1% = collection + training + one
+    guided step (grid build + render) scaled by (err / 0.01)^2."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    cam = sc.camera
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    cap = cam.width * cam.height * args.collect_spp * 16
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rec, n, _, _ = api.collect_vertices(ctx, g, kc, sc.optics, cam,
+                                        inputs.Sampling(seed=sc.sampling.seed + 101, spp=args.collect_spp), cap)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gd = api.Guide(ctx, seed=1)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    losses = []
+    for it in range(args.train_steps):
+        idx = torch.randint(0, rec.shape[0], (args.train_batch,), device="cuda", generator=gen)
+        lr = args.lr * (0.2 if it >= 0.75 * args.train_steps else 1.0)
+        l = gd.train_step(rec[idx], lr)
+        if it % max(1, args.train_steps // 4) == 0 or it == args.train_steps - 1:
+            losses.append(l)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, guide_frac=args.guide_frac)
+    api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)         # warm-up
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    s, s2 = api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)
+    e1.record()
+    torch.cuda.synchronize()
+    render_ms = e0.elapsed_time(e1)
+    eps = rel_err(s, s2, spp)
+    step_ms = build_ms + render_ms
+    collect_s, train_s = t1 - t0, t2 - t1
+    paths = cam.width * cam.height * spp
+    return {"collect_spp": args.collect_spp, "records": n, "collect_s": collect_s, "train_steps": args.train_steps,
+            "train_batch": args.train_batch, "train_s": train_s,
+            "loss": [round((x[0] / x[1]).item(), 4) for x in losses], "guide_frac": args.guide_frac,
+            "render_ms": render_ms, "paths_per_s": paths / (step_ms / 1e3), "rel_std_err": eps,
+            "time_to_1pct_s": collect_s + train_s + step_ms / 1e3 * (eps / 0.01) ** 2}, gd
 
 
 def batch_run(ctx, sc, kc, spp):

@@ -64,12 +64,15 @@ typedef struct {
  * the grid when its optical-depth criterion, evaluated in double precision, is
  *   criterion 0: (kmax_c + k_gas) * dz * 2^l < tau_tilde    (default)
  *   criterion 1: (kmax_c - kmin_c) * dz * 2^l < tau_tilde
+ *   criterion 2: l <= flat_level, whatever the field: the flat, single-level
+ *                majorant grid of 2^flat_level-cell supercells that the
+ *                hierarchy is compared with (Sections 2.4, 3); tau_tilde unused
  * tau_tilde = 0 keeps the raw resolution; tau_tilde = +inf gives one voxel. */
 typedef struct {
     double tau_tilde;
     double k_gas;
     int32_t criterion;
-    int32_t pad_;
+    int32_t flat_level;     /* criterion 2 only, 0..NC_MAX_LEVELS */
 } nc_grid_params;
 
 /* Medium, ground and sun.  ssa is the droplets' single-scattering albedo
@@ -93,7 +96,17 @@ typedef struct {
  * fov_y_deg, type 1 orthographic of extent ortho_w x ortho_h; forward =
  * target - pos, right = forward x up, row 0 is the top of the image, pixel
  * (i, j) is index j*width + i; directions are sampled uniformly over the
- * pixel's footprint on the image plane. */
+ * pixel's footprint on the image plane.
+ * Type 2 is a horizontal irradiance sensor (the ground pixels of the
+ * flux estimate, Section 5.1, traced backwards): an ortho_w x ortho_h
+ * rectangle centred at pos in the plane z = pos[2], pixel (i, j) with i
+ * along +x and j along +y (as nc_flux's ground pixels); target and up are
+ * ignored.  A sensor path adds the sun's direct transmissivity to a uniform
+ * point of the pixel and pi / cos(theta_sun) times the radiance of a path
+ * leaving it in a cosine-distributed upward direction, so its expectation is
+ * the downward irradiance over sun_irradiance * cos(theta_sun) (the
+ * transmissivity) times sun_irradiance.  It needs the sun above the horizon
+ * (NC_ERR_RANGE otherwise). */
 typedef struct {
     int32_t type;
     int32_t width, height;
@@ -146,7 +159,7 @@ void nc_ctx_destroy(nc_ctx *ctx);
  * nc_ctx_create when ctx is NULL).  Valid until the next call. */
 const char *nc_last_error(const nc_ctx *ctx);
 
-/* Build the acceleration grid over d_kc (Section 3.1.1; Appendix C's
+/* Build the acceleration grid over d_kc (Section 3.1.1; Appendix B.3's
  * power-of-two octree, with nodes wholly outside the field left out).
  * Level 0 is the field itself; level l (1..L, L = ceil(log2 max(nx,ny,nz)))
  * has ceil(n/2^l) nodes per axis, each holding the min and max of k_c over
@@ -239,6 +252,109 @@ nc_status nc_flux(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_
 nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                           double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,
                           const nc_sampling *sampling, const double *d_grad, double *d_out);
+
+/* ---------------------------------------------------------------------------
+ * Learned proposal for scattering directions (path guiding).  An MLP
+ * 7 -> 64 -> 64 -> 64 -> 40 (ReLU) maps a scattering vertex to a mixture of
+ * 8 von Mises-Fisher lobes over the outgoing direction; its inputs are the
+ * position normalised to [-1, 1]^3 over the field's box, the incoming
+ * direction, and ln(1 + k / 1 km^-1) at the vertex.  Output j*5 + {0,1,2,3,4}:
+ * lobe logit, unnormalised mean direction (3), log concentration (clamped to
+ * [-3, 8]).  Products run in bf16 on the matrix cores with fp32
+ * accumulation; master weights and Adam moments are fp32.  Parameters are
+ * flat fp32, layer by layer: W [out][in] row-major, then b [out] (11432).
+ * A training record is 12 floats: inputs (7), outgoing direction (3),
+ * weight (1), unused (1); the loss is -sum w ln q(w_out) / sum w.
+ * ------------------------------------------------------------------------- */
+typedef struct nc_guide nc_guide;
+#define NC_GUIDE_PARAMS 11432
+#define NC_GUIDE_RECORD 12
+
+/* New network with He-uniform weights from `seed` and zero biases. */
+nc_status nc_guide_create(nc_ctx *ctx, uint64_t seed, nc_guide **out);
+void nc_guide_destroy(nc_guide *guide);
+/* Copy the fp32 parameters to / from a device buffer of NC_GUIDE_PARAMS floats. */
+nc_status nc_guide_get_params(nc_ctx *ctx, const nc_guide *guide, float *d_params);
+nc_status nc_guide_set_params(nc_ctx *ctx, nc_guide *guide, const float *d_params);
+/* Raw network outputs for n inputs (rows of `stride` floats, inputs first):
+ * d_out is n x 48 floats (the 40 outputs, then padding). */
+nc_status nc_guide_forward(nc_ctx *ctx, const nc_guide *guide, const float *d_in, int32_t n, int32_t stride,
+                           float *d_out);
+/* One Adam step (lr) on the loss of n records; d_loss (may be NULL) receives
+ * [sum of -w ln q, sum of w] as float64. */
+nc_status nc_guide_train_step(nc_ctx *ctx, nc_guide *guide, const float *d_records, int32_t n, float lr,
+                              double *d_loss);
+/* Gradient of the loss of n records (NC_GUIDE_PARAMS floats), no update. */
+nc_status nc_guide_gradient(nc_ctx *ctx, nc_guide *guide, const float *d_records, int32_t n, float *d_grad,
+                            double *d_loss);
+
+/* Guided radiance image: nc_render, except that at a volume scattering
+ * event the new direction is drawn with probability c =
+ * sampling->guide_frac from the guide's vMF mixture q and otherwise from the
+ * HG phase function p, and the path weight is multiplied by
+ * p / (c q + (1 - c) p) (one-sample multiple importance sampling with the
+ * balance heuristic, Veach 1997).  The estimate is unbiased for any network;
+ * its variance depends on how closely q follows the light arriving at the
+ * vertex.  Ground reflections keep the cosine law.  The network runs inside
+ * the tracer (bf16 matrix cores, 16 vertices per product tile).  guide_frac
+ * outside [0, 1] is NC_ERR_INVALID_ARG. */
+nc_status nc_render_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                           const nc_camera *camera, const nc_sampling *sampling, const nc_guide *guide,
+                           double *d_sum, double *d_sumsq, nc_counters *d_counters);
+
+/* Progressive rendering to a target relative standard error.  Rounds of
+ * nc_render (guide NULL) or nc_render_guided add samples with consecutive
+ * sample offsets (the union of the rounds is one render of spp_done samples)
+ * until eps <= target_rel_err or max_spp samples per pixel are done.
+ * eps = sqrt(mean over units of SE_u^2) / mean over units of L_u, where a
+ * unit is a block x block pixel block (block = 1: one pixel), L_u the block's
+ * mean radiance and SE_u its standard error.  Each round after the first asks
+ * for the samples the 1/sqrt(n) law predicts are missing (+5 %), at most
+ * doubling the total.  The stream is synchronised after every round (the
+ * error is read back).  d_sum/d_sumsq must start at zero. */
+typedef struct {
+    double target_rel_err;  /* e.g. 0.01 */
+    int32_t first_spp;      /* samples per pixel of the first round (>= 2) */
+    int32_t max_spp;        /* cap on the total */
+    int32_t block;          /* pixel block side of the error estimate (>= 1) */
+    int32_t pad_;
+} nc_progressive;
+typedef struct {
+    int32_t spp_done;       /* samples per pixel taken */
+    int32_t rounds;
+    double rel_err;         /* eps after the last round */
+    double mean;            /* mean radiance over the units */
+    double seconds;         /* host wall time of all rounds */
+} nc_progress_report;
+nc_status nc_render_progressive(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                                const nc_camera *camera, const nc_sampling *sampling, const nc_guide *guide,
+                                const nc_progressive *plan, double *d_sum, double *d_sumsq, nc_counters *d_counters,
+                                nc_progress_report *report);
+
+/* Device random-read rate (not part of the method: the measured ceiling
+ * of the tracers' roofline).  threads x loads independent 4-byte reads at
+ * hashed addresses in d_buf[0 .. n_words) (n_words a power of two <= 2^32,
+ * device float array; pick it larger than the last-level cache to measure
+ * HBM); d_out receives one float per thread.  The second of two launches is
+ * timed on the ctx stream (synchronised); *loads_per_s = reads per second. */
+nc_status nc_gather_rate(nc_ctx *ctx, const float *d_buf, uint64_t n_words, int32_t threads, int32_t loads,
+                         float *d_out, double *loads_per_s);
+
+/* Training vertices for the guide: renders exactly as nc_render (same paths,
+ * same d_sum/d_sumsq) and, at every volume scattering event after which the
+ * path goes on, writes one NC_GUIDE_RECORD: the guide inputs at the vertex
+ * (7), the sampled outgoing direction (3), as weight the radiance the path
+ * gathered after the vertex (its final radiance minus what it held once the
+ * vertex's own sun estimate was added), and in [11] the path's slot
+ * (pixel * spp + sample) as uint32 bits.  d_records: device, capacity x 12
+ * floats; *d_count (device uint64, overwritten) receives the number of
+ * events, which may exceed capacity (the records past capacity are dropped,
+ * in no defined order).  d_path_L: device scratch of width * height * spp
+ * floats (per-path radiance), width * height * spp < 2^32. */
+nc_status nc_collect_vertices(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
+                              const nc_camera *camera, const nc_sampling *sampling, float *d_records,
+                              uint64_t capacity, unsigned long long *d_count, float *d_path_L, double *d_sum,
+                              double *d_sumsq, nc_counters *d_counters);
 
 /* Counter-based random numbers (Salmon et al., SC'11): out[i] =
  * Philox4x32-10(counter = d_ctr[4i..4i+3], key = d_key[2i..2i+1]) for i < n.

@@ -61,7 +61,7 @@ def lib():
             build(force=True)
         L = C.CDLL(_LIB_PATH)
         L.orc_philox4x32_10.argtypes = [_P, _P, _P]
-        L.orc_grid_build.argtypes = [C.POINTER(Field), C.c_double, C.c_int]
+        L.orc_grid_build.argtypes = [C.POINTER(Field), C.c_double, C.c_int, C.c_int]
         L.orc_grid_build.restype = _P
         L.orc_grid_free.argtypes = [_P]
         L.orc_grid_levels.argtypes = [_P]
@@ -138,9 +138,9 @@ def philox4x32_10(ctr, key):
 class OracleGrid:
     """Per-level (kmin_c, kmax_c, merged) arrays and the per-cell leaf-level map."""
 
-    def __init__(self, desc, kc, tau_tilde=1.0, k_gas=0.0, criterion=0):
+    def __init__(self, desc, kc, tau_tilde=1.0, k_gas=0.0, criterion=0, flat_level=3):
         self.field = make_field(desc, kc, k_gas)
-        self.handle = lib().orc_grid_build(C.byref(self.field), float(tau_tilde), int(criterion))
+        self.handle = lib().orc_grid_build(C.byref(self.field), float(tau_tilde), int(criterion), int(flat_level))
         if not self.handle:
             raise MemoryError("oracle grid build failed")
         self.L = lib().orc_grid_levels(self.handle)

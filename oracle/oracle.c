@@ -137,7 +137,7 @@ static double cell_kd(const orc_field *f, int i, int j, int m)
 
 /* ========================================================================
  * Grid build (Section 3.1.1 "Construction"; Section 4.2 merge criterion;
- * Appendix C power-of-two intermediate grid).
+ * Appendix B.3 power-of-two intermediate grid).
  *
  * Level 0 is the cell field.  A level-l node (i,j,m) covers the cells
  * [i 2^l, min((i+1) 2^l, n)) along each axis, which is the node indexing of
@@ -147,6 +147,9 @@ static double cell_kd(const orc_field *f, int i, int j, int m)
  * optical-depth criterion holds:
  *   criterion 0: (kmax_c + k_g) * dz 2^l  <  tau_tilde
  *   criterion 1: (kmax_c - kmin_c) * dz 2^l < tau_tilde
+ *   criterion 2: l <= flat_level (no test on the field: a flat grid of
+ *                supercells of 2^flat_level cells, the single-level majorant
+ *                grid the paper sets against its hierarchy, Sections 2.4 and 3)
  * evaluated in double precision.  Both are monotone (a merged node has merged
  * children), so the bottom-up merging of groups of 2^3 children gives the
  * same voxels as taking, for each cell, its coarsest ancestor that passes the
@@ -176,7 +179,7 @@ void orc_grid_free(orc_grid *g)
     free(g);
 }
 
-orc_grid *orc_grid_build(const orc_field *f, double tau_tilde, int criterion)
+orc_grid *orc_grid_build(const orc_field *f, double tau_tilde, int criterion, int flat_level)
 {
     orc_grid *g = (orc_grid *)calloc(1, sizeof(orc_grid));
     int nmax, l;
@@ -217,6 +220,10 @@ orc_grid *orc_grid_build(const orc_field *f, double tau_tilde, int criterion)
                     g->kmin[l][id] = (float)lo;  /* exact: values are floats */
                     g->kmax[l][id] = (float)hi;
                     dz_node = f->dz * (double)(1 << l);
+                    if (criterion == 2) {
+                        g->merged[l][id] = (unsigned char)(l <= flat_level);
+                        continue;
+                    }
                     if (criterion == 0) {
                         volatile double s = hi + f->k_gas;
                         crit = s * dz_node;
@@ -781,6 +788,13 @@ static void camera_ray(const orc_camera *c, int px, int py, double u1, double u2
         double sy = (1.0 - 2.0 * (py + u2) / c->height) * th;
         for (a = 0; a < 3; ++a) { o[a] = c->pos[a]; d[a] = f[a] + sx * r[a] + sy * u[a]; }
         normalize3(d);
+    } else if (c->type == 2) {
+        /* horizontal sensor: pixel (px, py) of an ortho_w x ortho_h rectangle
+         * centred at pos, px along +x, py along +y; looks up */
+        o[0] = c->pos[0] + ((px + u1) / c->width - 0.5) * c->ortho_w;
+        o[1] = c->pos[1] + ((py + u2) / c->height - 0.5) * c->ortho_h;
+        o[2] = c->pos[2];
+        d[0] = 0.0; d[1] = 0.0; d[2] = 1.0;
     } else {
         double sx = ((px + u1) / c->width - 0.5) * c->ortho_w;
         double sy = (0.5 - (py + u2) / c->height) * c->ortho_h;
@@ -811,6 +825,13 @@ void orc_camera_ray(const orc_camera *c, int px, int py, double u1, double u2, d
  * transmissivity exactly as exp(-tau); both have the same expectation as the
  * null-collision estimators they check.  Contributions whose sun
  * transmissivity is below exp(-200) are dropped.
+ *
+ * A camera of type 2 is a horizontal sensor of the downward irradiance E
+ * at its plane, reported as S times the transmissivity E / (S mu_sun): per
+ * path, S times the sun's direct transmissivity to the point, plus
+ * pi / mu_sun times the radiance of a path started from the point in a
+ * cosine-distributed upward direction (the cosine density is mu / pi, so
+ * pi L estimates the diffuse irradiance).
  *
  * Per pixel: sum and sum of squares of the per-path radiance (units of S,
  * per steradian), over `spp` paths.  `pixels` lists the pixel indices
@@ -892,7 +913,18 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
                 double u1 = rng_u01(&r), u2 = rng_u01(&r);
                 camera_ray(cam, px, py, u1, u2, o, d);
             }
-            L = radiance_path(f, op, s, o, d, &r, counters);
+            if (cam->type == 2) {
+                L = s[2] > 0.0 ? op->S * sun_transmissivity(f, o, s) : 0.0;
+                if (op->max_scatter != 0 && s[2] > 0.0) {
+                    double v1 = rng_u01(&r), v2 = rng_u01(&r), rr = sqrt(v1), phi = 2.0 * ORC_PI * v2;
+                    d[0] = rr * cos(phi);
+                    d[1] = rr * sin(phi);
+                    d[2] = sqrt(fmax(0.0, 1.0 - v1));
+                    L += ORC_PI / s[2] * radiance_path(f, op, s, o, d, &r, counters);
+                }
+            } else {
+                L = radiance_path(f, op, s, o, d, &r, counters);
+            }
             if (counters) counters[2]++;
             acc += L;
             acc2 += L * L;

@@ -31,7 +31,7 @@ class FieldDesc(C.Structure):
 
 
 class GridParams(C.Structure):
-    _fields_ = [("tau_tilde", C.c_double), ("k_gas", C.c_double), ("criterion", C.c_int32), ("pad_", C.c_int32)]
+    _fields_ = [("tau_tilde", C.c_double), ("k_gas", C.c_double), ("criterion", C.c_int32), ("flat_level", C.c_int32)]
 
 
 class Optics(C.Structure):
@@ -60,6 +60,18 @@ COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visit
                  "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
                                               for b in ("cross", "collide", "event", "ray", "sample")] + ["sched_pad"]
 N_COUNTER_WORDS = 26
+GUIDE_PARAMS = 11432
+GUIDE_RECORD = 12
+
+class Progressive(C.Structure):
+    _fields_ = [("target_rel_err", C.c_double), ("first_spp", C.c_int32), ("max_spp", C.c_int32),
+                ("block", C.c_int32), ("pad_", C.c_int32)]
+
+
+class ProgressReport(C.Structure):
+    _fields_ = [("spp_done", C.c_int32), ("rounds", C.c_int32), ("rel_err", C.c_double), ("mean", C.c_double),
+                ("seconds", C.c_double)]
+
 
 # (name, restype, argtypes)
 _P = C.c_void_p
@@ -79,10 +91,24 @@ _SIGS = [
     ("nc_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P, _P]),
     ("nc_set_launch", C.c_int32, [_P, C.POINTER(Launch)]),
     ("nc_get_launch", C.c_int32, [_P, C.POINTER(Launch)]),
+    ("nc_render_guided", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
+                                     _P, _P]),
+    ("nc_render_progressive", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P,
+                                          C.POINTER(Progressive), _P, _P, _P, C.POINTER(ProgressReport)]),
+    ("nc_gather_rate", C.c_int32, [_P, _P, C.c_uint64, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double)]),
+    ("nc_collect_vertices", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P,
+                                        C.c_uint64, _P, _P, _P, _P, _P]),
     ("nc_render_batch", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_autotune_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
                                        C.POINTER(C.c_double)]),
     ("nc_philox4x32_10", C.c_int32, [_P, _P, _P, _P, C.c_int32]),
+    ("nc_guide_create", C.c_int32, [_P, C.c_uint64, C.POINTER(_P)]),
+    ("nc_guide_destroy", None, [_P]),
+    ("nc_guide_get_params", C.c_int32, [_P, _P, _P]),
+    ("nc_guide_set_params", C.c_int32, [_P, _P, _P]),
+    ("nc_guide_forward", C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P]),
+    ("nc_guide_train_step", C.c_int32, [_P, _P, _P, C.c_int32, C.c_float, _P]),
+    ("nc_guide_gradient", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P]),
     ("nc_flux", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.c_double, C.c_int32, C.c_int32, C.c_uint64,
                             C.POINTER(Sampling), _P, _P, _P]),
     ("nc_flux_adjoint", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.c_double, C.c_int32, C.c_int32, C.c_uint64,

@@ -103,7 +103,7 @@ class Grid:
         self.ctx, self.desc, self.params = ctx, desc, params
         h = C.c_void_p()
         d = _desc(desc)
-        p = _lib.GridParams(params.tau_tilde, params.k_gas, params.criterion, 0)
+        p = _lib.GridParams(params.tau_tilde, params.k_gas, params.criterion, params.flat_level)
         _check(_lib.load().nc_grid_build(ctx.handle, _ptr(kc), C.byref(d), C.byref(p), C.byref(h)), ctx.handle)
         self.handle = h
         lv = C.c_int32()
@@ -188,6 +188,73 @@ def render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: C
     _check(_lib.load().nc_render(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
                                  _ptr(out_sum), _ptr(out_sumsq), _ptr(counters)), ctx.handle)
     return out_sum, out_sumsq
+
+
+def render_guided(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: Camera, sampling: Sampling,
+                  guide: "Guide", out_sum: torch.Tensor | None = None, out_sumsq: torch.Tensor | None = None,
+                  counters: torch.Tensor | None = None):
+    """Guided radiance image (nc_render_guided): one-sample MIS between the
+    guide's vMF mixture (probability sampling.guide_frac) and HG."""
+    dev = kc.device
+    if out_sum is None:
+        out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    if out_sumsq is None:
+        out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    o = _optics(optics)
+    c = _camera(camera)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_render_guided(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
+                                        guide.handle, _ptr(out_sum), _ptr(out_sumsq), _ptr(counters)), ctx.handle)
+    return out_sum, out_sumsq
+
+
+def render_progressive(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: Camera,
+                       sampling: Sampling, target_rel_err: float = 0.01, first_spp: int = 16, max_spp: int = 1 << 20,
+                       block: int = 1, guide: "Guide | None" = None, counters: torch.Tensor | None = None):
+    """Render in rounds until the image's relative standard error reaches the
+    target (nc_render_progressive).  Returns (sum, sumsq, report dict)."""
+    dev = kc.device
+    out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    plan = _lib.Progressive(float(target_rel_err), int(first_spp), int(max_spp), int(block), 0)
+    rep = _lib.ProgressReport()
+    o = _optics(optics)
+    c = _camera(camera)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_render_progressive(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
+                                             guide.handle if guide is not None else None, C.byref(plan),
+                                             _ptr(out_sum), _ptr(out_sumsq), _ptr(counters), C.byref(rep)),
+           ctx.handle)
+    return out_sum, out_sumsq, {k: getattr(rep, k) for k in ("spp_done", "rounds", "rel_err", "mean", "seconds")}
+
+
+def gather_rate(ctx: Context, buf: torch.Tensor, threads: int = 1 << 20, loads: int = 64) -> float:
+    """Random 4-byte reads per second over buf (float32, power-of-two length): nc_gather_rate."""
+    out = torch.empty(threads, dtype=torch.float32, device=buf.device)
+    r = C.c_double()
+    _check(_lib.load().nc_gather_rate(ctx.handle, _ptr(buf), buf.numel(), int(threads), int(loads), _ptr(out),
+                                      C.byref(r)), ctx.handle)
+    return r.value
+
+
+def collect_vertices(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: Camera,
+                     sampling: Sampling, capacity: int, counters: torch.Tensor | None = None):
+    """Training vertices (nc_collect_vertices).  Returns (records (m, 12) with
+    m = min(events, capacity), number of events, sum image, sum-of-squares image)."""
+    dev = kc.device
+    records = torch.empty((max(int(capacity), 1), _lib.GUIDE_RECORD), dtype=torch.float32, device=dev)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    path_L = torch.empty(max(camera.width * camera.height * sampling.spp, 1), dtype=torch.float32, device=dev)
+    out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
+    o = _optics(optics)
+    c = _camera(camera)
+    sm = _sampling(sampling)
+    _check(_lib.load().nc_collect_vertices(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
+                                           _ptr(records), int(capacity), _ptr(count), _ptr(path_L), _ptr(out_sum),
+                                           _ptr(out_sumsq), _ptr(counters)), ctx.handle)
+    n = int(count.item())
+    return records[:min(n, int(capacity))], n, out_sum, out_sumsq
 
 
 def philox4x32_10(ctx: Context, ctr: torch.Tensor, key: torch.Tensor) -> torch.Tensor:
@@ -284,3 +351,59 @@ def autotune_render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, 
                                           C.byref(_camera(camera)), C.byref(_sampling(sampling)), _ptr(s), _ptr(s2),
                                           C.byref(best)), ctx.handle)
     return ctx.get_launch(), best.value
+
+
+class Guide:
+    """The learned proposal's network (nc_guide_*): bf16 MFMA forward/backward, fp32 Adam."""
+
+    def __init__(self, ctx: Context, seed: int = 1):
+        self.ctx = ctx
+        h = C.c_void_p()
+        _check(_lib.load().nc_guide_create(ctx.handle, int(seed), C.byref(h)), ctx.handle)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().nc_guide_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> torch.Tensor:
+        p = torch.empty(_lib.GUIDE_PARAMS, dtype=torch.float32, device=torch.device("cuda", self.ctx.device))
+        _check(_lib.load().nc_guide_get_params(self.ctx.handle, self.handle, _ptr(p)), self.ctx.handle)
+        return p
+
+    def set_params(self, p: torch.Tensor):
+        p = p.to(dtype=torch.float32, device=torch.device("cuda", self.ctx.device)).contiguous()
+        assert p.numel() == _lib.GUIDE_PARAMS
+        _check(_lib.load().nc_guide_set_params(self.ctx.handle, self.handle, _ptr(p)), self.ctx.handle)
+
+    def forward(self, x: torch.Tensor) -> torch.Tensor:
+        """x: (n, stride >= 7) float32 -> raw outputs (n, 40)."""
+        x = x.contiguous()
+        n, stride = x.shape
+        out = torch.empty((n, 48), dtype=torch.float32, device=x.device)
+        _check(_lib.load().nc_guide_forward(self.ctx.handle, self.handle, _ptr(x), n, stride, _ptr(out)),
+               self.ctx.handle)
+        return out[:, :40]
+
+    def train_step(self, records: torch.Tensor, lr: float):
+        """records: (n, 12) float32.  Returns a (2,) float64 tensor [sum -w ln q, sum w] (not synchronised)."""
+        r = records.contiguous()
+        loss = torch.zeros(2, dtype=torch.float64, device=r.device)
+        _check(_lib.load().nc_guide_train_step(self.ctx.handle, self.handle, _ptr(r), r.shape[0], float(lr),
+                                               _ptr(loss)), self.ctx.handle)
+        return loss
+
+    def gradient(self, records: torch.Tensor):
+        r = records.contiguous()
+        g = torch.empty(_lib.GUIDE_PARAMS, dtype=torch.float32, device=r.device)
+        loss = torch.zeros(2, dtype=torch.float64, device=r.device)
+        _check(_lib.load().nc_guide_gradient(self.ctx.handle, self.handle, _ptr(r), r.shape[0], _ptr(g), _ptr(loss)),
+               self.ctx.handle)
+        return g, loss

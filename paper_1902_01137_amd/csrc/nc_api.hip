@@ -2,6 +2,8 @@
 // and the estimator entry points.  See include/nctrace.h for the contract.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -108,9 +110,25 @@ void cross3(const double a[3], const double b[3], double c[3])
 nc_status make_cam(nc_ctx *ctx, const nc_camera *c, nc::CamView &v)
 {
     if (!c) return fail(ctx, NC_ERR_INVALID_ARG, "camera is NULL");
-    if (c->type != 0 && c->type != 1) return fail(ctx, NC_ERR_INVALID_ARG, "camera type must be 0 or 1");
+    if (c->type < 0 || c->type > 2) return fail(ctx, NC_ERR_INVALID_ARG, "camera type must be 0, 1 or 2");
     if (c->width < 1 || c->height < 1 || (long long)c->width * c->height > (1ll << 30))
         return fail(ctx, NC_ERR_INVALID_ARG, "bad image size");
+    if (c->type == 2) {
+        // horizontal sensor: only the position and the rectangle matter
+        if (!(c->ortho_w > 0.0 && c->ortho_h > 0.0)) return fail(ctx, NC_ERR_RANGE, "sensor extent must be > 0");
+        v.type = 2;
+        v.W = c->width;
+        v.H = c->height;
+        for (int a = 0; a < 3; ++a) {
+            v.pos[a] = (float)c->pos[a];
+            v.f[a] = a == 2 ? 1.0f : 0.0f;
+            v.r[a] = a == 0 ? 1.0f : 0.0f;
+            v.u[a] = a == 1 ? 1.0f : 0.0f;
+        }
+        v.sx = (float)c->ortho_w;
+        v.sy = (float)c->ortho_h;
+        return NC_OK;
+    }
     double f[3], r[3], u[3];
     for (int a = 0; a < 3; ++a) f[a] = c->target[a] - c->pos[a];
     const double fn = std::sqrt(f[0] * f[0] + f[1] * f[1] + f[2] * f[2]);
@@ -271,8 +289,10 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
     if (!(params->tau_tilde >= 0.0)) return fail(ctx, NC_ERR_RANGE, "tau_tilde must be >= 0");
     if (!(params->k_gas >= 0.0) || !std::isfinite(params->k_gas))
         return fail(ctx, NC_ERR_RANGE, "k_gas must be finite and >= 0");
-    if (params->criterion != 0 && params->criterion != 1)
-        return fail(ctx, NC_ERR_INVALID_ARG, "criterion must be 0 or 1");
+    if (params->criterion < 0 || params->criterion > 2)
+        return fail(ctx, NC_ERR_INVALID_ARG, "criterion must be 0, 1 or 2");
+    if (params->criterion == 2 && (params->flat_level < 0 || params->flat_level > NC_MAX_LEVELS))
+        return fail(ctx, NC_ERR_INVALID_ARG, "flat_level must lie in [0, NC_MAX_LEVELS]");
     DeviceGuard guard(ctx->device);
     nc_grid *g = new (std::nothrow) nc_grid();
     if (!g) return fail(ctx, NC_ERR_OOM, "host allocation failed");
@@ -421,8 +441,9 @@ nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *g, const float *d_kc, con
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "transmittance");
 }
 
-nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics, const nc_camera *camera,
-                    const nc_sampling *s, double *d_sum, double *d_sumsq, nc_counters *d_counters)
+static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                            const nc_camera *camera, const nc_sampling *s, double *d_sum, double *d_sumsq,
+                            nc_counters *d_counters, const nc_guide *guide, const nc::CollectView *collect)
 {
     if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
     nc_status st = check_grid(ctx, g);
@@ -437,12 +458,130 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_o
         return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + spp must fit in 32 bits");
     if (!d_kc || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     DeviceGuard guard(ctx->device);
+    if (cam.type == 2 && !(std::cos(optics->sun_zenith_deg * M_PI / 180.0) > 0.0))
+        return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
+    if (guide && guide->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
+    if (guide && !(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
+        return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
     const nc::JobView job = make_job(cam, optics, 0);
     hipError_t e = ensure_jobs(ctx, 1);
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), &job, 1, *s, d_sum, d_sumsq,
-                              d_counters, (nc::JobView *)ctx->d_jobs);
+                              d_counters, (nc::JobView *)ctx->d_jobs, guide, collect);
+    if (e == hipSuccess && collect) e = nc::launch_collect_finish(ctx, *collect);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
+}
+
+nc_status nc_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics, const nc_camera *camera,
+                    const nc_sampling *s, double *d_sum, double *d_sumsq, nc_counters *d_counters)
+{
+    return render_one(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, d_counters, nullptr, nullptr);
+}
+
+nc_status nc_render_guided(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                           const nc_camera *camera, const nc_sampling *s, const nc_guide *guide, double *d_sum,
+                           double *d_sumsq, nc_counters *d_counters)
+{
+    if (!guide) return fail(ctx, NC_ERR_INVALID_ARG, "guide is NULL");
+    return render_one(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, d_counters, guide, nullptr);
+}
+
+nc_status nc_render_progressive(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                                const nc_camera *camera, const nc_sampling *s, const nc_guide *guide,
+                                const nc_progressive *plan, double *d_sum, double *d_sumsq, nc_counters *d_counters,
+                                nc_progress_report *report)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!s || !plan || !report || !camera) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    if (!(plan->target_rel_err > 0.0) || plan->first_spp < 2 || plan->max_spp < plan->first_spp || plan->block < 1)
+        return fail(ctx, NC_ERR_INVALID_ARG, "need target_rel_err > 0, 2 <= first_spp <= max_spp, block >= 1");
+    if (s->sample_offset + (uint64_t)plan->max_spp > 0xffffffffull)
+        return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + max_spp must fit in 32 bits");
+    *report = nc_progress_report{};
+    DeviceGuard guard(ctx->device);
+    const auto t0 = std::chrono::steady_clock::now();
+    int done = 0, next = plan->first_spp;
+    double err = INFINITY, mean = 0.0;
+    while (next > 0) {
+        nc_sampling r = *s;
+        r.sample_offset = s->sample_offset + (uint64_t)done;
+        r.spp = next;
+        const nc_status st = guide ? nc_render_guided(ctx, g, d_kc, optics, camera, &r, guide, d_sum, d_sumsq, d_counters)
+                                   : nc_render(ctx, g, d_kc, optics, camera, &r, d_sum, d_sumsq, d_counters);
+        if (st != NC_OK) return st;
+        done += next;
+        double acc[3];
+        const hipError_t e = nc::launch_image_err(ctx, d_sum, d_sumsq, camera->width, camera->height, done,
+                                                  plan->block, acc);
+        if (e != hipSuccess) return hip_fail(ctx, e, "progressive error estimate");
+        mean = acc[0] / acc[2];
+        err = mean > 0.0 ? std::sqrt(acc[1] / acc[2]) / mean : INFINITY;
+        ++report->rounds;
+        if (err <= plan->target_rel_err || done >= plan->max_spp) break;
+        // the error falls as 1/sqrt(n): ask for the predicted remainder (5 % margin), at most doubling
+        const double need = std::isfinite(err) ? done * ((err / plan->target_rel_err) * (err / plan->target_rel_err) - 1.0) * 1.05
+                                               : (double)done;
+        next = (int)std::min<double>({std::ceil(need), (double)done, (double)(plan->max_spp - done)});
+        next = std::max(next, 1);
+    }
+    report->spp_done = done;
+    report->rel_err = err;
+    report->mean = mean;
+    report->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    return NC_OK;
+}
+
+nc_status nc_gather_rate(nc_ctx *ctx, const float *d_buf, uint64_t n_words, int32_t threads, int32_t loads,
+                         float *d_out, double *loads_per_s)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!d_buf || !d_out || !loads_per_s) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    if (n_words < 2 || n_words > (1ull << 32) || (n_words & (n_words - 1)) != 0)
+        return fail(ctx, NC_ERR_INVALID_ARG, "n_words must be a power of two in [2, 2^32]");
+    if (threads < 256 || threads % 256 != 0 || loads < 8 || loads % 8 != 0)
+        return fail(ctx, NC_ERR_INVALID_ARG, "threads must be a multiple of 256, loads a multiple of 8");
+    DeviceGuard guard(ctx->device);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    hipError_t e = hipEventCreate(&e0);
+    if (e == hipSuccess) e = hipEventCreate(&e1);
+    const uint32_t mask = (uint32_t)(n_words - 1);
+    if (e == hipSuccess) e = nc::launch_gather_rate(ctx, d_buf, mask, threads, loads, 1u, d_out);   // warm-up
+    if (e == hipSuccess) e = hipEventRecord(e0, ctx->stream);
+    if (e == hipSuccess) e = nc::launch_gather_rate(ctx, d_buf, mask, threads, loads, 2u, d_out);
+    if (e == hipSuccess) e = hipEventRecord(e1, ctx->stream);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    float ms = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return hip_fail(ctx, e, "gather rate");
+    *loads_per_s = (double)threads * loads / (ms * 1e-3);
+    return NC_OK;
+}
+
+nc_status nc_collect_vertices(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                              const nc_camera *camera, const nc_sampling *s, float *d_records, uint64_t capacity,
+                              unsigned long long *d_count, float *d_path_L, double *d_sum, double *d_sumsq,
+                              nc_counters *d_counters)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!camera || !s) return fail(ctx, NC_ERR_INVALID_ARG, "camera or sampling is NULL");
+    if (!d_count || !d_path_L || (capacity > 0 && !d_records))
+        return fail(ctx, NC_ERR_INVALID_ARG, "NULL collection buffer");
+    const uint64_t slots = (uint64_t)(camera->width > 0 ? camera->width : 0) *
+                           (uint64_t)(camera->height > 0 ? camera->height : 0) * (uint64_t)(s->spp > 0 ? s->spp : 0);
+    if (slots > 0xffffffffull) return fail(ctx, NC_ERR_INVALID_ARG, "width * height * spp must fit in 32 bits");
+    nc::CollectView cv;
+    cv.records = d_records;
+    cv.cap = capacity;
+    cv.count = d_count;
+    cv.final_L = d_path_L;
+    if (s->spp == 0) {
+        DeviceGuard guard(ctx->device);
+        const hipError_t e = hipMemsetAsync(d_count, 0, sizeof(unsigned long long), ctx->stream);
+        return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "collect");
+    }
+    return render_one(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, d_counters, nullptr, &cv);
 }
 
 nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
@@ -469,6 +608,8 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int3
             return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
         nc::CamView cam;
         if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;
+        if (cam.type == 2 && !(std::cos(optics[j].sun_zenith_deg * M_PI / 180.0) > 0.0))
+            return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
         jobs[j] = make_job(cam, optics + j, out_offsets[j]);
     }
     DeviceGuard guard(ctx->device);
@@ -587,6 +728,150 @@ nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *g, const float *d_kc, cons
     hipError_t e = nc::launch_flux(ctx, g, d_kc, make_opt(optics, g->params.k_gas), (float)extinction_scale, px_nx,
                                    px_ny, n_photons, *s, nullptr, nullptr, d_grad, d_out, nullptr);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "flux adjoint");
+}
+
+nc_status nc_guide_create(nc_ctx *ctx, uint64_t seed, nc_guide **out)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out) return fail(ctx, NC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    DeviceGuard guard(ctx->device);
+    nc_guide *gd = new (std::nothrow) nc_guide();
+    if (!gd) return fail(ctx, NC_ERR_OOM, "host allocation failed");
+    gd->device = ctx->device;
+    const size_t np = nc::kGuideParams;
+    hipError_t e = hipMalloc(&gd->d_params, np * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&gd->d_m, np * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&gd->d_v, np * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&gd->d_grad, np * sizeof(float));
+    if (e == hipSuccess) e = hipMalloc(&gd->d_acc, 2 * sizeof(double));
+    const int in_pad[4] = {16, 64, 64, 64}, out_pad[4] = {64, 64, 64, 48};
+    for (int l = 0; l < 4 && e == hipSuccess; ++l) {
+        e = hipMalloc(&gd->d_w[l], sizeof(short) * in_pad[l] * out_pad[l]);
+        if (e == hipSuccess) e = hipMalloc(&gd->d_wt[l], sizeof(short) * in_pad[l] * out_pad[l]);
+        if (e == hipSuccess) e = hipMalloc(&gd->d_bias[l], sizeof(float) * out_pad[l]);
+    }
+    if (e != hipSuccess) {
+        nc_guide_destroy(gd);
+        return hip_fail(ctx, e, "hipMalloc(guide)");
+    }
+    // He-uniform weights U(-sqrt(6/in), sqrt(6/in)) from a splitmix64 stream, zero biases
+    std::vector<float> h(np, 0.0f), zero(np, 0.0f);
+    uint64_t st = seed;
+    auto next_u = [&st]() {
+        uint64_t z = (st += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        z ^= z >> 31;
+        return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+    };
+    const int ins[4] = {7, 64, 64, 64}, outs[4] = {64, 64, 64, 40};
+    size_t k = 0;
+    for (int l = 0; l < 4; ++l) {
+        const double lim = std::sqrt(6.0 / ins[l]);
+        for (int i = 0; i < outs[l] * ins[l]; ++i) h[k++] = (float)((2.0 * next_u() - 1.0) * lim);
+        k += outs[l];
+    }
+    e = hipMemcpyAsync(gd->d_params, h.data(), np * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(gd->d_m, zero.data(), np * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(gd->d_v, zero.data(), np * sizeof(float), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = nc::guide_pack(ctx, gd);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        nc_guide_destroy(gd);
+        return hip_fail(ctx, e, "guide init");
+    }
+    *out = gd;
+    return NC_OK;
+}
+
+void nc_guide_destroy(nc_guide *gd)
+{
+    if (!gd) return;
+    DeviceGuard guard(gd->device);
+    (void)hipFree(gd->d_params);
+    (void)hipFree(gd->d_m);
+    (void)hipFree(gd->d_v);
+    (void)hipFree(gd->d_grad);
+    (void)hipFree(gd->d_acc);
+    for (int l = 0; l < 4; ++l) {
+        (void)hipFree(gd->d_w[l]);
+        (void)hipFree(gd->d_wt[l]);
+        (void)hipFree(gd->d_bias[l]);
+    }
+    (void)hipFree(gd->d_scratch);
+    delete gd;
+}
+
+static nc_status guide_check(nc_ctx *ctx, const nc_guide *gd)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!gd) return fail(ctx, NC_ERR_INVALID_ARG, "guide is NULL");
+    if (gd->device != ctx->device) return fail(ctx, NC_ERR_STATE, "guide lives on another device");
+    return NC_OK;
+}
+
+nc_status nc_guide_get_params(nc_ctx *ctx, const nc_guide *gd, float *d_params)
+{
+    nc_status st = guide_check(ctx, gd);
+    if (st != NC_OK) return st;
+    if (!d_params) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipMemcpyAsync(d_params, gd->d_params, sizeof(float) * nc::kGuideParams, hipMemcpyDeviceToDevice,
+                                  ctx->stream);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide get params");
+}
+
+nc_status nc_guide_set_params(nc_ctx *ctx, nc_guide *gd, const float *d_params)
+{
+    nc_status st = guide_check(ctx, gd);
+    if (st != NC_OK) return st;
+    if (!d_params) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = hipMemcpyAsync(gd->d_params, d_params, sizeof(float) * nc::kGuideParams, hipMemcpyDeviceToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess) e = nc::guide_pack(ctx, gd);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide set params");
+}
+
+nc_status nc_guide_forward(nc_ctx *ctx, const nc_guide *gd, const float *d_in, int32_t n, int32_t stride,
+                           float *d_out)
+{
+    nc_status st = guide_check(ctx, gd);
+    if (st != NC_OK) return st;
+    if (n < 0 || stride < nc::kGuideIn) return fail(ctx, NC_ERR_INVALID_ARG, "bad size or stride");
+    if (n == 0) return NC_OK;
+    if (!d_in || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::guide_forward(ctx, gd, d_in, n, stride, d_out, nullptr, nullptr, nullptr);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide forward");
+}
+
+nc_status nc_guide_train_step(nc_ctx *ctx, nc_guide *gd, const float *d_records, int32_t n, float lr, double *d_loss)
+{
+    nc_status st = guide_check(ctx, gd);
+    if (st != NC_OK) return st;
+    if (n < 1) return fail(ctx, NC_ERR_INVALID_ARG, "need at least one record");
+    if (!d_records) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    if (!(lr >= 0.0f) || !std::isfinite(lr)) return fail(ctx, NC_ERR_RANGE, "bad learning rate");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::guide_train_step(ctx, gd, d_records, n, nc::kGuideRecord, lr, d_loss, true);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide train step");
+}
+
+nc_status nc_guide_gradient(nc_ctx *ctx, nc_guide *gd, const float *d_records, int32_t n, float *d_grad,
+                            double *d_loss)
+{
+    nc_status st = guide_check(ctx, gd);
+    if (st != NC_OK) return st;
+    if (n < 1) return fail(ctx, NC_ERR_INVALID_ARG, "need at least one record");
+    if (!d_records || !d_grad) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
+    DeviceGuard guard(ctx->device);
+    hipError_t e = nc::guide_train_step(ctx, gd, d_records, n, nc::kGuideRecord, 0.0f, d_loss, false);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(d_grad, gd->d_grad, sizeof(float) * nc::kGuideParams, hipMemcpyDeviceToDevice,
+                           ctx->stream);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide gradient");
 }
 
 nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d_key, uint32_t *d_out, int32_t n)

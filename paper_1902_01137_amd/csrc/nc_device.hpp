@@ -620,4 +620,28 @@ __device__ inline void stage_levels(const GridView &g, int lds_first, int lds_no
     __syncthreads();
 }
 
+// ---------------------------------------------------------------------------
+// Matrix-core fragments.  For v_mfma_f32_16x16x16_bf16, lane l (0..63) holds
+//   A[m][k] for m = l % 16, k = 4 (l / 16) + i  (i = 0..3),
+//   B[k][n] for n = l % 16, k = 4 (l / 16) + i,
+//   D[m][n] for n = l % 16, m = 4 (l / 16) + i.
+// ---------------------------------------------------------------------------
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline short to_bf16(float x)
+{
+    // round to nearest even (finite inputs)
+    uint32_t u = __float_as_uint(x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (short)(u >> 16);
+}
+
+__device__ inline float from_bf16(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+__device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
 }  // namespace nc

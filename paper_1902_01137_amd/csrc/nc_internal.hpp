@@ -34,9 +34,35 @@ struct nc_grid {
 };
 
 namespace nc {
+constexpr int kGuideIn = 7;
+constexpr int kGuideWidth = 64;
+constexpr int kGuideLayers = 4;
+constexpr int kGuideLobes = 8;
+constexpr int kGuideOut = 5 * kGuideLobes;
+constexpr int kGuideParams = 7 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 40 + 40;   // 11432
+constexpr int kGuideRecord = 12;   // floats per training record
+constexpr float kLogKappaMin = -3.0f, kLogKappaMax = 8.0f;
+}  // namespace nc
+
+struct nc_guide {
+    int device = 0;
+    float *d_params = nullptr;                 // fp32 master weights (flat, layer by layer: W [out][in], b [out])
+    float *d_m = nullptr, *d_v = nullptr;      // Adam moments
+    float *d_grad = nullptr;                   // gradient of the last step
+    double *d_acc = nullptr;                   // [loss sum, weight sum] of the last step
+    short *d_w[4] = {};                        // bf16 padded weights [out_pad][in_pad]
+    short *d_wt[4] = {};                       // and transposed
+    float *d_bias[4] = {};                     // fp32 padded biases
+    float *d_scratch = nullptr;                // training activations
+    int scratch_cap = 0;
+    long long step = 0;
+};
+
+namespace nc {
 
 constexpr int kScratchWords = 256;   // [0] queue head, [1] validation flag, [8..] launch parameters
 constexpr int kScratchRare = 8;
+constexpr int kScratchErr = 240;     // [240..242] image error accumulators (float64)
 
 // Camera, optics and launch records as the kernels see them (FP32).
 struct CamView {
@@ -50,6 +76,22 @@ struct OptView {
     float sun[3];
     float ground_w;      // rho / pi * S * cos(theta_sun): ground local estimate before transmissivity
     int max_scatter, max_segments;
+};
+
+// bf16 weights of the guide network as the kernels read them.
+struct GuideWeights {
+    const short *w[4];    // W_pad [out_pad][in_pad]
+    const short *wt[4];   // W_pad transposed [in_pad][out_pad]
+    const float *b[4];    // bias [out_pad]
+};
+GuideWeights guide_weights(const nc_guide *gd);
+
+// Vertex collection: where the renderer writes training records.
+struct CollectView {
+    float *records;                   // cap x 12 floats
+    unsigned long long cap;
+    unsigned long long *count;        // records attempted (may exceed cap)
+    float *final_L;                   // per path (pix * spp + sample): the path's radiance
 };
 
 // One job of a batched render: a view and its sun (device memory).
@@ -72,7 +114,7 @@ struct Shape {
 };
 
 GridView grid_view(const nc_grid *g, const float *d_kc);
-Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default);
+Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve = 0);
 
 hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad);
 hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int level, float *kmin, float *kmax, uint8_t *mg);
@@ -85,9 +127,22 @@ hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float
 hipError_t launch_flux(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op, float kscale,
                        int px_nx, int px_ny, unsigned long long n_photons, const nc_sampling &s, double *tally,
                        double *glob, const double *grad, double *out, nc_counters *counters);
+hipError_t guide_pack(const nc_ctx *ctx, nc_guide *gd);
+hipError_t guide_forward(const nc_ctx *ctx, const nc_guide *gd, const float *X, int n, int rec_stride, float *Z,
+                         float *H0, float *H1, float *H2);
+hipError_t guide_train_step(const nc_ctx *ctx, nc_guide *gd, const float *rec, int n, int rec_stride, float lr,
+                            double *d_loss, bool apply);
 hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, JobView *jobs_dev);
+                         nc_counters *counters, JobView *jobs_dev, const nc_guide *guide = nullptr,
+                         const CollectView *collect = nullptr);
+hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv);
+hipError_t launch_gather_rate(const nc_ctx *ctx, const float *buf, uint32_t mask, int threads, int loads,
+                              uint32_t seed, float *out);
+// Block-mean error statistics of an image estimate (synchronises the stream):
+// out3 = [sum of block means, sum of squared block standard errors, blocks].
+hipError_t launch_image_err(const nc_ctx *ctx, const double *sum, const double *sumsq, int W, int H, int n, int b,
+                            double *out3);
 
 }  // namespace nc

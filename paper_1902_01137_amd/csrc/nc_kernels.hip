@@ -10,7 +10,7 @@
 namespace nc {
 
 // ===========================================================================
-// Grid build (Section 3.1.1; criterion of Section 4.2; Appendix C indexing)
+// Grid build (Section 3.1.1; criterion of Section 4.2; Appendix B.3 indexing)
 // ===========================================================================
 
 __device__ inline bool merge_criterion(float kmin, float kmax, double k_gas, double dz_node, double tau, int crit)
@@ -159,16 +159,21 @@ hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsign
         const int d0 = level_dim(g->n[0], l), d1 = level_dim(g->n[1], l), d2 = level_dim(g->n[2], l);
         const long long total = (long long)d0 * d1 * d2;
         const double dz_node = g->h[2] * (double)(1 << l);
+        // the flat grid merges whole levels: criterion 0 against +inf
+        // (always true for finite k) or 0 (never true)
+        const bool flat = g->params.criterion == 2;
+        const double tau = flat ? (l <= g->params.flat_level ? INFINITY : 0.0) : g->params.tau_tilde;
+        const int crit = flat ? 0 : g->params.criterion;
         float2 *out = g->d_nodes + g->off[l];
         if (l == 1) {
             hipLaunchKernelGGL(build_level1_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream, d_kc,
-                               g->n[0], g->n[1], g->n[2], out, d0, d1, d2, g->params.k_gas, dz_node,
-                               g->params.tau_tilde, g->params.criterion, d_bad);
+                               g->n[0], g->n[1], g->n[2], out, d0, d1, d2, g->params.k_gas, dz_node, tau, crit,
+                               d_bad);
         } else {
             const int c0 = level_dim(g->n[0], l - 1), c1 = level_dim(g->n[1], l - 1), c2 = level_dim(g->n[2], l - 1);
             hipLaunchKernelGGL(build_level_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream,
                                (const float2 *)(g->d_nodes + g->off[l - 1]), c0, c1, c2, out, d0, d1, d2,
-                               g->params.k_gas, dz_node, g->params.tau_tilde, g->params.criterion);
+                               g->params.k_gas, dz_node, tau, crit);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -392,6 +397,11 @@ struct RenderArgs {
     uint32_t sample_base;       // sample_offset (fits 32 bits)
     uint32_t stream_base;
     const RenderRare *rare;
+    GuideWeights gw;            // guided mode: the network
+    float guide_frac;           // guided mode: probability of sampling the guide
+    CollectView col;            // collection mode: where vertices go
+    int col_spp;                // collection mode: samples per pixel (path slot = pix * spp + sample)
+    int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
     nc_counters *counters;
     unsigned long long *queue;
     unsigned long long items;
@@ -402,7 +412,9 @@ struct RenderArgs {
 // are waiting in (ballot counts); the other lanes wait.  Expensive code
 // (events, ray starts, new samples) thus runs for many lanes at once instead
 // of diverging inside every traversal step.
-enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhIdle = 5 };
+enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhGuide = 5, kPhIdle = 6 };
+enum RenderMode { kPlain = 0, kGuided = 1, kCollect = 2 };
+constexpr int kGuideScratchPerWave = 2 * 16 * 64 * 2 + 16 * 48 * 4;   // two bf16 activation tiles + fp32 outputs
 
 // After the optical thickness tau has been drawn or carried: a tentative
 // collision inside the current voxel, or a move to the next voxel.
@@ -440,7 +452,7 @@ __device__ inline void camera_ray_v(const volatile CamView &c, int px, int py, f
         const float inv = rsqrtf(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) d[a] = v[a] * inv;
-    } else {
+    } else if (c.type == 1) {
         const float sx = (((float)px + u1) / W - 0.5f) * c.sx;
         const float sy = (0.5f - ((float)py + u2) / H) * c.sy;
 #pragma unroll
@@ -448,10 +460,79 @@ __device__ inline void camera_ray_v(const volatile CamView &c, int px, int py, f
             o[a] = c.pos[a] + sx * c.r[a] + sy * c.u[a];
             d[a] = c.f[a];
         }
+    } else {
+        // horizontal sensor: px along +x, py along +y, looking up
+        o[0] = c.pos[0] + (((float)px + u1) / W - 0.5f) * c.sx;
+        o[1] = c.pos[1] + (((float)py + u2) / H - 0.5f) * c.sy;
+        o[2] = c.pos[2];
+        d[0] = 0.0f;
+        d[1] = 0.0f;
+        d[2] = 1.0f;
     }
 }
 
-template <int kWavesPerEU>
+__device__ inline void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Guided scattering (one-sample MIS): with probability c draw the new
+// direction from the network's vMF mixture, otherwise from HG; the path
+// weight is multiplied by p_HG / (c q + (1 - c) p_HG).  z: the 40 outputs.
+__device__ inline void guided_turn(const float *z, float c, float g, float u_sel, float u_lobe, float u1, float u2,
+                                   float pd[3], float &beta)
+{
+    float amax = z[0];
+#pragma unroll
+    for (int j = 1; j < kGuideLobes; ++j) amax = fmaxf(amax, z[5 * j]);
+    float psum = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kGuideLobes; ++j) psum += __expf(z[5 * j] - amax);
+    float nd[3] = {pd[0], pd[1], pd[2]};
+    if (u_sel < c) {
+        // lobe by its weight, then the stable vMF cosine inversion (Jakob 2012)
+        int pick = kGuideLobes - 1;
+        float cum = 0.0f;
+        const float target = u_lobe * psum;
+#pragma unroll
+        for (int j = 0; j < kGuideLobes; ++j) {
+            cum += __expf(z[5 * j] - amax);
+            if (target < cum && pick == kGuideLobes - 1 && j < kGuideLobes - 1) pick = j;
+        }
+        float m[3] = {z[5 * pick + 1], z[5 * pick + 2], z[5 * pick + 3]};
+        const float inv = rsqrtf(fmaxf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2], 1e-24f));
+        m[0] *= inv;
+        m[1] *= inv;
+        m[2] *= inv;
+        const float kap = __expf(fminf(fmaxf(z[5 * pick + 4], kLogKappaMin), kLogKappaMax));
+        const float t = fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) / kap));
+        nd[0] = m[0];
+        nd[1] = m[1];
+        nd[2] = m[2];
+        turn(nd, t, u2);
+    } else {
+        turn(nd, hg_sample_mu(g, u1), u2);
+    }
+    // mixture density of the chosen direction
+    float q = 0.0f;
+#pragma unroll
+    for (int j = 0; j < kGuideLobes; ++j) {
+        const float m0 = z[5 * j + 1], m1 = z[5 * j + 2], m2 = z[5 * j + 3];
+        const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
+        const float cw = (m0 * nd[0] + m1 * nd[1] + m2 * nd[2]) * inv;
+        const float kap = __expf(fminf(fmaxf(z[5 * j + 4], kLogKappaMin), kLogKappaMax));
+        const float norm = kap / (2.0f * kPi * (-expm1f(-2.0f * kap)));
+        q += __expf(z[5 * j] - amax) / psum * norm * __expf(kap * (cw - 1.0f));
+    }
+    const float php = hg_phase(g, pd[0] * nd[0] + pd[1] * nd[1] + pd[2] * nd[2]);
+    beta *= php / (c * q + (1.0f - c) * php);
+    pd[0] = nd[0];
+    pd[1] = nd[1];
+    pd[2] = nd[2];
+}
+
+template <int kWavesPerEU, int kMode>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
     extern __shared__ float2 s_nodes[];
@@ -487,6 +568,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     bool ground_ev = false;
     int order = 0, segs = 0;
     VoxelCache vc{g.L, -1, 0, 0, 0.0f, 0.0f};
+    float beta = 1.0f;                   // path weight (guided mode)
+    float kev = 0.0f;                    // extinction at the current event (guided and collection modes)
     unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
     int chunk_left = 0;
     bool queue_done = false;
@@ -497,13 +580,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         const int n_event = __popcll(__ballot(phase == kPhEvent));
         const int n_ray = __popcll(__ballot(phase == kPhRay));
         const int n_sample = __popcll(__ballot(phase == kPhSample));
-        if (n_cross + n_coll + n_event + n_ray + n_sample == 0) break;
+        const int n_guide = kMode == kGuided ? __popcll(__ballot(phase == kPhGuide)) : 0;
+        if (n_cross + n_coll + n_event + n_ray + n_sample + n_guide == 0) break;
         int run = kPhCross, best = n_cross;
         if (n_coll >= best) { run = kPhCollide; best = n_coll; }
         if (n_event >= best) { run = kPhEvent; best = n_event; }
         if (n_ray >= best) { run = kPhRay; best = n_ray; }
         if (n_sample > best) { run = kPhSample; best = n_sample; }
-        if (lane == 0) {
+        if (kMode == kGuided && n_guide > best) { run = kPhGuide; best = n_guide; }
+        if (lane == 0 && run < 5) {
             atomicAdd(s_cnt + kCTrips0 + run, 1ull);
             atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
         }
@@ -573,7 +658,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 rng.need(3, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 bool cont = false;               // go on to the scatter / reflect decision
                 if (shadow) {
-                    if (res == kExit) Lp += w_nee;   // the sun ray got through
+                    if (res == kExit) Lp += beta * w_nee;   // the sun ray got through
                     cont = true;
                 } else if (res == kReal) {
                     // volume event: local estimate of the sun, then scatter or absorb
@@ -584,6 +669,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         r.o[a] = r.o[a] + r.t * r.d[a];
                     }
                     const float kd = g.kscale * kc_hit;
+                    kev = kd + g.k_gas;
                     const float ssa = A.op.ssa * kd / (kd + g.k_gas);
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
                     w_nee = ssa * hg_phase(A.op.g, mu);
@@ -630,15 +716,101 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         phase = kPhSample;
                     } else if (rng.take() >= p_cont) {
                         phase = kPhSample;       // absorbed (volume) or not reflected (ground)
+                    } else if (kMode == kGuided && !ground_ev) {
+                        phase = kPhGuide;        // the network proposes the new direction
                     } else {
                         const float u1 = rng.take(), u2 = rng.take();
+                        const float win[3] = {pd[0], pd[1], pd[2]};
                         if (ground_ev)
                             lambert(pd, u1, u2);
                         else
                             turn(pd, hg_sample_mu(A.op.g, u1), u2);
                         phase = kPhRay;
+                        if (kMode == kCollect && !ground_ev) {
+                            // training record: vertex, incoming and outgoing directions, radiance so far
+                            const unsigned long long k = atomicAdd(A.col.count, 1ull);
+                            if (k < A.col.cap) {
+                                float *q = A.col.records + k * kGuideRecord;
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) {
+                                    q[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
+                                    q[3 + a] = win[a];
+                                    q[7 + a] = pd[a];
+                                }
+                                q[6] = __logf(1.0f + kev);
+                                q[10] = Lp;
+                                q[11] = __uint_as_float((uint32_t)(pix * A.col_spp + s));
+                            }
+                        }
                     }
                 }
+            }
+        } else if (kMode == kGuided && run == kPhGuide) {
+            // ---- network inference on the matrix cores, 16 lanes per tile, then MIS sampling
+            const bool active = phase == kPhGuide;
+            extern __shared__ float2 s_dyn[];
+            char *base = reinterpret_cast<char *>(s_dyn) + A.guide_lds + (threadIdx.x >> 6) * kGuideScratchPerWave;
+            short *act0 = reinterpret_cast<short *>(base);                     // [16][64] bf16
+            short *act1 = reinterpret_cast<short *>(base + 16 * 64 * 2);       // [16][64] bf16
+            float *outz = reinterpret_cast<float *>(base + 2 * 16 * 64 * 2);   // [16][48] fp32
+            const int mrow = lane & 15, kq = lane >> 4;
+            if (active) rng.need(4, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+            const unsigned long long want = __ballot(active);
+            for (int t = 0; t < 4; ++t) {
+                if (((want >> (16 * t)) & 0xFFFFull) == 0ull) continue;   // no lane of this tile needs the network
+                const bool owner = kq == t;
+                if (owner) {
+                    float in[16];
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) in[k] = 0.0f;
+                    if (active) {
+#pragma unroll
+                        for (int a = 0; a < 3; ++a) {
+                            in[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
+                            in[3 + a] = pd[a];
+                        }
+                        in[6] = __logf(1.0f + kev);
+                    }
+#pragma unroll
+                    for (int k = 0; k < 16; ++k) act0[mrow * 64 + k] = to_bf16(in[k]);
+                }
+                wave_sync();
+                for (int layer = 0; layer < kGuideLayers; ++layer) {
+                    const int kin = layer == 0 ? 16 : 64, nout = layer == kGuideLayers - 1 ? 48 : 64;
+                    const short *src = (layer & 1) ? act1 : act0;
+                    short *dst = (layer & 1) ? act0 : act1;
+                    for (int nt = 0; nt < nout / 16; ++nt) {
+                        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+                        for (int kt = 0; kt < kin / 16; ++kt) {
+                            bf16x4 a, b;
+                            const int kk = kt * 16 + 4 * kq;
+#pragma unroll
+                            for (int i = 0; i < 4; ++i) {
+                                a[i] = src[mrow * 64 + kk + i];
+                                b[i] = A.gw.w[layer][(nt * 16 + mrow) * kin + kk + i];
+                            }
+                            c = mfma16(a, b, c);
+                        }
+                        const int col = nt * 16 + mrow;
+                        const float bias = A.gw.b[layer][col];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int m = 4 * kq + i;
+                            const float v = c[i] + bias;
+                            if (layer < kGuideLayers - 1)
+                                dst[m * 64 + col] = to_bf16(fmaxf(v, 0.0f));
+                            else
+                                outz[m * 48 + col] = v;
+                        }
+                    }
+                    wave_sync();
+                }
+                if (owner && active) {
+                    const float u_sel = rng.take(), u_lobe = rng.take(), u1 = rng.take(), u2 = rng.take();
+                    guided_turn(outz + mrow * 48, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta);
+                    phase = kPhRay;
+                }
+                wave_sync();
             }
         } else if (run == kPhRay) {
             // ---- start the next ray at r.o along pd (path) or towards the sun
@@ -660,6 +832,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             if (phase == kPhSample) {
                 if (have_item) {
                     if (traced) {
+                        if (kMode == kCollect) A.col.final_L[(size_t)pix * A.col_spp + s] = Lp;
                         acc += Lp;
                         acc2 += Lp * Lp;
                         ++s;
@@ -752,6 +925,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
 #pragma unroll
                 for (int a = 0; a < 3; ++a) r.o[a] = o[a];
                 Lp = 0.0f;
+                beta = 1.0f;
                 order = 0;
                 segs = 0;
                 shadow = false;
@@ -759,6 +933,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 vc.lev = g.L;
                 vc.i0 = -1;
                 phase = kPhRay;
+                if (J.cam.type == 2) {
+                    // irradiance sensor: first the sun's direct beam (a sun ray of
+                    // weight 1), then, as after a ground reflection that always
+                    // happens, a cosine-distributed upward path of weight pi / mu_sun
+                    beta = kPi / sun[2];
+                    w_nee = sun[2] * (1.0f / kPi);
+                    p_cont = 1.0f;
+                    ground_ev = true;
+                    shadow = true;
+                }
             }
         }
         if (lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
@@ -786,11 +970,32 @@ __global__ void zero_u64_kernel(unsigned long long *p, int n)
     if (i < n) p[i] = 0ull;
 }
 
+__global__ void collect_finish_kernel(CollectView cv)
+{
+    const unsigned long long n = *cv.count < cv.cap ? *cv.count : cv.cap;
+    for (unsigned long long i = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; i < n;
+         i += (unsigned long long)gridDim.x * blockDim.x) {
+        float *q = cv.records + i * kGuideRecord;
+        const uint32_t slot = __float_as_uint(q[11]);
+        // radiance the path gathered after this vertex: its final value minus what it held here
+        q[10] = fmaxf(cv.final_L[slot] - q[10], 0.0f);
+    }
+}
+
+hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv)
+{
+    hipLaunchKernelGGL(collect_finish_kernel, dim3(512), dim3(256), 0, ctx->stream, cv);
+    return hipGetLastError();
+}
+
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs_host, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, JobView *jobs_dev)
+                         nc_counters *counters, JobView *jobs_dev, const nc_guide *guide, const CollectView *collect)
 {
-    Shape sh = choose_shape(ctx, g, 256);
+    const int mode = guide ? kGuided : collect ? kCollect : kPlain;
+    const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
+    const size_t guide_bytes = mode == kGuided ? (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -824,7 +1029,15 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.queue = ctx->d_scratch;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
-    static_assert(sizeof(RenderRare) <= (kScratchWords - kScratchRare) * sizeof(unsigned long long),
+    const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
+    A.guide_lds = (int)node_bytes;
+    A.guide_frac = s.guide_frac;
+    A.col_spp = s.spp;
+    A.gw = GuideWeights{};
+    A.col = CollectView{};
+    if (guide) A.gw = guide_weights(guide);
+    if (collect) A.col = *collect;
+    static_assert(sizeof(RenderRare) <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
     hipError_t e = hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
                                   ctx->stream);
@@ -832,20 +1045,79 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_scratch, 1);
+    if (collect) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, collect->count, 1);
     // register budget: waves per SIMD the kernel is compiled for (3..6)
-    const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 3;
-    const void *fn = wpe == 3   ? (const void *)render_kernel<3>
-                     : wpe == 4 ? (const void *)render_kernel<4>
-                     : wpe == 5 ? (const void *)render_kernel<5>
-                                : (const void *)render_kernel<6>;
+    // (default 4: the plain kernel fits 128 registers without spilling)
+    const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 4;
+    const void *fn = nullptr;
+    if (mode == kGuided)
+        fn = (const void *)render_kernel<3, kGuided>;   // the network phase needs the larger register budget
+    else if (mode == kCollect)
+        fn = (const void *)render_kernel<3, kCollect>;
+    else
+        fn = wpe == 3   ? (const void *)render_kernel<3, kPlain>
+             : wpe == 4 ? (const void *)render_kernel<4, kPlain>
+             : wpe == 5 ? (const void *)render_kernel<5, kPlain>
+                        : (const void *)render_kernel<6, kPlain>;
     int resident = 0;
-    const size_t lds = (size_t)sh.lds_nodes * sizeof(float2);
+    const size_t lds = node_bytes + guide_bytes;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, fn, sh.block, lds) == hipSuccess && resident > 0)
         sh.wgs = ctx->num_cus * resident;
     const long long max_wgs = (long long)((items + sh.block - 1) / sh.block);
     const int wgs = (int)std::max<long long>(1, std::min<long long>(max_wgs, sh.wgs));
     void *args[] = {&A};
     return hipLaunchKernel(fn, dim3(wgs), dim3(sh.block), args, lds, ctx->stream);
+}
+
+// Error of an image estimate over b x b pixel blocks (b = 1: per pixel):
+// acc[0] += block mean radiance, acc[1] += squared standard error of the
+// block mean, acc[2] += 1 per block.  A ragged edge block averages the
+// pixels it has.
+__global__ void image_err_kernel(const double *sum, const double *sumsq, int W, int H, int n, int b, double *acc)
+{
+    const int bw = (W + b - 1) / b, bh = (H + b - 1) / b;
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    double m = 0.0, e = 0.0, c = 0.0;
+    if (i < bw * bh) {
+        const int bx = i % bw, by = i / bw;
+        const int x1 = min(W, (bx + 1) * b), y1 = min(H, (by + 1) * b);
+        int cnt = 0;
+        for (int y = by * b; y < y1; ++y)
+            for (int x = bx * b; x < x1; ++x) {
+                const double mp = sum[(size_t)y * W + x] / n;
+                const double var = fmax(sumsq[(size_t)y * W + x] / n - mp * mp, 0.0) * n / (n > 1 ? n - 1 : 1);
+                m += mp;
+                e += var / n;
+                ++cnt;
+            }
+        m /= cnt;
+        e /= (double)cnt * cnt;
+        c = 1.0;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        m += __shfl_xor(m, off);
+        e += __shfl_xor(e, off);
+        c += __shfl_xor(c, off);
+    }
+    if (__lane_id() == 0 && c > 0.0) {
+        atomicAdd(acc, m);
+        atomicAdd(acc + 1, e);
+        atomicAdd(acc + 2, c);
+    }
+}
+
+hipError_t launch_image_err(const nc_ctx *ctx, const double *sum, const double *sumsq, int W, int H, int n, int b,
+                            double *out3)
+{
+    double *acc = reinterpret_cast<double *>(ctx->d_scratch + kScratchErr);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream,
+                       reinterpret_cast<unsigned long long *>(acc), 3);
+    const int units = ((W + b - 1) / b) * ((H + b - 1) / b);
+    hipLaunchKernelGGL(image_err_kernel, dim3((units + 255) / 256), dim3(256), 0, ctx->stream, sum, sumsq, W, H, n, b,
+                       acc);
+    hipError_t e = hipMemcpyAsync(out3, acc, 3 * sizeof(double), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    return e;
 }
 
 __global__ void philox_kernel(const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n)
@@ -887,7 +1159,7 @@ GridView grid_view(const nc_grid *g, const float *d_kc)
     return v;
 }
 
-Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default)
+Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve)
 {
     Shape sh;
     sh.block = ctx->launch.block > 0 ? ctx->launch.block : block_default;
@@ -897,7 +1169,8 @@ Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default)
     sh.spi = ctx->launch.samples_per_item > 0 ? ctx->launch.samples_per_item : 4;
     // LDS staging of the top levels: as many whole levels as fit the budget
     const size_t wgs_per_cu = std::max(1, waves / (sh.block / 64));
-    size_t budget = std::min<size_t>(ctx->lds_per_cu / wgs_per_cu, 60 * 1024) - 1024;
+    const size_t cap = std::min<size_t>(ctx->lds_per_cu / wgs_per_cu, 60 * 1024);
+    const size_t budget = cap > 1024 + reserve ? cap - 1024 - reserve : 0;
     int first = g->L + 1;
     if (ctx->launch.lds_levels == 0 || g->L == 0) {
         first = g->L + 1;

@@ -53,7 +53,8 @@ class FieldDesc:
 class GridParams:
     tau_tilde: float = 1.0
     k_gas: float = 0.0
-    criterion: int = 0          # 0: kmax*dz_node < tau_tilde, 1: (kmax-kmin)*dz_node < tau_tilde
+    criterion: int = 0          # 0: kmax*dz_node < tau_tilde, 1: (kmax-kmin)*dz_node < tau_tilde, 2: flat
+    flat_level: int = 3         # criterion 2: every node of level <= flat_level is a voxel (2^3-cell supercells)
 
 
 @dataclass
@@ -71,7 +72,7 @@ class Optics:
 
 @dataclass
 class Camera:
-    type: int = 0                  # 0 pinhole, 1 orthographic
+    type: int = 0                  # 0 pinhole, 1 orthographic, 2 horizontal irradiance sensor (looks up)
     pos: tuple = (0.0, 0.0, 0.0)
     target: tuple = (0.0, 0.0, -1.0)
     up: tuple = (0.0, 0.0, 1.0)
@@ -310,9 +311,11 @@ def scene_small(spp=16):
                  cam, Sampling(seed=SEED_GPU_BASE + 1, spp=spp))
 
 
-def scene_cumulus(fine=(320, 1024, 1024), pool=2, width=1024, height=1024, spp=64, workers=8):
-    """Broken cumulus at 25 m (512x512x160) seen by an oblique pinhole camera."""
-    desc, k = cumulus_field(fine=fine, pool=pool, workers=workers)
+def scene_cumulus(fine=(320, 1024, 1024), pool=2, width=1024, height=1024, spp=64, workers=8, field=None):
+    """Broken cumulus at 25 m (512x512x160) seen by an oblique pinhole camera.
+    `field` = (desc, k) replaces the generated field (e.g. another member of
+    the refinement family)."""
+    desc, k = field if field is not None else cumulus_field(fine=fine, pool=pool, workers=workers)
     (xa, xb), (ya, yb), (za, zb) = desc.box
     cx, cy = (xa + xb) / 2, (ya + yb) / 2
     # camera 3 km outside the -X face at mid-Y, 2 km high, looking at the cloud layer

@@ -38,6 +38,43 @@ def test_struct_layouts_match_header():
     assert C.sizeof(_lib.Camera) == 16 + 12 * 8
     assert C.sizeof(_lib.Sampling) == 40
     assert C.sizeof(_lib.Launch) == 16
+    assert C.sizeof(_lib.Progressive) == 24
+    assert C.sizeof(_lib.ProgressReport) == 32
+
+
+# ctypes mirror of each header struct
+_STRUCTS = {
+    "nc_field_desc": "FieldDesc", "nc_grid_params": "GridParams", "nc_optics": "Optics", "nc_camera": "Camera",
+    "nc_sampling": "Sampling", "nc_launch": "Launch", "nc_progressive": "Progressive",
+    "nc_progress_report": "ProgressReport",
+}
+
+
+def test_struct_offsets_match_compiled_header(tmp_path):
+    """Compile a C probe against the header and compare every field offset
+    and struct size with the ctypes mirrors of the binding."""
+    import json
+    import subprocess
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "nctrace.h"', 'int main(void) {', 'printf("{");']
+    first = True
+    for cname, pname in _STRUCTS.items():
+        py = getattr(_lib, pname)
+        for f in py._fields_:
+            lines.append('printf("%s\\"%s.%s\\": %%zu", offsetof(%s, %s));' % ("" if first else ",", cname, f[0],
+                                                                               cname, f[0]))
+            first = False
+        lines.append('printf(",\\"%s\\": %%zu", sizeof(%s));' % (cname, cname))
+    lines += ['printf("}\\n");', "return 0; }"]
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "probe"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = json.loads(subprocess.check_output([str(exe)]).decode())
+    for cname, pname in _STRUCTS.items():
+        py = getattr(_lib, pname)
+        assert got[cname] == C.sizeof(py), cname
+        for f in py._fields_:
+            assert got["%s.%s" % (cname, f[0])] == getattr(py, f[0]).offset, (cname, f[0])
 
 
 def test_null_context_errors():

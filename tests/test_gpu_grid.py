@@ -14,11 +14,11 @@ from paper_1902_01137_amd.inputs import FieldDesc, GridParams
 pytestmark = pytest.mark.gpu
 
 
-def _compare(desc, k, tau, kg=0.0, crit=0):
+def _compare(desc, k, tau, kg=0.0, crit=0, flat=3):
     c = ctx()
     kd = device_field(k)
-    g = api.build_grid(c, kd, desc, GridParams(tau, kg, crit))
-    og = oracle.OracleGrid(desc, k, tau_tilde=tau, k_gas=kg, criterion=crit)
+    g = api.build_grid(c, kd, desc, GridParams(tau, kg, crit, flat))
+    og = oracle.OracleGrid(desc, k, tau_tilde=tau, k_gas=kg, criterion=crit, flat_level=flat)
     assert g.L == og.L
     for l in range(1, g.L + 1):
         assert g.level_dims(l) == og.level_dims(l)
@@ -46,6 +46,16 @@ def test_ragged(shape):
     desc = FieldDesc(nx, ny, nz, 0, 0, 0, 0.05, 0.05, 0.05)
     for tau in (0.0, 0.3, 3.0):
         _compare(desc, k, tau, 0.02)
+
+
+@pytest.mark.parametrize("flat", [0, 1, 3, 9])
+def test_flat_supercells(flat):
+    desc, k = inputs.lognormal_blob()
+    g = _compare(desc, k, 0.0, 0.01, 2, flat)
+    assert (g.leaf_levels().cpu().numpy() == min(flat, g.L)).all()
+    rng = np.random.default_rng(flat)
+    k2 = (rng.random((5, 9, 12)) ** 8 * 60).astype(np.float32)
+    _compare(FieldDesc(12, 9, 5, 0, 0, 0, 0.05, 0.05, 0.05), k2, 0.0, 0.02, 2, flat)
 
 
 def test_cylinder_256():

@@ -1,0 +1,162 @@
+"""Guided rendering and the collection of its training vertices.
+
+The guided estimator (one-sample MIS between the network's vMF mixture and
+HG) must be unbiased for any network: its images are compared with the
+oracle's plain renderer.  The collection mode must trace exactly the plain
+paths, and its records must be well formed and consistent along each path.
+A guide trained on collected vertices must lower the variance per path."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from gpu_common import ctx, device_field
+from paper_1902_01137_amd import api, inputs
+from paper_1902_01137_amd.inputs import Optics, Sampling
+from stats import block, compare, mean_se
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(sc):
+    c = ctx()
+    kd = device_field(sc.kc)
+    g = api.build_grid(c, kd, sc.desc, sc.grid)
+    return c, kd, g
+
+
+@pytest.fixture(scope="module")
+def small_oracle():
+    sc = inputs.scene_small()
+    spp = 128
+    s, s2, _ = oracle.render(sc.desc, sc.kc, sc.grid.k_gas, sc.optics, sc.camera, spp, inputs.SEED_ORACLE_BASE + 31)
+    return mean_se(s, s2, spp)
+
+
+@pytest.mark.parametrize("frac", [0.0, 0.5, 0.9])
+def test_guided_unbiased_with_random_network(small_oracle, frac):
+    sc = inputs.scene_small()
+    c, kd, g = _setup(sc)
+    gd = api.Guide(c, seed=17)
+    spp = 256
+    cnt = api.new_counters("cuda")
+    s, s2 = api.render_guided(c, g, kd, sc.optics, sc.camera, Sampling(seed=4242, spp=spp, guide_frac=frac), gd,
+                              counters=cnt)
+    torch.cuda.synchronize()
+    gm, gse = mean_se(s.cpu().numpy().ravel(), s2.cpu().numpy().ravel(), spp)
+    om, ose = small_oracle
+    res = compare(*block(gm, gse, (64, 64)), *block(om, ose, (64, 64)))
+    assert res["ok"], (frac, res)
+    res_px = compare(gm, gse, om, ose)
+    assert res_px["ok"], (frac, res_px)
+    assert api.counters_dict(cnt)["paths"] == 64 * 64 * spp
+
+
+def test_guided_frac_zero_has_unit_weights():
+    """With c = 0 every MIS weight is p / p = 1: the estimator is the plain one
+    (other random numbers), so its per-pixel variance matches the plain render."""
+    sc = inputs.scene_small()
+    c, kd, g = _setup(sc)
+    gd = api.Guide(c, seed=3)
+    spp = 512
+    s, s2 = api.render_guided(c, g, kd, sc.optics, sc.camera, Sampling(seed=9, spp=spp, guide_frac=0.0), gd)
+    p, p2 = api.render(c, g, kd, sc.optics, sc.camera, Sampling(seed=10, spp=spp))
+    torch.cuda.synchronize()
+    vg = (s2.sum() / (s.numel() * spp)).item()
+    vp = (p2.sum() / (p.numel() * spp)).item()
+    assert vg == pytest.approx(vp, rel=0.05)
+
+
+def test_guided_rejects_bad_fraction():
+    sc = inputs.scene_small()
+    c, kd, g = _setup(sc)
+    gd = api.Guide(c, seed=3)
+    from paper_1902_01137_amd import _lib
+    with pytest.raises(_lib.NcError) as e:
+        api.render_guided(c, g, kd, sc.optics, sc.camera, Sampling(seed=1, spp=1, guide_frac=1.5), gd)
+    assert e.value.status == _lib.NC_ERR_INVALID_ARG
+
+
+def test_collect_traces_the_plain_paths_and_records_are_consistent():
+    sc = inputs.scene_small()
+    op = Optics(**{**vars(sc.optics), "ground_albedo": 0.0})   # no ground bounce between two volume vertices
+    c, kd, g = _setup(sc)
+    spp = 8
+    smp = Sampling(seed=77, spp=spp)
+    rec, n, s, s2 = api.collect_vertices(c, g, kd, op, sc.camera, smp, capacity=4 << 20)
+    p, p2 = api.render(c, g, kd, op, sc.camera, smp)
+    torch.cuda.synchronize()
+    assert torch.equal(s, p) and torch.equal(s2, p2)
+    assert 0 < n <= 4 << 20 and rec.shape == (n, 12)
+    r = rec.cpu().numpy().astype(np.float64)
+    slot = rec.cpu().numpy()[:, 11].view(np.uint32).astype(np.int64)
+    assert np.all(np.abs(r[:, 0:3]) <= 1.0 + 1e-5)
+    assert np.allclose(np.linalg.norm(r[:, 3:6], axis=1), 1.0, atol=1e-4)
+    assert np.allclose(np.linalg.norm(r[:, 7:10], axis=1), 1.0, atol=1e-4)
+    assert np.all(r[:, 6] > 0.0) and np.all(r[:, 10] >= 0.0)
+    assert np.all(slot < 64 * 64 * spp)
+    # records of one path come from one lane in order: the weight (radiance
+    # still to come) never grows and each vertex is entered along the
+    # direction the previous one left by
+    order = np.lexsort((np.arange(n), slot))
+    rs, ss = r[order], slot[order]
+    same = ss[1:] == ss[:-1]
+    assert same.any()
+    assert np.all(rs[1:, 10][same] <= rs[:-1, 10][same] + 1e-6 * (1 + rs[:-1, 10][same]))
+    assert np.allclose(rs[1:, 3:6][same], rs[:-1, 7:10][same], atol=1e-6)
+    # the first vertex of every path collects everything after its own sun estimate:
+    # its weight cannot exceed the path's radiance
+    first = np.concatenate([[True], ~same])
+    Lpath = p.cpu().numpy().ravel()   # per pixel sums; each path is at most its pixel's sum
+    pix = ss[first] // spp
+    assert np.all(rs[first, 10] <= Lpath[pix] + 1e-5)
+
+
+def test_collect_capacity_overflow_drops_records():
+    sc = inputs.scene_small()
+    c, kd, g = _setup(sc)
+    rec, n, _, _ = api.collect_vertices(c, g, kd, sc.optics, sc.camera, Sampling(seed=5, spp=2), capacity=100)
+    torch.cuda.synchronize()
+    assert n > 100 and rec.shape == (100, 12)
+    assert np.all(np.isfinite(rec.cpu().numpy()[:, :11]))
+
+
+def _train(gd, rec, steps, batch=8192, lr=3e-3):
+    t = rec.contiguous()
+    n = t.shape[0]
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1)
+    for it in range(steps):
+        idx = torch.randint(0, n, (batch,), device="cuda", generator=gen)
+        gd.train_step(t[idx], lr * (0.2 if it > 0.75 * steps else 1.0))
+
+
+def test_trained_guide_lowers_variance():
+    """Camera under the blob looking up, sun at 60 degrees: paths that leave
+    the cloud sideways towards the lit flank carry the light.  After training
+    on the plain tracer's vertices, the guided images keep the plain mean and
+    their summed per-pixel variance drops."""
+    sc = inputs.scene_small()
+    (xa, xb), (ya, yb), (za, zb) = sc.desc.box
+    cam = inputs.Camera(type=1, pos=((xa + xb) / 2, (ya + yb) / 2, za - 0.2),
+                        target=((xa + xb) / 2, (ya + yb) / 2, zb), up=(0.0, 1.0, 0.0),
+                        ortho_w=xb - xa, ortho_h=yb - ya, width=64, height=64)
+    op = Optics(**{**vars(sc.optics), "sun_zenith_deg": 60.0, "ground_albedo": 0.0})
+    c, kd, g = _setup(sc)
+    rec, n, _, _ = api.collect_vertices(c, g, kd, op, cam, Sampling(seed=101, spp=64), capacity=8 << 20)
+    keep = rec[rec[:, 10] > 0]
+    gd = api.Guide(c, seed=2)
+    _train(gd, keep if keep.shape[0] > 1000 else rec, 600)
+    spp = 256
+    gs, gs2 = api.render_guided(c, g, kd, op, cam, Sampling(seed=202, spp=spp, guide_frac=0.5), gd)
+    ps, ps2 = api.render(c, g, kd, op, cam, Sampling(seed=303, spp=spp))
+    torch.cuda.synchronize()
+    gm, gse = mean_se(gs.cpu().numpy().ravel(), gs2.cpu().numpy().ravel(), spp)
+    pm, pse = mean_se(ps.cpu().numpy().ravel(), ps2.cpu().numpy().ravel(), spp)
+    res = compare(*block(gm, gse, (64, 64)), *block(pm, pse, (64, 64)))
+    assert res["ok"], res
+    ratio = float((gse ** 2).sum() / (pse ** 2).sum())
+    print("variance ratio guided/plain = %.3f" % ratio)
+    assert ratio < 0.9, ratio

@@ -154,6 +154,21 @@ def test_small_cloud_majorant_and_grid_invariance():
         assert res["ok"], (tt, m, res)
 
 
+def test_small_cloud_flat_supercell_grid():
+    """The flat grid of 8^3-cell supercells is a valid majorant: same image."""
+    sc = inputs.scene_small()
+    spp = 128
+    rm, rse = mean_se(*_render(sc.desc, sc.kc, 0.0, 1.0, sc.optics, sc.camera, spp, seed=5), spp)
+    c = ctx()
+    kd = device_field(sc.kc)
+    g = api.build_grid(c, kd, sc.desc, GridParams(0.0, 0.0, 2, 3))
+    s, s2 = api.render(c, g, kd, sc.optics, sc.camera, Sampling(seed=61, spp=spp))
+    torch.cuda.synchronize()
+    gm, gse = mean_se(s.cpu().numpy().ravel(), s2.cpu().numpy().ravel(), spp)
+    res = compare(*block(gm, gse, (64, 64)), *block(rm, rse, (64, 64)))
+    assert res["ok"], res
+
+
 def test_resume_with_sample_offset():
     sc = inputs.scene_small()
     c = ctx()
@@ -165,3 +180,54 @@ def test_resume_with_sample_offset():
     torch.cuda.synchronize()
     assert torch.allclose(s_full, s_a, rtol=1e-12, atol=1e-12)
     assert torch.allclose(q_full, q_a, rtol=1e-12, atol=1e-12)
+
+
+def _sensor(desc, n, z=0.0):
+    (xa, xb), (ya, yb), _ = desc.box
+    c = ((xa + xb) / 2, (ya + yb) / 2, z)
+    return Camera(type=2, pos=c, target=(c[0], c[1], z + 1.0), up=(0.0, 1.0, 0.0), ortho_w=xb - xa, ortho_h=yb - ya,
+                  width=n, height=n)
+
+
+def test_sensor_pure_absorber_slab():
+    """Irradiance sensor under an absorbing slab: S times Bernoulli(exp(-tau/mu0))."""
+    tau, H, th0 = 0.8, 0.4, 40.0
+    desc, k = inputs.slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.5, sun_zenith_deg=th0, sun_azimuth_deg=10.0, sun_irradiance=2.0)
+    cam = Camera(type=2, pos=(0.0, 0.0, 0.0), ortho_w=0.1, ortho_h=0.1, width=4, height=4)
+    spp = 4096
+    s, s2 = _render(desc, k, 0.0, 1.0, op, cam, spp, seed=71)
+    p = math.exp(-tau / math.cos(math.radians(th0)))
+    se = 2.0 * math.sqrt(p * (1 - p) / spp)
+    assert np.all(np.abs(s / spp - 2.0 * p) < 4.5 * se)
+    assert np.allclose(s2, 2.0 * s)        # every path is 0 or S
+
+
+def test_sensor_image_vs_oracle():
+    sc = inputs.scene_small()
+    cam = _sensor(sc.desc, 8)
+    spp_g, spp_o = 16384, 4096
+    s, s2 = _render(sc.desc, sc.kc, sc.grid.k_gas, 1.0, sc.optics, cam, spp_g, seed=72)
+    os_, os2, _ = oracle.render(sc.desc, sc.kc, sc.grid.k_gas, sc.optics, cam, spp_o, inputs.SEED_ORACLE_BASE + 72)
+    res = compare(*mean_se(s, s2, spp_g), *mean_se(os_, os2, spp_o))
+    assert res["ok"], res
+
+
+def test_sensor_reciprocity_with_forward_flux():
+    """The cylinder cumulus (sun at zenith, black ground): backward sensor
+    paths and forward photons (nc_flux) give the same ground transmissivity."""
+    sc = inputs.scene_cylinder()
+    c = ctx()
+    kd = device_field(sc.kc)
+    g = api.build_grid(c, kd, sc.desc, sc.grid)
+    n, N, spp = 16, 1 << 23, 8192
+    tally, glob = api.flux(c, g, kd, sc.optics, (n, n), N, Sampling(seed=73, spp=1))
+    s, s2 = api.render(c, g, kd, sc.optics, _sensor(sc.desc, n), Sampling(seed=74, spp=spp))
+    torch.cuda.synchronize()
+    t = tally.cpu().numpy()
+    Tf = t[0] * n * n / N
+    sef = np.sqrt(np.maximum(t[1] * (n * n) ** 2 / N - Tf ** 2, 0) / (N - 1))
+    mb, seb = mean_se(s.cpu().numpy().ravel(), s2.cpu().numpy().ravel(), spp)
+    res = compare(mb, seb, Tf.ravel(), sef.ravel())
+    assert res["ok"], res
+    assert 0.05 < Tf.mean() < 1.0

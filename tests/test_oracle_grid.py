@@ -123,3 +123,24 @@ def test_single_cell_field(orc):
     k = np.full((1, 1, 1), 3.0, np.float32)
     g = grid(orc, FieldDesc(1, 1, 1, 0, 0, 0, 1, 1, 1), k, 10.0)
     assert g.L == 0 and (g.leaf_levels() == 0).all()
+
+
+@pytest.mark.parametrize("shape,flat", [((16, 16, 16), 3), ((7, 3, 5), 1), ((5, 9, 12), 8), ((1, 1, 6), 0)])
+def test_flat_supercell_grid(orc, shape, flat):
+    """Criterion 2: every node of level <= flat_level is merged whatever the
+    field, so every cell's voxel is its level-min(flat_level, L) ancestor,
+    and the stored extrema are still the exact block extrema."""
+    rng = np.random.default_rng(sum(shape) + flat)
+    k = (rng.random(shape) ** 8 * 60).astype(np.float32)
+    nz, ny, nx = shape
+    desc = FieldDesc(nx, ny, nz, 0, 0, 0, 0.05, 0.05, 0.05)
+    g = orc.OracleGrid(desc, k, tau_tilde=0.0, criterion=2, flat_level=flat)
+    assert (g.leaf_levels() == min(flat, g.L)).all()
+    for l in range(1, g.L + 1):
+        kmin, kmax, mg = g.level(l)
+        assert (mg == (l <= flat)).all()
+        s = 1 << l
+        dz_, dy_, dx_ = kmin.shape
+        for m, j, i in [(0, 0, 0), (dz_ - 1, dy_ - 1, dx_ - 1), (dz_ // 2, dy_ // 2, dx_ // 2)]:
+            blk = k[m * s:(m + 1) * s, j * s:(j + 1) * s, i * s:(i + 1) * s]
+            assert kmin[m, j, i] == blk.min() and kmax[m, j, i] == blk.max()

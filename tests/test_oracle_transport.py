@@ -69,6 +69,10 @@ def test_majorant_invariance_blob(orc):
     gm, _, _ = orc.transmittance(f, rays, n, seed=9, mode=1, majorant_scale=1.0)
     se = np.sqrt(np.maximum(exact * (1 - exact), 1e-4) / n)
     assert np.abs((gm - exact) / se).max() < 4.5
+    # the flat grid of 8^3-cell supercells is a valid majorant too
+    g = orc.OracleGrid(desc, k, criterion=2, flat_level=3)
+    fm, _, _ = orc.transmittance(g.field, rays, n, seed=11, mode=2, grid=g)
+    assert np.abs((fm - exact) / se).max() < 4.5
 
 
 def test_null_counts_grow_with_majorant(orc):
@@ -179,3 +183,79 @@ def test_camera_centre_ray(orc):
     v = np.array([1.0, -(-2.0 * t), t])          # right = f x up = -y; left of centre is +y
     v /= np.linalg.norm(v)
     assert np.allclose(r[3:], v, atol=1e-14)
+
+
+# ---------------------------------------------------------------- irradiance sensor (camera type 2)
+
+def _sensor(desc, n, z=0.0):
+    (xa, xb), (ya, yb), _ = desc.box
+    c = ((xa + xb) / 2, (ya + yb) / 2, z)
+    return Camera(type=2, pos=c, target=(c[0], c[1], z + 1.0), up=(0.0, 1.0, 0.0), ortho_w=xb - xa, ortho_h=yb - ya,
+                  width=n, height=n)
+
+
+def test_sensor_pure_absorber_is_exact(orc):
+    """No scattering: every path reports S exp(-tau / mu_sun), whatever the ground."""
+    tau, H, th0 = 0.8, 0.4, 40.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.5, sun_zenith_deg=th0, sun_azimuth_deg=10.0, sun_irradiance=2.0)
+    cam = Camera(type=2, pos=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                 width=2, height=2)
+    spp = 500
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=8)
+    exact = 2.0 * math.exp(-tau / math.cos(math.radians(th0)))
+    assert np.allclose(s / spp, exact, rtol=1e-12)
+    assert np.allclose(s2 / spp, exact ** 2, rtol=1e-12)
+
+
+def test_sensor_single_scattering_slab(orc):
+    """Direct plus single-scattered transmissivity of a slab seen from below:
+    T = exp(-tau/mu0) + (1/mu0) int L1(mu, phi) mu dmu dphi with
+    L1 = ssa p(cos Theta) mu0/(mu0 - mu) (exp(-tau/mu0) - exp(-tau/mu))."""
+    tau, H, ssa, g, th0, phi0 = 1.1, 0.5, 0.9, 0.6, 35.0, 60.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=ssa, g=g, ground_albedo=0.0, sun_zenith_deg=th0, sun_azimuth_deg=phi0, max_scatter=1)
+    cam = Camera(type=2, pos=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                 width=2, height=2)
+    spp = 40000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=9)
+    mu0 = math.cos(math.radians(th0))
+    sv = np.array([math.sin(math.radians(th0)) * math.cos(math.radians(phi0)),
+                   math.sin(math.radians(th0)) * math.sin(math.radians(phi0)), mu0])
+
+    def L1(mu, phi):
+        w = np.array([math.sqrt(1 - mu * mu) * math.cos(phi), math.sqrt(1 - mu * mu) * math.sin(phi), mu])
+        c = float(w @ sv)
+        p = (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * c) ** 1.5)
+        if abs(mu - mu0) < 1e-9:
+            f = tau / mu0 * math.exp(-tau / mu0)
+        else:
+            f = mu0 / (mu0 - mu) * (math.exp(-tau / mu0) - math.exp(-tau / mu))
+        return ssa * p * f
+
+    T1 = integrate.dblquad(lambda mu, phi: L1(mu, phi) * mu, 0.0, 2 * math.pi, 1e-9, 1.0, epsabs=1e-10)[0] / mu0
+    exact = math.exp(-tau / mu0) + T1
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / (spp - 1))
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact)
+
+
+def test_sensor_reciprocity_with_forward_photons(orc):
+    """Backward sensor paths and forward photons from the top face estimate
+    the same ground transmissivity per pixel (sun at zenith, black ground, so
+    the sun reaches the ground only through the top face)."""
+    desc, k = lognormal_blob()
+    op = Optics(ssa=0.999, g=0.85, ground_albedo=0.0, sun_zenith_deg=0.0)
+    n, N, spp = 4, 1000000, 40000
+    tally, glob = orc.flux(desc, k, 0.01, op, (n, n), N, seed=21)
+    assert glob.sum() == N
+    Tf = tally[0] * n * n / N
+    sef = np.sqrt(np.maximum(tally[1] * (n * n) ** 2 / N - Tf ** 2, 0) / (N - 1))
+    s, s2, _ = orc.render(desc, k, 0.01, op, _sensor(desc, n), spp, seed=22)
+    Tb = (s / spp).reshape(n, n)
+    seb = np.sqrt(np.maximum(s2 / spp - (s / spp) ** 2, 0) / (spp - 1)).reshape(n, n)
+    z = (Tb - Tf) / np.sqrt(sef ** 2 + seb ** 2)
+    assert np.abs(z).max() < 4.0, z
+    zg = (Tb.mean() - Tf.mean()) / math.sqrt((sef ** 2).sum() + (seb ** 2).sum()) * n * n
+    assert abs(zg) < 4.0, zg
