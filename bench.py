@@ -22,7 +22,7 @@ sys.path.insert(0, ROOT)
 METRIC = "paths/s + time to 1% rel. std err radiance, plain vs guided, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 GRANULE = 64  # bytes moved by one random 4- or 8-byte read from HBM
-PHASES = ("cross", "collide", "event", "ray", "sample")
+PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
 
 
 def kernel_sources_digest():

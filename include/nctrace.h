@@ -118,7 +118,11 @@ typedef struct {
 /* Sampling: seed keys the random streams; sample s of pixel p of job j uses
  * the Philox counter (p, sample_offset + s, draw, stream + j), so a run with
  * sample_offset = n continues one that took n samples per pixel, and runs
- * with different `stream` values are independent. */
+ * with different `stream` values are independent.  guide_frac and
+ * guide_max_order concern nc_render_guided only: the probability of drawing
+ * from the guide at a scattering, and the last scattering order that is
+ * guided (0: every order; the weights of guided events multiply along a
+ * path, so guiding only the first orders bounds their spread). */
 typedef struct {
     uint64_t seed;
     uint64_t sample_offset;
@@ -126,7 +130,7 @@ typedef struct {
     int32_t flags;
     double guide_frac;
     uint32_t stream;
-    uint32_t pad_;
+    uint32_t guide_max_order;
 } nc_sampling;
 
 /* Per-call event counters (summed over all paths of the call). */
@@ -141,9 +145,10 @@ typedef struct {
     uint64_t node_reads;     /* grid node reads from global memory */
     uint64_t nee_rays;       /* sun rays traced */
     uint64_t truncated;      /* paths stopped at max_segments */
-    uint64_t sched[16];      /* renderer scheduling, per phase (voxel crossing, collision, event, ray
-                                start, sample): [0..4] wave trips, [5..9] active lanes summed over the
-                                trips, [10..14] wave wall-clock ticks spent in the phase */
+    uint64_t sched[24];      /* renderer scheduling, per phase (voxel crossing, collision, event, ray
+                                start, sample, guide network): [0..5] wave trips, [6..11] active lanes
+                                summed over the trips, [12..17] wave wall-clock ticks spent in the
+                                phase, [18..23] unused */
 } nc_counters;
 
 /* Library ABI version (NC_ABI_VERSION). */
@@ -301,6 +306,17 @@ nc_status nc_guide_gradient(nc_ctx *ctx, nc_guide *guide, const float *d_records
 nc_status nc_render_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                            const nc_camera *camera, const nc_sampling *sampling, const nc_guide *guide,
                            double *d_sum, double *d_sumsq, nc_counters *d_counters);
+
+/* The guided scattering step of nc_render_guided on n given vertices (for
+ * testing and inspection): the network on the matrix cores, then with
+ * probability guide_frac a direction from the vMF mixture q, else from HG(g)
+ * about the incoming direction.  d_in: n rows of 8 floats (the 7 network
+ * inputs, of which 3..5 are the incoming direction; one unused); d_u: n rows
+ * of 4 uniforms in [0,1) (branch, lobe, cosine, azimuth); d_out: n rows of 8
+ * floats: new direction (3), weight factor p / (c q + (1 - c) p), q and p at
+ * the new direction, 2 zeros.  All device float arrays. */
+nc_status nc_guide_sample(nc_ctx *ctx, const nc_guide *guide, const float *d_in, const float *d_u, int32_t n,
+                          float guide_frac, float g, float *d_out);
 
 /* Progressive rendering to a target relative standard error.  Rounds of
  * nc_render (guide NULL) or nc_render_guided add samples with consecutive

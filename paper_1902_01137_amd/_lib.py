@@ -48,7 +48,7 @@ class Camera(C.Structure):
 
 class Sampling(C.Structure):
     _fields_ = [("seed", C.c_uint64), ("sample_offset", C.c_uint64), ("spp", C.c_int32), ("flags", C.c_int32),
-                ("guide_frac", C.c_double), ("stream", C.c_uint32), ("pad_", C.c_uint32)]
+                ("guide_frac", C.c_double), ("stream", C.c_uint32), ("guide_max_order", C.c_uint32)]
 
 
 class Launch(C.Structure):
@@ -56,10 +56,11 @@ class Launch(C.Structure):
                 ("lds_levels", C.c_int32)]
 
 
+PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
 COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visits", "gathers", "node_reads",
                  "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
-                                              for b in ("cross", "collide", "event", "ray", "sample")] + ["sched_pad"]
-N_COUNTER_WORDS = 26
+                                              for b in PHASES] + ["sched_pad%d" % i for i in range(6)]
+N_COUNTER_WORDS = 34
 GUIDE_PARAMS = 11432
 GUIDE_RECORD = 12
 
@@ -95,6 +96,7 @@ _SIGS = [
                                      _P, _P]),
     ("nc_render_progressive", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P,
                                           C.POINTER(Progressive), _P, _P, _P, C.POINTER(ProgressReport)]),
+    ("nc_guide_sample", C.c_int32, [_P, _P, _P, _P, C.c_int32, C.c_float, C.c_float, _P]),
     ("nc_gather_rate", C.c_int32, [_P, _P, C.c_uint64, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double)]),
     ("nc_collect_vertices", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P,
                                         C.c_uint64, _P, _P, _P, _P, _P]),

@@ -43,7 +43,7 @@ def _camera(c: Camera):
 
 
 def _sampling(s: Sampling):
-    return _lib.Sampling(s.seed, s.sample_offset, s.spp, s.flags, s.guide_frac, s.stream, 0)
+    return _lib.Sampling(s.seed, s.sample_offset, s.spp, s.flags, s.guide_frac, s.stream, s.guide_max_order)
 
 
 def counters_dict(t: torch.Tensor):
@@ -399,6 +399,16 @@ class Guide:
         _check(_lib.load().nc_guide_train_step(self.ctx.handle, self.handle, _ptr(r), r.shape[0], float(lr),
                                                _ptr(loss)), self.ctx.handle)
         return loss
+
+    def sample(self, inputs: torch.Tensor, u: torch.Tensor, guide_frac: float, g: float) -> torch.Tensor:
+        """The renderer's guided scattering step (nc_guide_sample): inputs (n, 8)
+        float32, u (n, 4) -> (n, 8) [direction(3), weight factor, q, p, 0, 0]."""
+        x = inputs.contiguous()
+        uu = u.contiguous()
+        out = torch.empty((x.shape[0], 8), dtype=torch.float32, device=x.device)
+        _check(_lib.load().nc_guide_sample(self.ctx.handle, self.handle, _ptr(x), _ptr(uu), x.shape[0],
+                                           float(guide_frac), float(g), _ptr(out)), self.ctx.handle)
+        return out
 
     def gradient(self, records: torch.Tensor):
         r = records.contiguous()

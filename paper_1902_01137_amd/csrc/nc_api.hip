@@ -531,6 +531,20 @@ nc_status nc_render_progressive(nc_ctx *ctx, const nc_grid *g, const float *d_kc
     return NC_OK;
 }
 
+nc_status nc_guide_sample(nc_ctx *ctx, const nc_guide *guide, const float *d_in, const float *d_u, int32_t n,
+                          float guide_frac, float g, float *d_out)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!guide || !d_in || !d_u || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    if (n < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative count");
+    if (!(guide_frac >= 0.0f && guide_frac <= 1.0f)) return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
+    if (!(g > -1.0f && g < 1.0f)) return fail(ctx, NC_ERR_RANGE, "g must lie in (-1, 1)");
+    if (n == 0) return NC_OK;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e = nc::launch_guide_sample(ctx, guide, d_in, d_u, guide_frac, g, n, d_out);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide sample");
+}
+
 nc_status nc_gather_rate(nc_ctx *ctx, const float *d_buf, uint64_t n_words, int32_t threads, int32_t loads,
                          float *d_out, double *loads_per_s)
 {

@@ -114,7 +114,7 @@ struct Shape {
 };
 
 GridView grid_view(const nc_grid *g, const float *d_kc);
-Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve = 0);
+Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve = 0, int waves_default = 0);
 
 hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad);
 hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int level, float *kmin, float *kmax, uint8_t *mg);
@@ -138,6 +138,8 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
                          nc_counters *counters, JobView *jobs_dev, const nc_guide *guide = nullptr,
                          const CollectView *collect = nullptr);
 hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv);
+hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const float *in, const float *u, float c,
+                               float g, int n, float *out);
 hipError_t launch_gather_rate(const nc_ctx *ctx, const float *buf, uint32_t mask, int threads, int loads,
                               uint32_t seed, float *out);
 // Block-mean error statistics of an image estimate (synchronises the stream):

@@ -399,6 +399,7 @@ struct RenderArgs {
     const RenderRare *rare;
     GuideWeights gw;            // guided mode: the network
     float guide_frac;           // guided mode: probability of sampling the guide
+    int guide_max_order;        // guided mode: last guided scattering order (0: all)
     CollectView col;            // collection mode: where vertices go
     int col_spp;                // collection mode: samples per pixel (path slot = pix * spp + sample)
     int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
@@ -414,7 +415,7 @@ struct RenderArgs {
 // of diverging inside every traversal step.
 enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhGuide = 5, kPhIdle = 6 };
 enum RenderMode { kPlain = 0, kGuided = 1, kCollect = 2 };
-constexpr int kGuideScratchPerWave = 2 * 16 * 64 * 2 + 16 * 48 * 4;   // two bf16 activation tiles + fp32 outputs
+static_assert(kPhGuide == 5 && kPhIdle == 6, "six running phases, one counter slot each");
 
 // After the optical thickness tau has been drawn or carried: a tentative
 // collision inside the current voxel, or a move to the next voxel.
@@ -426,8 +427,7 @@ __device__ inline int voxel_phase(const Ray &r, float tau)
 // block-level event counters in LDS (same order as nc_counters)
 enum BlockCounter {
     kCPaths = 0, kCSegments, kCTentative, kCNulls, kCReals, kCLeaf, kCGathers, kCReads, kCNee, kCTrunc,
-    kCTrips0, kCTrips1, kCTrips2, kCTrips3, kCTrips4, kCLanes0, kCLanes1, kCLanes2, kCLanes3, kCLanes4,
-    kCCycles0, kCCycles1, kCCycles2, kCCycles3, kCCycles4, kNumBlockCounters
+    kCTrips0, kCLanes0 = kCTrips0 + 6, kCCycles0 = kCLanes0 + 6, kNumBlockCounters = kCCycles0 + 6
 };
 
 __device__ inline void wave_count(unsigned long long *s_cnt, int k, bool pred)
@@ -479,16 +479,18 @@ __device__ inline void wave_sync()
 
 // Guided scattering (one-sample MIS): with probability c draw the new
 // direction from the network's vMF mixture, otherwise from HG; the path
-// weight is multiplied by p_HG / (c q + (1 - c) p_HG).  z: the 40 outputs.
-__device__ inline void guided_turn(const float *z, float c, float g, float u_sel, float u_lobe, float u1, float u2,
-                                   float pd[3], float &beta)
+// weight is multiplied by p_HG / (c q + (1 - c) p_HG).  zb: the 40 outputs
+// (bf16; the same rounded values define both the sampling and the density).
+__device__ inline void guided_turn(const short *zb, float c, float g, float u_sel, float u_lobe, float u1, float u2,
+                                   float pd[3], float &beta, float &q_out, float &p_out)
 {
-    float amax = z[0];
+    auto z = [zb](int i) { return from_bf16(zb[i]); };
+    float amax = z(0);
 #pragma unroll
-    for (int j = 1; j < kGuideLobes; ++j) amax = fmaxf(amax, z[5 * j]);
+    for (int j = 1; j < kGuideLobes; ++j) amax = fmaxf(amax, z(5 * j));
     float psum = 0.0f;
 #pragma unroll
-    for (int j = 0; j < kGuideLobes; ++j) psum += __expf(z[5 * j] - amax);
+    for (int j = 0; j < kGuideLobes; ++j) psum += __expf(z(5 * j) - amax);
     float nd[3] = {pd[0], pd[1], pd[2]};
     if (u_sel < c) {
         // lobe by its weight, then the stable vMF cosine inversion (Jakob 2012)
@@ -497,15 +499,15 @@ __device__ inline void guided_turn(const float *z, float c, float g, float u_sel
         const float target = u_lobe * psum;
 #pragma unroll
         for (int j = 0; j < kGuideLobes; ++j) {
-            cum += __expf(z[5 * j] - amax);
+            cum += __expf(z(5 * j) - amax);
             if (target < cum && pick == kGuideLobes - 1 && j < kGuideLobes - 1) pick = j;
         }
-        float m[3] = {z[5 * pick + 1], z[5 * pick + 2], z[5 * pick + 3]};
+        float m[3] = {z(5 * pick + 1), z(5 * pick + 2), z(5 * pick + 3)};
         const float inv = rsqrtf(fmaxf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2], 1e-24f));
         m[0] *= inv;
         m[1] *= inv;
         m[2] *= inv;
-        const float kap = __expf(fminf(fmaxf(z[5 * pick + 4], kLogKappaMin), kLogKappaMax));
+        const float kap = __expf(fminf(fmaxf(z(5 * pick + 4), kLogKappaMin), kLogKappaMax));
         const float t = fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) / kap));
         nd[0] = m[0];
         nd[1] = m[1];
@@ -518,18 +520,135 @@ __device__ inline void guided_turn(const float *z, float c, float g, float u_sel
     float q = 0.0f;
 #pragma unroll
     for (int j = 0; j < kGuideLobes; ++j) {
-        const float m0 = z[5 * j + 1], m1 = z[5 * j + 2], m2 = z[5 * j + 3];
+        const float m0 = z(5 * j + 1), m1 = z(5 * j + 2), m2 = z(5 * j + 3);
         const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
         const float cw = (m0 * nd[0] + m1 * nd[1] + m2 * nd[2]) * inv;
-        const float kap = __expf(fminf(fmaxf(z[5 * j + 4], kLogKappaMin), kLogKappaMax));
+        const float kap = __expf(fminf(fmaxf(z(5 * j + 4), kLogKappaMin), kLogKappaMax));
         const float norm = kap / (2.0f * kPi * (-expm1f(-2.0f * kap)));
-        q += __expf(z[5 * j] - amax) / psum * norm * __expf(kap * (cw - 1.0f));
+        q += __expf(z(5 * j) - amax) / psum * norm * __expf(kap * (cw - 1.0f));
     }
     const float php = hg_phase(g, pd[0] * nd[0] + pd[1] * nd[1] + pd[2] * nd[2]);
     beta *= php / (c * q + (1.0f - c) * php);
+    q_out = q;
+    p_out = php;
     pd[0] = nd[0];
     pd[1] = nd[1];
     pd[2] = nd[2];
+}
+
+// The network in LDS.  Layer l's weights W_l [out][in] are staged once per
+// workgroup with rows padded by 4 bf16 (row strides of 20 and 68 elements
+// spread a fragment read over the banks), then the biases (fp32).  A wave's
+// tile is two [16][68] bf16 activation buffers; the 40 outputs end in the
+// first one (bf16, row stride 68).
+constexpr int kActStride = 68;
+constexpr int kWOff[5] = {0, 64 * 20, 64 * 20 + 64 * 68, 64 * 20 + 2 * 64 * 68, 64 * 20 + 2 * 64 * 68 + 48 * 68};
+constexpr int kBOff[4] = {0, 64, 128, 192};
+constexpr int kGuideWeightBytes = kWOff[4] * 2 + 240 * 4;                   // 27456
+constexpr int kGuideScratchPerWave = 2 * 16 * kActStride * 2;               // 4352
+
+__device__ inline int w_stride(int l) { return l == 0 ? 20 : 68; }
+
+// Copy the packed network (W_pad [out_pad][in_pad] bf16 and fp32 biases per
+// layer) into the padded LDS layout; all threads of the block take part.
+__device__ inline void stage_guide(const GuideWeights &W, short *wl, float *bl)
+{
+    for (int l = 0; l < kGuideLayers; ++l) {
+        const int kin = l == 0 ? 16 : 64, nout = l == kGuideLayers - 1 ? 48 : 64, st = w_stride(l);
+        for (int i = threadIdx.x; i < nout * kin; i += blockDim.x) {
+            const int o = i / kin, k = i - o * kin;
+            wl[kWOff[l] + o * st + k] = W.w[l][i];
+        }
+        for (int i = threadIdx.x; i < nout; i += blockDim.x) bl[kBOff[l] + i] = W.b[l][i];
+    }
+}
+
+// The network on one tile of 16 vertices held by one wave: act0 rows hold
+// the bf16 inputs (columns 0..15); afterwards act0 rows hold the 40 outputs
+// (bf16).  D = A B on the matrix cores: lane l supplies A[l % 16][4 (l / 16) + i]
+// and B[4 (l / 16) + i][l % 16] and receives D[4 (l / 16) + i][l % 16].
+__device__ inline void guide_tile_forward(const short *wl, const float *bl, short *act0, short *act1, int lane)
+{
+    const int mrow = lane & 15, kq = lane >> 4;
+    for (int layer = 0; layer < kGuideLayers; ++layer) {
+        const int kin = layer == 0 ? 16 : 64, nout = layer == kGuideLayers - 1 ? 48 : 64, st = w_stride(layer);
+        const short *src = (layer & 1) ? act1 : act0;
+        short *dst = (layer & 1) ? act0 : act1;
+        const short *wrow = wl + kWOff[layer];
+        for (int nt = 0; nt < nout / 16; ++nt) {
+            f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int kt = 0; kt < kin / 16; ++kt) {
+                const int kk = kt * 16 + 4 * kq;
+                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(src + mrow * kActStride + kk);
+                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(wrow + (nt * 16 + mrow) * st + kk);
+                c = mfma16(a, b, c);
+            }
+            const int col = nt * 16 + mrow;
+            const float bias = bl[kBOff[layer] + col];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int m = 4 * kq + i;
+                const float v = c[i] + bias;
+                dst[m * kActStride + col] = to_bf16(layer < kGuideLayers - 1 ? fmaxf(v, 0.0f) : v);
+            }
+        }
+        wave_sync();
+    }
+}
+
+// The renderer's guided scattering step on given vertices (one wave per 64):
+// in rows of 8 floats (the 7 network inputs; the incoming direction is
+// inputs 3..5), u rows of 4 uniforms, out rows of 8 floats (new direction,
+// weight factor, q, p_HG, 0, 0).
+__global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const float *__restrict__ in,
+                                                          const float *__restrict__ u, float c, float g, int n,
+                                                          float *__restrict__ out)
+{
+    __shared__ __align__(16) short wl[kWOff[4]];
+    __shared__ float bl[240];
+    __shared__ __align__(16) short act[2 * 16 * kActStride];
+    stage_guide(W, wl, bl);
+    __syncthreads();
+    short *act0 = act, *act1 = act + 16 * kActStride;
+    const int lane = threadIdx.x, mrow = lane & 15, kq = lane >> 4;
+    for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
+        const int r = base + lane;
+        const bool active = r < n;
+        for (int t = 0; t < 4; ++t) {
+            if (kq == t) {
+#pragma unroll
+                for (int k = 0; k < 16; ++k)
+                    act0[mrow * kActStride + k] = to_bf16(active && k < kGuideIn ? in[(size_t)r * 8 + k] : 0.0f);
+            }
+            wave_sync();
+            guide_tile_forward(wl, bl, act0, act1, lane);
+            if (kq == t && active) {
+                float pd[3] = {in[(size_t)r * 8 + 3], in[(size_t)r * 8 + 4], in[(size_t)r * 8 + 5]};
+                float beta = 1.0f, q = 0.0f, p = 0.0f;
+                const float *uu = u + (size_t)r * 4;
+                guided_turn(act0 + mrow * kActStride, c, g, uu[0], uu[1], uu[2], uu[3], pd, beta, q, p);
+                float *o = out + (size_t)r * 8;
+                o[0] = pd[0];
+                o[1] = pd[1];
+                o[2] = pd[2];
+                o[3] = beta;
+                o[4] = q;
+                o[5] = p;
+                o[6] = 0.0f;
+                o[7] = 0.0f;
+            }
+            wave_sync();
+        }
+    }
+}
+
+hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const float *in, const float *u, float c,
+                               float g, int n, float *out)
+{
+    const int blocks = std::max(1, std::min((n + 63) / 64, 4096));
+    hipLaunchKernelGGL(guide_sample_kernel, dim3(blocks), dim3(64), 0, ctx->stream, guide_weights(gd), in, u, c, g, n,
+                       out);
+    return hipGetLastError();
 }
 
 template <int kWavesPerEU, int kMode>
@@ -539,7 +658,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     __shared__ unsigned long long s_cnt[kNumBlockCounters];
     for (int i = threadIdx.x; i < kNumBlockCounters; i += blockDim.x) s_cnt[i] = 0ull;
-    stage_levels(A.g, A.lds_first, A.lds_nodes, s_nodes, s_off);
+    if (kMode == kGuided) {
+        char *gb = reinterpret_cast<char *>(s_nodes) + A.guide_lds;
+        stage_guide(A.gw, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
+    }
+    stage_levels(A.g, A.lds_first, A.lds_nodes, s_nodes, s_off);   // ends with a block barrier
     const GridView &g = A.g;
     const NodeSrc ns{g.nodes, s_nodes, s_off, A.lds_first, s_off[A.lds_first <= g.L ? A.lds_first : 0], g.n[0],
                      g.n[1]};
@@ -588,7 +711,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         if (n_ray >= best) { run = kPhRay; best = n_ray; }
         if (n_sample > best) { run = kPhSample; best = n_sample; }
         if (kMode == kGuided && n_guide > best) { run = kPhGuide; best = n_guide; }
-        if (lane == 0 && run < 5) {
+        if (lane == 0) {
             atomicAdd(s_cnt + kCTrips0 + run, 1ull);
             atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
         }
@@ -716,7 +839,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         phase = kPhSample;
                     } else if (rng.take() >= p_cont) {
                         phase = kPhSample;       // absorbed (volume) or not reflected (ground)
-                    } else if (kMode == kGuided && !ground_ev) {
+                    } else if (kMode == kGuided && !ground_ev &&
+                               (A.guide_max_order == 0 || order <= A.guide_max_order)) {
                         phase = kPhGuide;        // the network proposes the new direction
                     } else {
                         const float u1 = rng.take(), u2 = rng.take();
@@ -746,68 +870,41 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 }
             }
         } else if (kMode == kGuided && run == kPhGuide) {
-            // ---- network inference on the matrix cores, 16 lanes per tile, then MIS sampling
+            // ---- network inference on the matrix cores, then MIS sampling.  The
+            // waiting lanes are packed into tiles of 16 by their rank.
             const bool active = phase == kPhGuide;
             extern __shared__ float2 s_dyn[];
-            char *base = reinterpret_cast<char *>(s_dyn) + A.guide_lds + (threadIdx.x >> 6) * kGuideScratchPerWave;
-            short *act0 = reinterpret_cast<short *>(base);                     // [16][64] bf16
-            short *act1 = reinterpret_cast<short *>(base + 16 * 64 * 2);       // [16][64] bf16
-            float *outz = reinterpret_cast<float *>(base + 2 * 16 * 64 * 2);   // [16][48] fp32
-            const int mrow = lane & 15, kq = lane >> 4;
+            char *gb = reinterpret_cast<char *>(s_dyn) + A.guide_lds;
+            const short *wl = reinterpret_cast<const short *>(gb);
+            const float *bl = reinterpret_cast<const float *>(gb + kWOff[4] * 2);
+            short *act0 = reinterpret_cast<short *>(gb + kGuideWeightBytes + (threadIdx.x >> 6) * kGuideScratchPerWave);
+            short *act1 = act0 + 16 * kActStride;
             if (active) rng.need(4, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
             const unsigned long long want = __ballot(active);
-            for (int t = 0; t < 4; ++t) {
-                if (((want >> (16 * t)) & 0xFFFFull) == 0ull) continue;   // no lane of this tile needs the network
-                const bool owner = kq == t;
+            const int rank = __popcll(want & ((1ull << lane) - 1ull));
+            const int ntiles = (__popcll(want) + 15) >> 4;
+            for (int t = 0; t < ntiles; ++t) {
+                const bool owner = active && (rank >> 4) == t;
+                const int row = rank & 15;
                 if (owner) {
                     float in[16];
 #pragma unroll
                     for (int k = 0; k < 16; ++k) in[k] = 0.0f;
-                    if (active) {
 #pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            in[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
-                            in[3 + a] = pd[a];
-                        }
-                        in[6] = __logf(1.0f + kev);
+                    for (int a = 0; a < 3; ++a) {
+                        in[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
+                        in[3 + a] = pd[a];
                     }
+                    in[6] = __logf(1.0f + kev);
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) act0[mrow * 64 + k] = to_bf16(in[k]);
+                    for (int k = 0; k < 16; ++k) act0[row * kActStride + k] = to_bf16(in[k]);
                 }
                 wave_sync();
-                for (int layer = 0; layer < kGuideLayers; ++layer) {
-                    const int kin = layer == 0 ? 16 : 64, nout = layer == kGuideLayers - 1 ? 48 : 64;
-                    const short *src = (layer & 1) ? act1 : act0;
-                    short *dst = (layer & 1) ? act0 : act1;
-                    for (int nt = 0; nt < nout / 16; ++nt) {
-                        f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-                        for (int kt = 0; kt < kin / 16; ++kt) {
-                            bf16x4 a, b;
-                            const int kk = kt * 16 + 4 * kq;
-#pragma unroll
-                            for (int i = 0; i < 4; ++i) {
-                                a[i] = src[mrow * 64 + kk + i];
-                                b[i] = A.gw.w[layer][(nt * 16 + mrow) * kin + kk + i];
-                            }
-                            c = mfma16(a, b, c);
-                        }
-                        const int col = nt * 16 + mrow;
-                        const float bias = A.gw.b[layer][col];
-#pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int m = 4 * kq + i;
-                            const float v = c[i] + bias;
-                            if (layer < kGuideLayers - 1)
-                                dst[m * 64 + col] = to_bf16(fmaxf(v, 0.0f));
-                            else
-                                outz[m * 48 + col] = v;
-                        }
-                    }
-                    wave_sync();
-                }
-                if (owner && active) {
+                guide_tile_forward(wl, bl, act0, act1, lane);
+                if (owner) {
                     const float u_sel = rng.take(), u_lobe = rng.take(), u1 = rng.take(), u2 = rng.take();
-                    guided_turn(outz + mrow * 48, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta);
+                    float q, p;
+                    guided_turn(act0 + row * kActStride, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta, q, p);
                     phase = kPhRay;
                 }
                 wave_sync();
@@ -959,7 +1056,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         for (int k = 0; k < 10; ++k)
             if (v[k]) atomicAdd(o + k, v[k]);
         unsigned long long *sch = reinterpret_cast<unsigned long long *>(A.counters->sched);
-        for (int k = 0; k < 15; ++k)
+        for (int k = 0; k < 18; ++k)
             if (s_cnt[kCTrips0 + k]) atomicAdd(sch + k, s_cnt[kCTrips0 + k]);
     }
 }
@@ -994,8 +1091,10 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
 {
     const int mode = guide ? kGuided : collect ? kCollect : kPlain;
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
-    const size_t guide_bytes = mode == kGuided ? (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
-    Shape sh = choose_shape(ctx, g, 256, guide_bytes);
+    const size_t guide_bytes =
+        mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
+    // the guided kernel holds 3 waves per SIMD (12 per CU) by its register count
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes, mode == kGuided ? 12 : 0);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -1032,6 +1131,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
     A.guide_lds = (int)node_bytes;
     A.guide_frac = s.guide_frac;
+    A.guide_max_order = (int)std::min<uint32_t>(s.guide_max_order, 1u << 30);
     A.col_spp = s.spp;
     A.gw = GuideWeights{};
     A.col = CollectView{};
@@ -1159,12 +1259,12 @@ GridView grid_view(const nc_grid *g, const float *d_kc)
     return v;
 }
 
-Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve)
+Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve, int waves_default)
 {
     Shape sh;
     sh.block = ctx->launch.block > 0 ? ctx->launch.block : block_default;
     sh.block = std::max(64, std::min(256, (sh.block / 64) * 64));
-    const int waves = ctx->launch.waves_per_cu > 0 ? ctx->launch.waves_per_cu : 16;
+    const int waves = ctx->launch.waves_per_cu > 0 ? ctx->launch.waves_per_cu : waves_default > 0 ? waves_default : 16;
     sh.wgs = std::max(1, ctx->num_cus * waves / (sh.block / 64));
     sh.spi = ctx->launch.samples_per_item > 0 ? ctx->launch.samples_per_item : 4;
     // LDS staging of the top levels: as many whole levels as fit the budget

@@ -91,6 +91,7 @@ class Sampling:
     flags: int = 0
     guide_frac: float = 0.5
     stream: int = 0
+    guide_max_order: int = 0    # last guided scattering order (0: all)
 
 
 @dataclass

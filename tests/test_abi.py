@@ -64,12 +64,14 @@ def test_struct_offsets_match_compiled_header(tmp_path):
                                                                                cname, f[0]))
             first = False
         lines.append('printf(",\\"%s\\": %%zu", sizeof(%s));' % (cname, cname))
+    lines.append('printf(",\\"nc_counters\\": %zu", sizeof(nc_counters));')
     lines += ['printf("}\\n");', "return 0; }"]
     src = tmp_path / "probe.c"
     src.write_text("\n".join(lines))
     exe = tmp_path / "probe"
     subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
     got = json.loads(subprocess.check_output([str(exe)]).decode())
+    assert got["nc_counters"] == 8 * _lib.N_COUNTER_WORDS == 8 * len(_lib.COUNTER_NAMES)
     for cname, pname in _STRUCTS.items():
         py = getattr(_lib, pname)
         assert got[cname] == C.sizeof(py), cname

@@ -84,3 +84,58 @@ def test_training_fits_a_direction_field():
     L1 = G.loss_grad(p1, rec[:, :7].astype(np.float64), rec[:, 7:10].astype(np.float64), np.ones(n))[0]
     # the density of a kappa = 30 lobe at its mean is ~4.8/sr; uniform is 1/(4 pi)
     assert L1 < L0 - 2.0, (L0, L1)
+
+
+def _hg(g, mu):
+    return (1 - g * g) / (4 * math.pi * (1 + g * g - 2 * g * mu) ** 1.5)
+
+
+def test_guided_sampling_step_against_oracle():
+    """The renderer's guided step on given vertices: the mixture density it
+    reports at the drawn direction matches the oracle's network and mixture,
+    p is HG at that direction, and the weight factor is p / (c q + (1-c) p)."""
+    c = ctx()
+    gd = api.Guide(c, seed=17)
+    prm = gd.get_params().cpu().numpy()
+    n = 20011
+    rec = _records(n, 3)
+    X = np.zeros((n, 8), np.float32)
+    X[:, :7] = rec[:, :7]
+    U = np.random.default_rng(4).random((n, 4)).astype(np.float32)
+    gf, g = 0.5, 0.85
+    out = gd.sample(torch.from_numpy(X).cuda(), torch.from_numpy(U).cuda(), gf, g).cpu().numpy().astype(np.float64)
+    d = out[:, :3]
+    assert np.allclose(np.linalg.norm(d, axis=1), 1.0, atol=1e-5)
+    z, _ = G.forward(prm, X[:, :7].astype(np.float64))
+    # the tracer keeps the network outputs in bf16 (sampling and density use the same rounded values)
+    q_ref = G.mixture_pdf(G.bf16_round(z), d)
+    rel = np.abs(out[:, 4] - q_ref) / q_ref
+    assert np.median(rel) < 0.01 and np.quantile(rel, 0.99) < 0.1, (np.median(rel), np.quantile(rel, 0.99))
+    p_ref = _hg(g, np.sum(d * X[:, 3:6], axis=1))
+    assert np.allclose(out[:, 5], p_ref, rtol=1e-4)
+    w_ref = out[:, 5] / (gf * out[:, 4] + (1 - gf) * out[:, 5])
+    assert np.allclose(out[:, 3], w_ref, rtol=1e-5)
+
+
+@pytest.mark.parametrize("gf", [0.5, 0.9])
+def test_guided_sampling_step_is_unbiased(gf):
+    """Over the mixture proposal, E[w] = 1 and E[w omega] = g omega_in (the
+    HG mean cosine) exactly, for any network."""
+    c = ctx()
+    gd = api.Guide(c, seed=17)
+    g = 0.85
+    rec = _records(4, 5)
+    m = 1 << 18
+    X = np.zeros((4 * m, 8), np.float32)
+    X[:, :7] = np.repeat(rec[:, :7], m, axis=0)
+    U = np.random.default_rng(6).random((4 * m, 4)).astype(np.float32)
+    out = gd.sample(torch.from_numpy(X).cuda(), torch.from_numpy(U).cuda(), gf, g).cpu().numpy().astype(np.float64)
+    for v in range(4):
+        o = out[v * m:(v + 1) * m]
+        w = o[:, 3]
+        wd = w[:, None] * o[:, :3]
+        se_w = w.std() / math.sqrt(m)
+        assert abs(w.mean() - 1.0) < 5 * se_w + 1e-6, (v, w.mean(), se_w)
+        exp = g * rec[v, 3:6].astype(np.float64)
+        se = wd.std(axis=0) / math.sqrt(m)
+        assert np.all(np.abs(wd.mean(axis=0) - exp) < 5 * se + 1e-6), (v, wd.mean(axis=0), exp, se)

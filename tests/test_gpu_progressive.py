@@ -32,7 +32,7 @@ def test_progressive_reaches_target_and_equals_one_render(block):
     c = ctx()
     kd = device_field(sc.kc)
     g = api.build_grid(c, kd, sc.desc, sc.grid)
-    target = 0.05 if block == 1 else 0.01
+    target = {1: 0.1, 5: 0.02, 8: 0.01}[block]
     s, s2, rep = api.render_progressive(c, g, kd, sc.optics, sc.camera, Sampling(seed=21, spp=0), target, first_spp=4,
                                         max_spp=4096, block=block)
     torch.cuda.synchronize()
