@@ -63,7 +63,7 @@ def parse():
     p.add_argument("--batch-spp", type=int, default=4)
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
     p.add_argument("--collect-spp", type=int, default=4, help="plain samples per pixel whose vertices train the guide")
-    p.add_argument("--train-steps", type=int, default=1000)
+    p.add_argument("--train-steps", type=int, default=1500)
     p.add_argument("--train-batch", type=int, default=8192)
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
@@ -71,7 +71,13 @@ def parse():
     p.add_argument("--no-refinement", action="store_true", help="skip the refinement sweep (fields 128^2x40..1024^2x320)")
     p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
     p.add_argument("--max-spp", type=int, default=16384, help="cap of the progressive runs")
-    return p.parse_args()
+    p.add_argument("--no-ceiling", action="store_true", help="skip the random-read ceiling measurement")
+    p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
+    a = p.parse_args()
+    if a.main_only:
+        a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
+        a.no_progressive = a.no_ceiling = True
+    return a
 
 
 def main():
@@ -180,8 +186,9 @@ def main():
     if not args.no_guided:
         out["guided"], gd = guided_run(ctx, sc, kc, spp, args, build_ms=ms_step - render_ms)
         out["time_to_1pct_s"]["guided"] = out["guided"]["time_to_1pct_s"]
-    out["gather_ceiling"] = gather_ceiling(ctx)
-    out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
+    if not args.no_ceiling:
+        out["gather_ceiling"] = gather_ceiling(ctx)
+        out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
     if not args.no_progressive:
         out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
     if args.workload == "cumulus" and not args.no_variants:
