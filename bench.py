@@ -63,10 +63,11 @@ def parse():
     p.add_argument("--batch-spp", type=int, default=4)
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
     p.add_argument("--collect-spp", type=int, default=4, help="plain samples per pixel whose vertices train the guide")
-    p.add_argument("--train-steps", type=int, default=1500)
+    p.add_argument("--train-steps", type=int, default=6000)
     p.add_argument("--train-batch", type=int, default=8192)
     p.add_argument("--lr", type=float, default=3e-3)
-    p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
+    p.add_argument("--guide-frac", type=float, default=0.35, help="probability of sampling the guide at a scattering")
+    p.add_argument("--guide-max-order", type=int, default=3, help="last guided scattering order (0: all)")
     p.add_argument("--no-variants", action="store_true", help="skip the grid variants (flat supercells, tau 0, global)")
     p.add_argument("--no-refinement", action="store_true", help="skip the refinement sweep (fields 128^2x40..1024^2x320)")
     p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
@@ -225,7 +226,8 @@ def progressive_run(ctx, sc, kc, gd, args):
     for name, guide in (("plain", None), ("guided", gd)):
         if name == "guided" and guide is None:
             continue
-        smp = inputs.Sampling(seed=sc.sampling.seed + 31, spp=0, guide_frac=args.guide_frac)
+        smp = inputs.Sampling(seed=sc.sampling.seed + 31, spp=0, guide_frac=args.guide_frac,
+                              guide_max_order=args.guide_max_order)
         _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, 0.01, first_spp=16,
                                            max_spp=args.max_spp, block=8, guide=guide)
         torch.cuda.synchronize()
@@ -333,13 +335,14 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
     losses = []
     for it in range(args.train_steps):
         idx = torch.randint(0, rec.shape[0], (args.train_batch,), device="cuda", generator=gen)
-        lr = args.lr * (0.2 if it >= 0.75 * args.train_steps else 1.0)
+        lr = args.lr * (0.2 if it >= 0.8 * args.train_steps else 1.0)
         l = gd.train_step(rec[idx], lr)
         if it % max(1, args.train_steps // 4) == 0 or it == args.train_steps - 1:
             losses.append(l)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, guide_frac=args.guide_frac)
+    smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, guide_frac=args.guide_frac,
+                          guide_max_order=args.guide_max_order)
     api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)         # warm-up
     torch.cuda.synchronize()
     e0 = torch.cuda.Event(enable_timing=True)
@@ -356,6 +359,7 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
     return {"collect_spp": args.collect_spp, "records": n, "collect_s": collect_s, "train_steps": args.train_steps,
             "train_batch": args.train_batch, "train_s": train_s,
             "loss": [round((x[0] / x[1]).item(), 4) for x in losses], "guide_frac": args.guide_frac,
+            "guide_max_order": args.guide_max_order,
             "render_ms": render_ms, "paths_per_s": paths / (step_ms / 1e3), "rel_std_err": eps,
             "time_to_1pct_s": collect_s + train_s + step_ms / 1e3 * (eps / 0.01) ** 2}, gd
 

@@ -491,6 +491,7 @@ __device__ inline void guided_turn(const short *zb, float c, float g, float u_se
     float psum = 0.0f;
 #pragma unroll
     for (int j = 0; j < kGuideLobes; ++j) psum += __expf(z(5 * j) - amax);
+    const float inv_psum = __builtin_amdgcn_rcpf(psum);
     float nd[3] = {pd[0], pd[1], pd[2]};
     if (u_sel < c) {
         // lobe by its weight, then the stable vMF cosine inversion (Jakob 2012)
@@ -508,7 +509,8 @@ __device__ inline void guided_turn(const short *zb, float c, float g, float u_se
         m[1] *= inv;
         m[2] *= inv;
         const float kap = __expf(fminf(fmaxf(z(5 * pick + 4), kLogKappaMin), kLogKappaMax));
-        const float t = fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) / kap));
+        const float t =
+            fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) * __builtin_amdgcn_rcpf(kap)));
         nd[0] = m[0];
         nd[1] = m[1];
         nd[2] = m[2];
@@ -524,11 +526,12 @@ __device__ inline void guided_turn(const short *zb, float c, float g, float u_se
         const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
         const float cw = (m0 * nd[0] + m1 * nd[1] + m2 * nd[2]) * inv;
         const float kap = __expf(fminf(fmaxf(z(5 * j + 4), kLogKappaMin), kLogKappaMax));
-        const float norm = kap / (2.0f * kPi * (-expm1f(-2.0f * kap)));
-        q += __expf(z(5 * j) - amax) / psum * norm * __expf(kap * (cw - 1.0f));
+        // kappa >= e^-3, so 1 - exp(-2 kappa) >= 0.095 keeps its relative precision
+        const float norm = kap * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - __expf(-2.0f * kap)));
+        q += __expf(z(5 * j) - amax) * inv_psum * norm * __expf(kap * (cw - 1.0f));
     }
     const float php = hg_phase(g, pd[0] * nd[0] + pd[1] * nd[1] + pd[2] * nd[2]);
-    beta *= php / (c * q + (1.0f - c) * php);
+    beta *= php * __builtin_amdgcn_rcpf(c * q + (1.0f - c) * php);
     q_out = q;
     p_out = php;
     pd[0] = nd[0];
@@ -539,13 +542,12 @@ __device__ inline void guided_turn(const short *zb, float c, float g, float u_se
 // The network in LDS.  Layer l's weights W_l [out][in] are staged once per
 // workgroup with rows padded by 4 bf16 (row strides of 20 and 68 elements
 // spread a fragment read over the banks), then the biases (fp32).  A wave's
-// tile is two [16][68] bf16 activation buffers; the 40 outputs end in the
-// first one (bf16, row stride 68).
+// tile is one [16][68] bf16 buffer: inputs in, outputs out.
 constexpr int kActStride = 68;
 constexpr int kWOff[5] = {0, 64 * 20, 64 * 20 + 64 * 68, 64 * 20 + 2 * 64 * 68, 64 * 20 + 2 * 64 * 68 + 48 * 68};
 constexpr int kBOff[4] = {0, 64, 128, 192};
 constexpr int kGuideWeightBytes = kWOff[4] * 2 + 240 * 4;                   // 27456
-constexpr int kGuideScratchPerWave = 2 * 16 * kActStride * 2;               // 4352
+constexpr int kGuideScratchPerWave = 16 * kActStride * 2;                   // 2176
 
 __device__ inline int w_stride(int l) { return l == 0 ? 20 : 68; }
 
@@ -563,37 +565,64 @@ __device__ inline void stage_guide(const GuideWeights &W, short *wl, float *bl)
     }
 }
 
-// The network on one tile of 16 vertices held by one wave: act0 rows hold
-// the bf16 inputs (columns 0..15); afterwards act0 rows hold the 40 outputs
-// (bf16).  D = A B on the matrix cores: lane l supplies A[l % 16][4 (l / 16) + i]
-// and B[4 (l / 16) + i][l % 16] and receives D[4 (l / 16) + i][l % 16].
-__device__ inline void guide_tile_forward(const short *wl, const float *bl, short *act0, short *act1, int lane)
+// bf16 of four floats (round to nearest even; v_cvt_pk_bf16_f32 on gfx950).
+__device__ inline bf16x4 cvt_bf16x4(float a, float b, float c, float d)
 {
-    const int mrow = lane & 15, kq = lane >> 4;
-    for (int layer = 0; layer < kGuideLayers; ++layer) {
-        const int kin = layer == 0 ? 16 : 64, nout = layer == kGuideLayers - 1 ? 48 : 64, st = w_stride(layer);
-        const short *src = (layer & 1) ? act1 : act0;
-        short *dst = (layer & 1) ? act0 : act1;
-        const short *wrow = wl + kWOff[layer];
-        for (int nt = 0; nt < nout / 16; ++nt) {
-            f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
-            for (int kt = 0; kt < kin / 16; ++kt) {
-                const int kk = kt * 16 + 4 * kq;
-                const bf16x4 a = *reinterpret_cast<const bf16x4 *>(src + mrow * kActStride + kk);
-                const bf16x4 b = *reinterpret_cast<const bf16x4 *>(wrow + (nt * 16 + mrow) * st + kk);
-                c = mfma16(a, b, c);
-            }
-            const int col = nt * 16 + mrow;
-            const float bias = bl[kBOff[layer] + col];
+    bf16x4 r;
+    r[0] = __builtin_bit_cast(short, (__bf16)a);
+    r[1] = __builtin_bit_cast(short, (__bf16)b);
+    r[2] = __builtin_bit_cast(short, (__bf16)c);
+    r[3] = __builtin_bit_cast(short, (__bf16)d);
+    return r;
+}
+
+// One 16-neuron block of a layer for the 16 vertices of a tile, as D = W X^T:
+// the weights are the A operand (rows = output neurons), the activations the
+// B operand (columns = vertices).  Lane l supplies W[16 nt + l % 16][16 kt + 4 (l / 16) + i]
+// and X[vertex l % 16][16 kt + 4 (l / 16) + i], and receives
+// out[vertex l % 16][16 nt + 4 (l / 16) + i], which is exactly its B operand
+// for block kt = nt of the next layer: activations never leave the registers.
+template <int KT>
+__device__ inline f32x4 guide_block(const short *w, int st, int nt, const bf16x4 *x, int n, int kq)
+{
+    f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int m = 4 * kq + i;
-                const float v = c[i] + bias;
-                dst[m * kActStride + col] = to_bf16(layer < kGuideLayers - 1 ? fmaxf(v, 0.0f) : v);
-            }
-        }
-        wave_sync();
+    for (int kt = 0; kt < KT; ++kt)
+        c = mfma16(*reinterpret_cast<const bf16x4 *>(w + (nt * 16 + n) * st + kt * 16 + 4 * kq), x[kt], c);
+    return c;
+}
+
+template <int KT>
+__device__ inline void guide_hidden(const short *w, int st, const float *b, const bf16x4 *x, bf16x4 *y, int n, int kq)
+{
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const f32x4 c = guide_block<KT>(w, st, nt, x, n, kq);
+        const f32x4 bb = *reinterpret_cast<const f32x4 *>(b + nt * 16 + 4 * kq);
+        y[nt] = cvt_bf16x4(fmaxf(c[0] + bb[0], 0.0f), fmaxf(c[1] + bb[1], 0.0f), fmaxf(c[2] + bb[2], 0.0f),
+                           fmaxf(c[3] + bb[3], 0.0f));
     }
+}
+
+// The network on one tile of 16 vertices held by one wave.  io: the wave's
+// [16][kActStride] bf16 tile; on entry row r holds vertex r's inputs in
+// columns 0..15, on exit its 40 outputs (bf16) in columns 0..39.
+__device__ inline void guide_tile_forward(const short *wl, const float *bl, short *io, int lane)
+{
+    const int n = lane & 15, kq = lane >> 4;
+    bf16x4 h[4], y[4];
+    h[0] = *reinterpret_cast<const bf16x4 *>(io + n * kActStride + 4 * kq);
+    guide_hidden<1>(wl + kWOff[0], 20, bl + kBOff[0], h, y, n, kq);
+    guide_hidden<4>(wl + kWOff[1], 68, bl + kBOff[1], y, h, n, kq);
+    guide_hidden<4>(wl + kWOff[2], 68, bl + kBOff[2], h, y, n, kq);
+#pragma unroll
+    for (int nt = 0; nt < 3; ++nt) {
+        const f32x4 c = guide_block<4>(wl + kWOff[3], 68, nt, y, n, kq);
+        const f32x4 bb = *reinterpret_cast<const f32x4 *>(bl + kBOff[3] + nt * 16 + 4 * kq);
+        *reinterpret_cast<bf16x4 *>(io + n * kActStride + nt * 16 + 4 * kq) =
+            cvt_bf16x4(c[0] + bb[0], c[1] + bb[1], c[2] + bb[2], c[3] + bb[3]);
+    }
+    wave_sync();
 }
 
 // The renderer's guided scattering step on given vertices (one wave per 64):
@@ -605,11 +634,10 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
                                                           float *__restrict__ out)
 {
     __shared__ __align__(16) short wl[kWOff[4]];
-    __shared__ float bl[240];
-    __shared__ __align__(16) short act[2 * 16 * kActStride];
+    __shared__ __align__(16) float bl[240];
+    __shared__ __align__(16) short act0[16 * kActStride];
     stage_guide(W, wl, bl);
     __syncthreads();
-    short *act0 = act, *act1 = act + 16 * kActStride;
     const int lane = threadIdx.x, mrow = lane & 15, kq = lane >> 4;
     for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
         const int r = base + lane;
@@ -621,7 +649,7 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
                     act0[mrow * kActStride + k] = to_bf16(active && k < kGuideIn ? in[(size_t)r * 8 + k] : 0.0f);
             }
             wave_sync();
-            guide_tile_forward(wl, bl, act0, act1, lane);
+            guide_tile_forward(wl, bl, act0, lane);
             if (kq == t && active) {
                 float pd[3] = {in[(size_t)r * 8 + 3], in[(size_t)r * 8 + 4], in[(size_t)r * 8 + 5]};
                 float beta = 1.0f, q = 0.0f, p = 0.0f;
@@ -703,14 +731,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         const int n_event = __popcll(__ballot(phase == kPhEvent));
         const int n_ray = __popcll(__ballot(phase == kPhRay));
         const int n_sample = __popcll(__ballot(phase == kPhSample));
-        const int n_guide = kMode == kGuided ? __popcll(__ballot(phase == kPhGuide)) : 0;
-        if (n_cross + n_coll + n_event + n_ray + n_sample + n_guide == 0) break;
+        if (n_cross + n_coll + n_event + n_ray + n_sample == 0) break;
         int run = kPhCross, best = n_cross;
         if (n_coll >= best) { run = kPhCollide; best = n_coll; }
         if (n_event >= best) { run = kPhEvent; best = n_event; }
         if (n_ray >= best) { run = kPhRay; best = n_ray; }
         if (n_sample > best) { run = kPhSample; best = n_sample; }
-        if (kMode == kGuided && n_guide > best) { run = kPhGuide; best = n_guide; }
         if (lane == 0) {
             atomicAdd(s_cnt + kCTrips0 + run, 1ull);
             atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
@@ -869,45 +895,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 }
             }
-        } else if (kMode == kGuided && run == kPhGuide) {
-            // ---- network inference on the matrix cores, then MIS sampling.  The
-            // waiting lanes are packed into tiles of 16 by their rank.
-            const bool active = phase == kPhGuide;
-            extern __shared__ float2 s_dyn[];
-            char *gb = reinterpret_cast<char *>(s_dyn) + A.guide_lds;
-            const short *wl = reinterpret_cast<const short *>(gb);
-            const float *bl = reinterpret_cast<const float *>(gb + kWOff[4] * 2);
-            short *act0 = reinterpret_cast<short *>(gb + kGuideWeightBytes + (threadIdx.x >> 6) * kGuideScratchPerWave);
-            short *act1 = act0 + 16 * kActStride;
-            if (active) rng.need(4, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
-            const unsigned long long want = __ballot(active);
-            const int rank = __popcll(want & ((1ull << lane) - 1ull));
-            const int ntiles = (__popcll(want) + 15) >> 4;
-            for (int t = 0; t < ntiles; ++t) {
-                const bool owner = active && (rank >> 4) == t;
-                const int row = rank & 15;
-                if (owner) {
-                    float in[16];
+            if (kMode == kGuided && __ballot(phase == kPhGuide) != 0ull) {
+                const unsigned long long t_guide = wall_clock64();
+                // ---- lanes that scatter with guidance: network inference on the
+                // matrix cores, then MIS sampling, in the same trip.  The lanes are
+                // packed into tiles of 16 by their rank.
+                const bool active = phase == kPhGuide;
+                extern __shared__ float2 s_dyn[];
+                char *gb = reinterpret_cast<char *>(s_dyn) + A.guide_lds;
+                const short *wl = reinterpret_cast<const short *>(gb);
+                const float *bl = reinterpret_cast<const float *>(gb + kWOff[4] * 2);
+                short *act0 = reinterpret_cast<short *>(gb + kGuideWeightBytes + (threadIdx.x >> 6) * kGuideScratchPerWave);
+                if (active) rng.need(4, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+                const unsigned long long want = __ballot(active);
+                const int rank = __popcll(want & ((1ull << lane) - 1ull));
+                const int ntiles = (__popcll(want) + 15) >> 4;
+                for (int t = 0; t < ntiles; ++t) {
+                    const bool owner = active && (rank >> 4) == t;
+                    const int row = rank & 15;
+                    if (owner) {
+                        short *x = act0 + row * kActStride;
 #pragma unroll
-                    for (int k = 0; k < 16; ++k) in[k] = 0.0f;
+                        for (int a = 0; a < 3; ++a) {
+                            x[a] = to_bf16(2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f);
+                            x[3 + a] = to_bf16(pd[a]);
+                        }
+                        x[6] = to_bf16(__logf(1.0f + kev));
 #pragma unroll
-                    for (int a = 0; a < 3; ++a) {
-                        in[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
-                        in[3 + a] = pd[a];
+                        for (int k = 7; k < 16; ++k) x[k] = 0;
                     }
-                    in[6] = __logf(1.0f + kev);
-#pragma unroll
-                    for (int k = 0; k < 16; ++k) act0[row * kActStride + k] = to_bf16(in[k]);
+                    wave_sync();
+                    guide_tile_forward(wl, bl, act0, lane);
+                    if (owner) {
+                        const float u_sel = rng.take(), u_lobe = rng.take(), u1 = rng.take(), u2 = rng.take();
+                        float q, p;
+                        guided_turn(act0 + row * kActStride, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta, q, p);
+                        phase = kPhRay;
+                    }
+                    wave_sync();
                 }
-                wave_sync();
-                guide_tile_forward(wl, bl, act0, act1, lane);
-                if (owner) {
-                    const float u_sel = rng.take(), u_lobe = rng.take(), u1 = rng.take(), u2 = rng.take();
-                    float q, p;
-                    guided_turn(act0 + row * kActStride, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta, q, p);
-                    phase = kPhRay;
+                if (lane == 0) {
+                    atomicAdd(s_cnt + kCTrips0 + kPhGuide, 1ull);
+                    atomicAdd(s_cnt + kCLanes0 + kPhGuide, (unsigned long long)__popcll(want));
+                    atomicAdd(s_cnt + kCCycles0 + kPhGuide, (unsigned long long)(wall_clock64() - t_guide));
                 }
-                wave_sync();
             }
         } else if (run == kPhRay) {
             // ---- start the next ray at r.o along pd (path) or towards the sun
@@ -1151,7 +1182,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 4;
     const void *fn = nullptr;
     if (mode == kGuided)
-        fn = (const void *)render_kernel<3, kGuided>;   // the network phase needs the larger register budget
+        fn = wpe == 3 ? (const void *)render_kernel<3, kGuided> : (const void *)render_kernel<4, kGuided>;
     else if (mode == kCollect)
         fn = (const void *)render_kernel<3, kCollect>;
     else
