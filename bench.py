@@ -73,15 +73,22 @@ def parse():
     p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
     p.add_argument("--max-spp", type=int, default=16384, help="cap of the progressive runs")
     p.add_argument("--no-ceiling", action="store_true", help="skip the random-read ceiling measurement")
+    p.add_argument("--sun", choices=["delta", "ratio", "residual"], default="residual",
+                   help="sun-ray transmissivity estimator (residual: decomposition tracking with the voxel minimum)")
+    p.add_argument("--no-estimators", action="store_true", help="skip the comparison of sun-ray estimators")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
         a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
-        a.no_progressive = a.no_ceiling = True
+        a.no_progressive = a.no_ceiling = a.no_estimators = True
     return a
 
 
+FLAGS = 0   # sun-ray estimator of every render in the run (set from --sun)
+
+
 def main():
+    global FLAGS
     args = parse()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (requested --gpus %d)" % args.gpus,
@@ -89,8 +96,9 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1902_01137_amd import api, inputs
+    from paper_1902_01137_amd import _lib, api, inputs
 
+    FLAGS = {"delta": _lib.NC_SUN_DELTA, "ratio": _lib.NC_SUN_RATIO, "residual": _lib.NC_SUN_RESIDUAL}[args.sun]
     fine = None
     if args.workload == "cumulus":
         # the 12.5 m field (1024^2 x 320) is generated once; the workload field is its 2x2x2 regional average
@@ -121,7 +129,8 @@ def main():
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=sc.sampling.seed + 7919 * i, spp=spp), s, s2,
+        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=sc.sampling.seed + 7919 * i, spp=spp, flags=FLAGS),
+                   s, s2,
                    counters)
         e1.record()
         ev.append((e0, e1))
@@ -163,7 +172,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": name, "spp": spp, "image": [cam.width, cam.height],
+        "config": {"workload": name, "spp": spp, "image": [cam.width, cam.height], "sun_estimator": args.sun,
                    "field": [sc.desc.nx, sc.desc.ny, sc.desc.nz], "tau_tilde": sc.grid.tau_tilde,
                    "paths_per_step": paths_per_step},
         "render_ms": render_ms,
@@ -192,6 +201,8 @@ def main():
         out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
     if not args.no_progressive:
         out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
+    if not args.no_estimators:
+        out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
     if args.workload == "cumulus" and not args.no_variants:
         out["grid_variants"] = grid_variants(ctx, sc, kc, spp)
     if fine is not None:
@@ -226,13 +237,38 @@ def progressive_run(ctx, sc, kc, gd, args):
     for name, guide in (("plain", None), ("guided", gd)):
         if name == "guided" and guide is None:
             continue
-        smp = inputs.Sampling(seed=sc.sampling.seed + 31, spp=0, guide_frac=args.guide_frac,
+        smp = inputs.Sampling(seed=sc.sampling.seed + 31, spp=0, flags=FLAGS, guide_frac=args.guide_frac,
                               guide_max_order=args.guide_max_order)
         _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, 0.01, first_spp=16,
                                            max_spp=args.max_spp, block=8, guide=guide)
         torch.cuda.synchronize()
         out[name] = rep
     return out
+
+
+def estimator_run(ctx, sc, kc, spp, build_ms):
+    """The same step with each sun-ray estimator: render time, error and time to 1 %."""
+    import torch
+
+    from paper_1902_01137_amd import _lib, api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    cam = sc.camera
+    res = {}
+    for name, fl in (("delta", _lib.NC_SUN_DELTA), ("ratio", _lib.NC_SUN_RATIO), ("residual", _lib.NC_SUN_RESIDUAL)):
+        smp = inputs.Sampling(seed=sc.sampling.seed + 61, spp=spp, flags=fl)
+        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=1, spp=1, flags=fl))   # warm-up
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        eps = rel_err(s, s2, spp)
+        paths = cam.width * cam.height * spp
+        res[name] = {"render_ms": ms, "paths_per_s": paths / (ms / 1e3), "rel_std_err": eps,
+                     "time_to_1pct_s": (build_ms + ms) / 1e3 * (eps / 0.01) ** 2}
+    return res
 
 
 def grid_variants(ctx, sc, kc, spp):
@@ -249,7 +285,7 @@ def grid_variants(ctx, sc, kc, spp):
                      ("global", inputs.GridParams(math.inf, sc.grid.k_gas, 0))):
         g = api.build_grid(ctx, kc, sc.desc, gp)
         cnt = api.new_counters("cuda")
-        smp = inputs.Sampling(seed=sc.sampling.seed + 41, spp=spp)
+        smp = inputs.Sampling(seed=sc.sampling.seed + 41, spp=spp, flags=FLAGS)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
@@ -290,7 +326,7 @@ def refinement_sweep(ctx, sc, fine):
                 g = api.build_grid(ctx, kc, desc, gp)
             torch.cuda.synchronize()
             build_ms = (time.perf_counter() - t0) * 1e3 / reps
-            smp = inputs.Sampling(seed=sc.sampling.seed + 51, spp=spp)
+            smp = inputs.Sampling(seed=sc.sampling.seed + 51, spp=spp, flags=FLAGS)
             e0 = torch.cuda.Event(enable_timing=True)
             e1 = torch.cuda.Event(enable_timing=True)
             e0.record()
@@ -326,7 +362,8 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rec, n, _, _ = api.collect_vertices(ctx, g, kc, sc.optics, cam,
-                                        inputs.Sampling(seed=sc.sampling.seed + 101, spp=args.collect_spp), cap)
+                                        inputs.Sampling(seed=sc.sampling.seed + 101, spp=args.collect_spp, flags=FLAGS),
+                                        cap)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     gd = api.Guide(ctx, seed=1)
@@ -341,7 +378,7 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
             losses.append(l)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
-    smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, guide_frac=args.guide_frac,
+    smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, flags=FLAGS, guide_frac=args.guide_frac,
                           guide_max_order=args.guide_max_order)
     api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)         # warm-up
     torch.cuda.synchronize()
@@ -373,11 +410,11 @@ def batch_run(ctx, sc, kc, spp):
     views = inputs.batch_views()
     jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})) for cam, sz in views]
     px = sum(c.width * c.height for c, _ in jobs)
-    smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp)
+    smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp, flags=FLAGS)
     api.render_batch(ctx, g, kc, jobs, smp)                       # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp))
+    api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp, flags=FLAGS))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     return {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "ms": dt * 1e3,

@@ -115,6 +115,23 @@ typedef struct {
     double fov_y_deg, ortho_w, ortho_h;
 } nc_camera;
 
+/* Estimators of the sun's transmissivity in the local estimate (bits 0-1
+ * of nc_sampling.flags).  Section 4.1 evaluates the direct sun with
+ * decomposition tracking (Novak et al. 2014; Kutz et al. 2017):
+ *   NC_SUN_DELTA     null-collision (delta) tracking: 0 or 1 per sun ray;
+ *   NC_SUN_RATIO     ratio tracking: the product of 1 - k/k_hat over the
+ *                    tentative collisions to the box exit;
+ *   NC_SUN_RESIDUAL  residual ratio tracking with each voxel's minimum
+ *                    extinction as the control: exp(-integral of k_min)
+ *                    times the product of 1 - (k - k_min)/(k_hat - k_min)
+ *                    over collisions sampled with the residual majorant.
+ * The ratio estimators play Russian roulette below a transmissivity of 0.1.
+ * All three have the same expectation. */
+#define NC_SUN_DELTA 0
+#define NC_SUN_RATIO 1
+#define NC_SUN_RESIDUAL 2
+#define NC_SUN_ESTIMATOR_MASK 3
+
 /* Sampling: seed keys the random streams; sample s of pixel p of job j uses
  * the Philox counter (p, sample_offset + s, draw, stream + j), so a run with
  * sample_offset = n continues one that took n samples per pixel, and runs
@@ -195,10 +212,12 @@ nc_status nc_trace_leaves(nc_ctx *ctx, const nc_grid *grid, const float *d_rays,
                           int32_t *d_leaf, float *d_t, int32_t *d_count);
 
 /* Direct transmissivity by the null-collision algorithm of Section 2.3
- * (Eq. 2): for each ray, nsamples Bernoulli paths in the grid's
- * piecewise-constant majorant; d_sum[n], d_sumsq[n] (float64) receive the
- * sum and sum of squares of the path transmissivities.  The ground is not
- * intersected (rays are cast through the field's box only). */
+ * (Eq. 2): for each ray, sampling->spp paths in the grid's piecewise-constant
+ * majorant, each returning 0 or 1 (NC_SUN_DELTA) or a ratio-tracking
+ * estimate (NC_SUN_RATIO, NC_SUN_RESIDUAL: bits 0-1 of sampling->flags);
+ * d_sum[n], d_sumsq[n] (float64) receive the sum and sum of squares of the
+ * path estimates.  The ground is not intersected (rays are cast through the
+ * field's box only). */
 nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                            const float *d_rays, int32_t n, const nc_sampling *sampling, double *d_sum,
                            double *d_sumsq, nc_counters *d_counters);

@@ -61,6 +61,7 @@ COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visit
                  "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
                                               for b in PHASES] + ["sched_pad%d" % i for i in range(6)]
 N_COUNTER_WORDS = 34
+NC_SUN_DELTA, NC_SUN_RATIO, NC_SUN_RESIDUAL = 0, 1, 2
 GUIDE_PARAMS = 11432
 GUIDE_RECORD = 12
 

@@ -434,6 +434,7 @@ nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *g, const float *d_kc, con
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (n < 0 || s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative size");
     if (n == 0 || s->spp == 0) return NC_OK;
+    if ((s->flags & NC_SUN_ESTIMATOR_MASK) == 3) return fail(ctx, NC_ERR_INVALID_ARG, "unknown sun estimator");
     if (!d_kc || !d_rays || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     DeviceGuard guard(ctx->device);
     hipError_t e = nc::launch_transmittance(ctx, g, d_kc, make_opt(optics, g->params.k_gas), d_rays, n, *s, d_sum,
@@ -460,6 +461,7 @@ static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, co
     DeviceGuard guard(ctx->device);
     if (cam.type == 2 && !(std::cos(optics->sun_zenith_deg * M_PI / 180.0) > 0.0))
         return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
+    if ((s->flags & NC_SUN_ESTIMATOR_MASK) == 3) return fail(ctx, NC_ERR_INVALID_ARG, "unknown sun estimator");
     if (guide && guide->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
     if (guide && !(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
         return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
@@ -609,6 +611,7 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int3
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative spp");
     if (n_jobs == 0 || s->spp == 0) return NC_OK;
+    if ((s->flags & NC_SUN_ESTIMATOR_MASK) == 3) return fail(ctx, NC_ERR_INVALID_ARG, "unknown sun estimator");
     if (!cams || !optics || !out_offsets || !d_kc || !d_sum || !d_sumsq)
         return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     if (s->sample_offset + (uint64_t)s->spp > 0xffffffffull)

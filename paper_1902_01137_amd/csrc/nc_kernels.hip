@@ -263,10 +263,56 @@ struct TransArgs {
     long long items;
     uint64_t seed, sample_offset;
     float mscale;
+    int est;                 // 0 delta, 1 ratio, 2 residual ratio tracking
     double *sum, *sumsq;
     nc_counters *counters;
     int lds_first, lds_nodes;
 };
+
+// Ratio (kctrl = 0) or residual ratio tracking (kctrl = the voxel minimum,
+// collisions sampled with the residual majorant) of one ray to the box exit.
+// The same estimators as the renderer's sun rays, as a plain loop.
+__device__ inline float ratio_transmittance(const GridView &g, const NodeSrc &ns, Ray &r, Rng &rng, float mscale,
+                                            bool resid, Counters &cnt)
+{
+    const float sun_rr = 0.1f;
+    float T = 1.0f;
+    auto kctrl = [&]() { return resid ? g.kscale * r.kmin + g.k_gas : 0.0f; };
+    if (resid) r.khat = fmaxf(r.khat - kctrl(), 0.0f);
+    float tau = rng.exp1();
+    for (;;) {
+        ++cnt.segments;
+        const float ktau = r.khat * (r.texit - r.t);
+        if (r.khat > 0.0f && tau < ktau) {
+            const float t0 = r.t;
+            r.t = fminf(r.t + tau / r.khat, r.texit);
+            const float kc = kctrl();
+            float kx = g.kscale * r.kmin + g.k_gas;
+            if (r.lev != 0) {
+                kx = g.kscale * g.kc[collision_cell(g, r, r.t)] + g.k_gas;
+                ++cnt.gathers;
+            }
+            ++cnt.tentative;
+            ++cnt.nulls;
+            T *= __expf(-kc * (r.t - t0)) * fmaxf(0.0f, 1.0f - (kx - kc) / r.khat);
+            if (T < sun_rr) T = rng.u01() * sun_rr < T ? sun_rr : 0.0f;
+            if (T == 0.0f) return 0.0f;
+            tau = rng.exp1();
+        } else {
+            if (resid) {
+                T *= __expf(-kctrl() * (r.texit - r.t));
+                if (T < sun_rr) T = rng.u01() * sun_rr < T ? sun_rr : 0.0f;
+                if (T == 0.0f) return 0.0f;
+            }
+            tau -= ktau;
+            uint32_t rd = 0;
+            if (!next_leaf(g, ns, r, mscale, rd)) return T;
+            cnt.node_reads += rd;
+            ++cnt.leaf_visits;
+            if (resid) r.khat = fmaxf(r.khat - kctrl(), 0.0f);
+        }
+    }
+}
 
 __global__ __launch_bounds__(256) void transmittance_kernel(TransArgs A)
 {
@@ -283,25 +329,32 @@ __global__ __launch_bounds__(256) void transmittance_kernel(TransArgs A)
         const int s0 = blk * A.spi, s1 = min(s0 + A.spi, A.spp);
         const float o[3] = {A.rays[6 * i], A.rays[6 * i + 1], A.rays[6 * i + 2]};
         const float d[3] = {A.rays[6 * i + 3], A.rays[6 * i + 4], A.rays[6 * i + 5]};
-        double acc = 0.0;
+        double acc = 0.0, acc2 = 0.0;
         int hint = A.g.L;
         for (int s = s0; s < s1; ++s) {
             Rng rng;
             rng.init((uint32_t)i, (uint32_t)(A.sample_offset + s), 1u, A.seed);
             Ray r;
             start_ray(A.g, ns, r, o, d, hint, A.mscale, cnt);
-            float tau = rng.exp1();
-            float kc_hit = 0.0f;
-            int res;
-            do {
-                res = track_step(A.g, ns, r, tau, rng, A.mscale, true, kc_hit, cnt);
-            } while (res == kContinue);
-            if (res == kExit) acc += 1.0;
+            float T;
+            if (A.est == 0) {
+                float tau = rng.exp1();
+                float kc_hit = 0.0f;
+                int res;
+                do {
+                    res = track_step(A.g, ns, r, tau, rng, A.mscale, true, kc_hit, cnt);
+                } while (res == kContinue);
+                T = res == kExit ? 1.0f : 0.0f;
+            } else {
+                T = ratio_transmittance(A.g, ns, r, rng, A.mscale, A.est == 2, cnt);
+            }
+            acc += T;
+            acc2 += (double)T * T;
             ++cnt.paths;
             ++cnt.nee_rays;
         }
         unsafeAtomicAdd(A.sum + i, acc);
-        unsafeAtomicAdd(A.sumsq + i, acc);   // t is 0 or 1
+        unsafeAtomicAdd(A.sumsq + i, acc2);
     }
     flush_counters(cnt, A.counters);
 }
@@ -321,6 +374,7 @@ hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float
     A.seed = s.seed;
     A.sample_offset = s.sample_offset;
     A.mscale = op.mscale;
+    A.est = s.flags & NC_SUN_ESTIMATOR_MASK;
     A.sum = sum;
     A.sumsq = sumsq;
     A.counters = counters;
@@ -415,6 +469,7 @@ struct RenderArgs {
 // of diverging inside every traversal step.
 enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhGuide = 5, kPhIdle = 6 };
 enum RenderMode { kPlain = 0, kGuided = 1, kCollect = 2 };
+constexpr float kSunRoulette = 0.1f;   // ratio estimators: Russian roulette below this transmissivity
 static_assert(kPhGuide == 5 && kPhIdle == 6, "six running phases, one counter slot each");
 
 // After the optical thickness tau has been drawn or carried: a tentative
@@ -679,7 +734,7 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
     return hipGetLastError();
 }
 
-template <int kWavesPerEU, int kMode>
+template <int kWavesPerEU, int kMode, int kSun>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
     extern __shared__ float2 s_nodes[];
@@ -705,7 +760,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     bool have_item = false;    // the lane holds a queue item with samples left
     bool traced = false;       // a path has been traced since the last sample phase
     int res = kContinue;       // outcome of the last step (for the event phase)
-    float kc_hit = 0.0f;
+    float kc_hit = 0.0f;       // k_c at the last real collision of a path ray
+    float &t_sun = kc_hit;     // during a sun ray (ratio estimators): its transmissivity estimate so far
     int pix = 0, s = 0, s_end = 0;
     float acc = 0.0f, acc2 = 0.0f;
     float Lp = 0.0f;
@@ -748,12 +804,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             const bool active = phase == kPhCross;
             bool leaf = false, trunc = false;
             if (active) {
+                const bool resid = shadow && kSun == 2;
+                if (resid) {
+                    t_sun *= __expf(-(g.kscale * r.kmin + g.k_gas) * (r.texit - r.t));
+                    if (t_sun < kSunRoulette) {     // Russian roulette on small estimates
+                        rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
+                                 A.key1);
+                        t_sun = rng.take() * kSunRoulette < t_sun ? kSunRoulette : 0.0f;
+                    }
+                }
                 tau -= r.khat * (r.texit - r.t);
-                if (!next_leaf(g, ns, r, A.op.mscale, reads)) {
+                if (resid && t_sun == 0.0f) {
+                    res = kReal;                    // the estimate is zero: the sun ray ends here
+                    phase = kPhEvent;
+                } else if (!next_leaf(g, ns, r, A.op.mscale, reads)) {
                     res = kExit;
                     phase = kPhEvent;
                 } else {
                     leaf = true;
+                    if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + g.k_gas), 0.0f);
                     phase = voxel_phase(r, tau);
                     if (++segs >= A.op.max_segments) {
                         trunc = true;
@@ -768,7 +837,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             // ---- tentative collision in the current voxel: real or null
             const bool active = phase == kPhCollide;
             bool real = false, gathered = false, trunc = false;
-            if (active) {
+            if (active && shadow && kSun != 0) {
+                // ratio tracking (control 0) or residual ratio tracking (control
+                // = the voxel minimum; r.khat then holds the residual majorant):
+                // every tentative collision scales the estimate t_sun by
+                // 1 - (k - k_ctrl) / khat, the control part by exp(-k_ctrl dt)
+                rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+                const float t0 = r.t;
+                r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
+                const float kmin = g.kscale * r.kmin + g.k_gas;
+                const float kctrl = kSun == 2 ? kmin : 0.0f;
+                float kx = kmin;                // a level-0 voxel is one cell: k is known
+                if (r.lev != 0) {
+                    kx = g.kscale * g.kc[collision_cell(g, r, r.t)] + g.k_gas;
+                    ++reads;
+                    gathered = true;
+                }
+                t_sun *= __expf(-kctrl * (r.t - t0)) * fmaxf(0.0f, 1.0f - (kx - kctrl) * __builtin_amdgcn_rcpf(r.khat));
+                const float u = rng.take();
+                if (t_sun < kSunRoulette) {     // Russian roulette on small estimates
+                    if (u * kSunRoulette < t_sun)
+                        t_sun = kSunRoulette;
+                    else
+                        t_sun = 0.0f;
+                }
+                if (t_sun == 0.0f) {
+                    res = kReal;
+                    phase = kPhEvent;
+                    real = true;
+                } else {
+                    tau = rng.take_exp1();
+                    phase = voxel_phase(r, tau);
+                    if (++segs >= A.op.max_segments) {
+                        trunc = true;
+                        phase = kPhSample;
+                    }
+                }
+            } else if (active) {
                 rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
                 const float thr = rng.take() * r.khat;
@@ -807,7 +912,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 rng.need(3, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 bool cont = false;               // go on to the scatter / reflect decision
                 if (shadow) {
-                    if (res == kExit) Lp += beta * w_nee;   // the sun ray got through
+                    if (res == kExit) Lp += beta * w_nee * (kSun != 0 ? t_sun : 1.0f);   // the sun ray got through
                     cont = true;
                 } else if (res == kReal) {
                     // volume event: local estimate of the sun, then scatter or absorb
@@ -948,6 +1053,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const float o[3] = {r.o[0], r.o[1], r.o[2]};
                 const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
                 hit = start_ray_cached_r(g, ns, r, o, rd, vc, A.op.mscale, reads);
+                if (kSun != 0 && shadow) {
+                    t_sun = 1.0f;
+                    if (kSun == 2) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + g.k_gas), 0.0f);
+                }
                 rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 tau = rng.take_exp1();
                 phase = voxel_phase(r, tau);
@@ -1180,16 +1289,27 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     // register budget: waves per SIMD the kernel is compiled for (3..6)
     // (default 4: the plain kernel fits 128 registers without spilling)
     const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 4;
+    // kernel variant: mode, sun-ray estimator, register budget (waves per SIMD)
+    const int est = s.flags & NC_SUN_ESTIMATOR_MASK;
     const void *fn = nullptr;
-    if (mode == kGuided)
-        fn = wpe == 3 ? (const void *)render_kernel<3, kGuided> : (const void *)render_kernel<4, kGuided>;
-    else if (mode == kCollect)
-        fn = (const void *)render_kernel<3, kCollect>;
-    else
-        fn = wpe == 3   ? (const void *)render_kernel<3, kPlain>
-             : wpe == 4 ? (const void *)render_kernel<4, kPlain>
-             : wpe == 5 ? (const void *)render_kernel<5, kPlain>
-                        : (const void *)render_kernel<6, kPlain>;
+    if (mode == kGuided) {
+        fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0>
+             : est == 1 ? (const void *)render_kernel<3, kGuided, 1>
+                        : (const void *)render_kernel<3, kGuided, 2>;
+    } else if (mode == kCollect) {
+        fn = est == 0 ? (const void *)render_kernel<3, kCollect, 0>
+             : est == 1 ? (const void *)render_kernel<3, kCollect, 1>
+                        : (const void *)render_kernel<3, kCollect, 2>;
+    } else if (est == 0) {
+        fn = wpe == 3   ? (const void *)render_kernel<3, kPlain, 0>
+             : wpe == 4 ? (const void *)render_kernel<4, kPlain, 0>
+             : wpe == 5 ? (const void *)render_kernel<5, kPlain, 0>
+                        : (const void *)render_kernel<6, kPlain, 0>;
+    } else if (est == 1) {
+        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 1> : (const void *)render_kernel<4, kPlain, 1>;
+    } else {
+        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 2> : (const void *)render_kernel<4, kPlain, 2>;
+    }
     int resident = 0;
     const size_t lds = node_bytes + guide_bytes;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&resident, fn, sh.block, lds) == hipSuccess && resident > 0)
