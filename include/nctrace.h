@@ -250,16 +250,19 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const n
  * reflected (Lambertian, probability ground_albedo) or stops.
  *
  * Each arrival adds, in pixel order [k][px_ny][px_nx] of d_tally (float64,
- * ADDED to the buffer):
+ * 9 x px_ny x px_nx, ADDED to the buffer):
  *   k=0: 1, k=1: 1 (sum of squares), k=2: 1 if the photon was never
  *   scattered or reflected (direct), k=3: sigma_s, k=4: sigma_s^2,
- *   k=5: sigma_g, k=6: sigma_g^2,
+ *   k=5: sigma_g, k=6: sigma_g^2, k=7: sigma_a, k=8: sigma_a^2,
  * where sigma_s and sigma_g are the path's accumulated scores: real
  * collision + k_c/k, null collision - k_c/(k_hat - k), scattering
- * + k_gas/(s k); HG scattering of cosine mu + d ln p(mu)/dg.  The
+ * + k_gas/(s k); HG scattering of cosine mu + d ln p(mu)/dg; sigma_a, the
+ * score of the droplets' absorptivity alpha = 1 - ssa (Section 5.1's
+ * sensitivity), adds -1/(1 - alpha) per scattering.  The
  * transmissivity of pixel p is T_p = tally[0][p] * px_nx*px_ny / n_photons
  * (ground flux over the flux through the top, per unit area), and
- * dT_p/ds, dT_p/dg are tally[3][p], tally[5][p] times the same factor.
+ * dT_p/ds, dT_p/dg, dT_p/dalpha are tally[3][p], tally[5][p], tally[7][p]
+ * times the same factor.
  * d_global[4] (float64, added): photons escaping upward, absorbed by the
  * ground inside / outside the footprint, absorbed in the volume; they sum to
  * n_photons. */
@@ -270,8 +273,9 @@ nc_status nc_flux(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_
 /* Derivative-path replay of nc_flux: the same photons (same sampling and
  * n_photons) are traced again and, at every arrival in pixel p, d_grad[p]
  * times the path's scores is accumulated: d_out[0] += sum grad[p] sigma_s,
- * d_out[1] += sum grad[p] sigma_g (float64).  Multiplied by
- * px_nx*px_ny / n_photons this is dL/ds and dL/dg for L = sum_p grad[p] T_p.
+ * d_out[1] += sum grad[p] sigma_g, d_out[2] += sum grad[p] sigma_a
+ * (float64).  Multiplied by px_nx*px_ny / n_photons this is dL/ds, dL/dg
+ * and dL/dalpha for L = sum_p grad[p] T_p.
  * d_grad is float64 [px_ny][px_nx]. */
 nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                           double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,

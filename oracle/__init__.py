@@ -252,7 +252,7 @@ def flux(desc, kc, k_gas, optics, px, n_photons, seed, mode=0, kscale=1.0, grid=
     f = make_field(desc, kc, k_gas, kscale)
     op = make_optics(optics)
     nx, ny = px
-    tally = np.zeros((7, ny, nx))
+    tally = np.zeros((9, ny, nx))
     glob = np.zeros(4)
     lib().orc_flux(C.byref(f), grid.handle if grid is not None else None, C.byref(op), int(mode), nx, ny,
                    int(n_photons), int(seed), int(photon_offset), _ptr(tally), _ptr(glob))

@@ -957,13 +957,18 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
  *             real: k_c / k;  null: -k_c / (k_hat - k);  and, at each
  *             scattering, d ln ssa(x) / d s = k_g / (s k),
  *   sigma_g = sum over HG scatterings of d ln p(mu) / d g,
+ *   sigma_a = sum over scatterings of d ln ssa(x) / d alpha = -1 / (1 - alpha)
+ *             for the droplets' absorptivity alpha = 1 - ssa (the
+ *             sensitivity of Section 5.1; an absorbed photon arrives
+ *             nowhere, so absorption events need no term),
  * so that the derivative estimates are the means of (arrival) x sigma.
  * The scores need the tentative collisions of null-collision tracking
  * (mode 2: the grid's majorant m (s kmax_c + k_g)); mode 0 tracks with exact
  * free paths and reports the transmissivity only.
  *
- * tally[7][px_ny][px_nx]: T sum, T sum of squares, direct-T sum,
- *   dT/ds sum, dT/ds sum of squares, dT/dg sum, dT/dg sum of squares
+ * tally[9][px_ny][px_nx]: T sum, T sum of squares, direct-T sum,
+ *   dT/ds sum, dT/ds sum of squares, dT/dg sum, dT/dg sum of squares,
+ *   dT/dalpha sum, dT/dalpha sum of squares
  *   (per-arrival values; the caller scales by A_top / (N a_pixel)).
  * glob[4]: up-escapes, ground absorptions in / out of the footprint,
  *   volume absorptions.
@@ -1005,13 +1010,13 @@ static int delta_hier_scored(const orc_field *f, const orc_grid *g, double m, co
     }
 }
 
-typedef struct { int pix; int direct; double ss, sg; } orc_arrival;
+typedef struct { int pix; int direct; double ss, sg, sa; } orc_arrival;
 
 /* One photon; returns the number of arrivals stored (at most cap). */
 static int photon_walk(const orc_field *f, const orc_grid *g, const orc_optics *op, int mode, orc_rng *r,
                        int px_nx, int px_ny, orc_arrival *arr, int cap, double *glob)
 {
-    double s[3], o[3], d[3], sig_s = 0.0, sig_g = 0.0;
+    double s[3], o[3], d[3], sig_s = 0.0, sig_g = 0.0, sig_a = 0.0;
     double Lx = f->nx * f->dx, Ly = f->ny * f->dy;
     int a, scattered = 0, n = 0, segs = 0;
     sun_dir(op, s);
@@ -1032,6 +1037,8 @@ static int photon_walk(const orc_field *f, const orc_grid *g, const orc_optics *
             for (a = 0; a < 3; ++a) o[a] = o[a] + tc * d[a];
             if (rng_u01(r) >= ssa) { glob[3] += 1.0; return n; }
             if (f->k_gas > 0.0) sig_s += f->k_gas / (f->kscale * k);
+            /* survival has probability (1 - alpha) k_d / k: d ln / d alpha = -1 / (1 - alpha) */
+            sig_a -= 1.0 / op->ssa;
             {
                 double mu = orc_hg_sample_mu(op->g, rng_u01(r));
                 double phi = 2.0 * ORC_PI * rng_u01(r);
@@ -1055,6 +1062,7 @@ static int photon_walk(const orc_field *f, const orc_grid *g, const orc_optics *
                     arr[n].direct = !scattered;
                     arr[n].ss = sig_s;
                     arr[n].sg = sig_g;
+                    arr[n].sa = sig_a;
                     n++;
                 }
             }
@@ -1096,6 +1104,8 @@ void orc_flux(const orc_field *f, const orc_grid *g, const orc_optics *op, int32
             tally[4 * np + q] += arr[i].ss * arr[i].ss;
             tally[5 * np + q] += arr[i].sg;
             tally[6 * np + q] += arr[i].sg * arr[i].sg;
+            tally[7 * np + q] += arr[i].sa;
+            tally[8 * np + q] += arr[i].sa * arr[i].sa;
         }
     }
     free(arr);
@@ -1104,7 +1114,7 @@ void orc_flux(const orc_field *f, const orc_grid *g, const orc_optics *op, int32
 /* Central finite differences with common random numbers: each photon is
  * traced twice with identical random streams and exact free paths (path
  * tracking), at parameter + h and - h (which = 0: extinction scale s,
- * which = 1: asymmetry g).  With exact free-path inversion and inverse-CDF
+ * which = 1: asymmetry g, which = 2: droplet absorptivity alpha = 1 - ssa).  With exact free-path inversion and inverse-CDF
  * HG sampling the trajectories move continuously with the parameter.
  * out[2][px_ny][px_nx]: sum and sum of squares over photons of the
  * per-photon quotient (arrivals(+h) - arrivals(-h)) / (2h) in each pixel;
@@ -1123,7 +1133,8 @@ void orc_flux_fd(const orc_field *f_in, const orc_optics *op_in, int32_t which, 
         orc_rng r;
         int np_, nm_, i, j;
         if (which == 0) { fp.kscale += h; fm.kscale -= h; }
-        else { opp.g += h; opm.g -= h; }
+        else if (which == 1) { opp.g += h; opm.g -= h; }
+        else { opp.ssa -= h; opm.ssa += h; }
         rng_init(&r, seed, (uint64_t)(photon_offset + p));
         np_ = photon_walk(&fp, NULL, &opp, 0, &r, px_nx, px_ny, ap, ORC_MAX_ARRIVALS, glob);
         rng_init(&r, seed, (uint64_t)(photon_offset + p));

@@ -268,9 +268,9 @@ def philox4x32_10(ctx: Context, ctr: torch.Tensor, key: torch.Tensor) -> torch.T
 
 def flux(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, n_photons: int,
          sampling: Sampling, extinction_scale: float = 1.0, counters: torch.Tensor | None = None):
-    """Forward photons (nc_flux): raw tallies [7, py, px] and terminal counts [4], float64 on the device."""
+    """Forward photons (nc_flux): raw tallies [9, py, px] and terminal counts [4], float64 on the device."""
     nx, ny = px
-    tally = torch.zeros((7, ny, nx), dtype=torch.float64, device=kc.device)
+    tally = torch.zeros((9, ny, nx), dtype=torch.float64, device=kc.device)
     glob = torch.zeros(4, dtype=torch.float64, device=kc.device)
     o = _optics(optics)
     sm = _sampling(sampling)
@@ -281,10 +281,10 @@ def flux(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, 
 
 def flux_adjoint(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, n_photons: int,
                  sampling: Sampling, grad: torch.Tensor, extinction_scale: float = 1.0):
-    """Derivative-path replay (nc_flux_adjoint): raw [sum grad*sigma_s, sum grad*sigma_g], float64."""
+    """Derivative-path replay (nc_flux_adjoint): raw [sum grad*sigma_s, sum grad*sigma_g, sum grad*sigma_a]."""
     nx, ny = px
     assert tuple(grad.shape) == (ny, nx)
-    out = torch.zeros(2, dtype=torch.float64, device=kc.device)
+    out = torch.zeros(3, dtype=torch.float64, device=kc.device)
     g64 = grad.to(dtype=torch.float64).contiguous()
     o = _optics(optics)
     sm = _sampling(sampling)
@@ -294,16 +294,18 @@ def flux_adjoint(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px:
 
 
 class TransmissionFn(torch.autograd.Function):
-    """Ground transmissivity map T(s, g) with gradients through the adjoint kernel.
+    """Ground transmissivity map T(s, g, alpha) with gradients through the adjoint kernel.
 
-    forward: photons traced by nc_flux; T_p = arrivals_p * n_pixels / n_photons.
-    backward: nc_flux_adjoint replays the same photons weighting each arrival
-    by grad_T[p], giving dL/ds and dL/dg for the same samples."""
+    s scales the droplet extinction, g is the HG asymmetry, alpha = 1 - ssa the
+    droplets' absorptivity.  forward: photons traced by nc_flux; T_p =
+    arrivals_p * n_pixels / n_photons.  backward: nc_flux_adjoint replays the
+    same photons weighting each arrival by grad_T[p], giving dL/ds, dL/dg and
+    dL/dalpha for the same samples."""
 
     @staticmethod
-    def forward(fctx, scale, g, lib_ctx, grid, kc, optics, px, n_photons, sampling):
+    def forward(fctx, scale, g, alpha, lib_ctx, grid, kc, optics, px, n_photons, sampling):
         import dataclasses
-        op = dataclasses.replace(optics, g=float(g))
+        op = dataclasses.replace(optics, g=float(g), ssa=1.0 - float(alpha))
         tally, _ = flux(lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale))
         f = px[0] * px[1] / float(n_photons)
         fctx.args = (lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale), f)
@@ -316,7 +318,8 @@ class TransmissionFn(torch.autograd.Function):
         out = flux_adjoint(lib_ctx, grid, kc, op, px, n_photons, sampling, grad_T, s) * f
         ds = out[0].to(fctx.dev)
         dg = out[1].to(fctx.dev)
-        return ds, dg, None, None, None, None, None, None, None
+        da = out[2].to(fctx.dev)
+        return ds, dg, da, None, None, None, None, None, None, None
 
 
 def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, sampling: Sampling,

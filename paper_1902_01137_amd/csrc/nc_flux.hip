@@ -14,8 +14,12 @@
 // multiplies the path density by k/k_hat (real) or 1 - k/k_hat (null), so a
 // path carries the score
 //   sigma_s = sum_real k_c/k - sum_null k_c/(k_hat - k) + sum_scatter k_g/(s k)
-// (the last term is d ln ssa(x)/ds), and every HG scattering of cosine mu adds
-//   sigma_g += d ln p(mu)/dg = -2g/(1-g^2) - 3(g-mu)/(1+g^2-2g mu).
+// (the last term is d ln ssa(x)/ds), every HG scattering of cosine mu adds
+//   sigma_g += d ln p(mu)/dg = -2g/(1-g^2) - 3(g-mu)/(1+g^2-2g mu),
+// and every scattering adds d ln ssa(x)/d alpha = -1/(1 - alpha) to the
+// score of the droplets' absorptivity alpha = 1 - ssa (the sensitivity the
+// paper computes in Section 5.1).  Absorbed photons arrive nowhere, so the
+// absorption events need no term.
 // The derivative of a tally is the mean of (tally) x sigma.  The adjoint
 // replay re-runs the same photons (same counter-based random numbers) and
 // accumulates grad[pixel] x sigma at each arrival.
@@ -34,10 +38,10 @@ struct FluxArgs {
     float x0, y0, Lx, Ly, ztop;
     unsigned long long n_photons;
     uint64_t seed, offset;
-    double *tally;          // [7][px_ny][px_nx] (forward) or NULL
+    double *tally;          // [9][px_ny][px_nx] (forward) or NULL
     double *glob;           // [4] (forward) or NULL
     const double *grad;     // [px_ny][px_nx] (adjoint) or NULL
-    double *out;            // [2] (adjoint) or NULL
+    double *out;            // [3] (adjoint) or NULL
     nc_counters *counters;
     int lds_first, lds_nodes;
 };
@@ -93,7 +97,8 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
     const size_t np = (size_t)A.px_nx * A.px_ny;
     Counters cnt = {};
     uint32_t up = 0, gin = 0, gout = 0, vabs = 0;
-    double adj_s = 0.0, adj_g = 0.0;
+    double adj_s = 0.0, adj_g = 0.0, adj_a = 0.0;
+    const float dln_alpha = A.op.ssa > 0.0f ? -1.0f / A.op.ssa : 0.0f;
 
     for (unsigned long long p = blockIdx.x * (unsigned long long)blockDim.x + threadIdx.x; p < A.n_photons;
          p += (unsigned long long)gridDim.x * blockDim.x) {
@@ -102,7 +107,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
         rng.init((uint32_t)id, (uint32_t)(id >> 32), 2u, A.seed);
         float o[3] = {A.x0 + rng.u01() * A.Lx, A.y0 + rng.u01() * A.Ly, A.ztop};
         float d[3] = {-sun[0], -sun[1], -sun[2]};
-        float sig_s = 0.0f, sig_g = 0.0f;
+        float sig_s = 0.0f, sig_g = 0.0f, sig_a = 0.0f;
         bool scattered = false;
         int segs = 0;
         Ray r;
@@ -128,6 +133,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                     break;
                 }
                 if (g.k_gas > 0.0f) sig_s += g.k_gas / (g.kscale * k);
+                sig_a += dln_alpha;
                 const float mu = hg_sample_mu(A.op.g, rng.u01());
                 sig_g += hg_dlng(A.op.g, mu);
                 float nd[3] = {r.d[0], r.d[1], r.d[2]};
@@ -149,6 +155,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                         const double w = A.grad[q];
                         adj_s += w * (double)sig_s;
                         adj_g += w * (double)sig_g;
+                        adj_a += w * (double)sig_a;
                     } else {
                         unsafeAtomicAdd(A.tally + q, 1.0);
                         unsafeAtomicAdd(A.tally + np + q, 1.0);
@@ -157,6 +164,8 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                         unsafeAtomicAdd(A.tally + 4 * np + q, (double)sig_s * (double)sig_s);
                         unsafeAtomicAdd(A.tally + 5 * np + q, (double)sig_g);
                         unsafeAtomicAdd(A.tally + 6 * np + q, (double)sig_g * (double)sig_g);
+                        unsafeAtomicAdd(A.tally + 7 * np + q, (double)sig_a);
+                        unsafeAtomicAdd(A.tally + 8 * np + q, (double)sig_a * (double)sig_a);
                     }
                 }
                 if (rng.u01() >= A.op.rho) {
@@ -178,15 +187,17 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
     }
     flush_counters(cnt, A.counters);
     if (kAdjoint) {
-        double s = adj_s, t = adj_g;
+        double s = adj_s, t = adj_g, u = adj_a;
 #pragma unroll
         for (int off = 32; off >= 1; off >>= 1) {
             s += __shfl_xor(s, off);
             t += __shfl_xor(t, off);
+            u += __shfl_xor(u, off);
         }
         if (__lane_id() == 0) {
             unsafeAtomicAdd(A.out, s);
             unsafeAtomicAdd(A.out + 1, t);
+            unsafeAtomicAdd(A.out + 2, u);
         }
     } else {
         const unsigned long long a = wave_sum(up), b = wave_sum(gin), c = wave_sum(gout), e = wave_sum(vabs);

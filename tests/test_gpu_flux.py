@@ -47,7 +47,7 @@ def test_beer_lambert_and_scale_derivative(s):
     op = Optics(ssa=0.0, g=0.85, ground_albedo=0.0, sun_zenith_deg=th0, majorant_scale=2.0)
     n = 2_000_000
     tally, glob = api.flux(c, g, kd, op, (1, 1), n, Sampling(seed=4), extinction_scale=s)
-    t = tally.cpu().numpy().reshape(7)
+    t = tally.cpu().numpy().reshape(9)
     mu0 = math.cos(math.radians(th0))
     exact = math.exp(-s * tau / mu0)
     T = t[0] / n
@@ -55,7 +55,7 @@ def test_beer_lambert_and_scale_derivative(s):
     d = t[3] / n
     se = math.sqrt(max(t[4] / n - d * d, 0) / n)
     assert abs(d - (-(tau / mu0) * exact)) < 4.5 * se
-    assert t[5] == 0.0 and t[2] == t[0]
+    assert t[5] == 0.0 and t[7] == 0.0 and t[2] == t[0]
 
 
 def _cyl(n_photons_gpu=10_000_000):
@@ -97,26 +97,29 @@ def test_cylinder_transmissivity_vs_oracle():
 
 
 def test_cylinder_sensitivities_vs_oracle():
-    """GPU score estimates of dT/ds and dT/dg against the oracle's score
-    estimator and its common-random-number central differences (h = 1e-3)."""
+    """GPU score estimates of dT/ds, dT/dg and dT/dalpha against the oracle's
+    score estimator and its common-random-number central differences."""
     N = 10_000_000
     sc, c, kd, g, t, glob, cnt = _cyl(N)
     f = 100 * 100
     ds_g, ds_gse = _maps(np.stack([t[3], t[4]]), N, f)
     dg_g, dg_gse = _maps(np.stack([t[5], t[6]]), N, f)
+    da_g, da_gse = _maps(np.stack([t[7], t[8]]), N, f)
     No = 800_000
     ot, _ = oracle.parallel_flux(sc.desc, sc.kc, 0.0, sc.optics, (100, 100), No, seed=inputs.SEED_ORACLE_BASE + 14,
                                  mode=2, tau_tilde=1.0)
     ds_o, ds_ose = _maps(np.stack([ot[3], ot[4]]), No, f)
     dg_o, dg_ose = _maps(np.stack([ot[5], ot[6]]), No, f)
-    for a, sa, b, sb in ((ds_g, ds_gse, ds_o, ds_ose), (dg_g, dg_gse, dg_o, dg_ose)):
+    da_o, da_ose = _maps(np.stack([ot[7], ot[8]]), No, f)
+    for a, sa, b, sb in ((ds_g, ds_gse, ds_o, ds_ose), (dg_g, dg_gse, dg_o, dg_ose), (da_g, da_gse, da_o, da_ose)):
         res = compare(*_blocks(a, sa), *_blocks(b, sb))
         assert res["ok"], res
     # domain means against CRN finite differences of exactly-tracked photons
     Nf = 2_000_000
-    for which, (a, sa) in ((0, (ds_g, ds_gse)), (1, (dg_g, dg_gse))):
+    # alpha = 1 - ssa = 0.001 here: its step stays below alpha so that ssa stays a probability
+    for which, (a, sa), h in ((0, (ds_g, ds_gse), 1e-3), (1, (dg_g, dg_gse), 1e-3), (2, (da_g, da_gse), 5e-4)):
         _, tot = oracle.parallel_flux_fd(sc.desc, sc.kc, 0.0, sc.optics, (100, 100), Nf,
-                                         seed=inputs.SEED_ORACLE_BASE + 24 + which, which=which, h=1e-3)
+                                         seed=inputs.SEED_ORACLE_BASE + 24 + which, which=which, h=h)
         q = tot[0] / Nf        # per-photon quotient summed over pixels
         q2 = tot[1] / Nf
         se_fd = math.sqrt(max(q2 - q * q, 0) / Nf)
@@ -141,9 +144,11 @@ def test_adjoint_replays_forward_paths():
     gr = grad.cpu().numpy()
     exp_s = (gr * t[3]).sum()
     exp_g = (gr * t[5]).sum()
+    exp_a = (gr * t[7]).sum()
     o = out.cpu().numpy()
     assert o[0] == pytest.approx(exp_s, rel=1e-9, abs=1e-6)
     assert o[1] == pytest.approx(exp_g, rel=1e-9, abs=1e-6)
+    assert o[2] == pytest.approx(exp_a, rel=1e-9, abs=1e-6)
 
 
 def test_autograd_function():
@@ -153,7 +158,8 @@ def test_autograd_function():
     smp = Sampling(seed=78)
     s = torch.tensor(1.0, dtype=torch.float64, requires_grad=True)
     gg = torch.tensor(0.85, dtype=torch.float64, requires_grad=True)
-    T = api.TransmissionFn.apply(s, gg, c, g, kd, sc.optics, (100, 100), N, smp)
+    aa = torch.tensor(1.0 - sc.optics.ssa, dtype=torch.float64, requires_grad=True)
+    T = api.TransmissionFn.apply(s, gg, aa, c, g, kd, sc.optics, (100, 100), N, smp)
     w = torch.linspace(0, 1, 100 * 100, dtype=torch.float64, device="cuda").reshape(100, 100)
     L = (T * w).sum()
     L.backward()
@@ -164,5 +170,7 @@ def test_autograd_function():
     assert float(L) == pytest.approx((wn * t[0]).sum() * f, rel=1e-12)
     assert float(s.grad) == pytest.approx((wn * t[3]).sum() * f, rel=1e-9)
     assert float(gg.grad) == pytest.approx((wn * t[5]).sum() * f, rel=1e-9)
+    assert float(aa.grad) == pytest.approx((wn * t[7]).sum() * f, rel=1e-9)
+    assert float(aa.grad) < 0          # more absorption -> less transmission
     # more extinction -> less transmission under the cloud
     assert float(s.grad) < 0

@@ -108,3 +108,44 @@ def test_hg_log_derivative(orc):
             h = 1e-6
             num = (math.log(orc.hg_phase(g + h, mu)) - math.log(orc.hg_phase(g - h, mu))) / (2 * h)
             assert orc.hg_dlng(g, mu) == pytest.approx(num, rel=1e-6, abs=1e-6)
+
+
+def test_absorptivity_score_matches_crn_fd(orc):
+    """Sensitivity to the droplets' absorptivity alpha = 1 - ssa (Section
+    5.1): the score -1/(1 - alpha) per scattering along delta-tracked paths
+    against central differences of exactly-tracked paths (the survival draw
+    is shared, so the difference only counts the flipped decisions)."""
+    tau = 2.0
+    desc, k = _slab(tau)
+    og = orc.OracleGrid(desc, k, tau_tilde=1.0)
+    op = Optics(ssa=0.9, g=0.7, ground_albedo=0.0, sun_zenith_deg=20.0, majorant_scale=2.0)
+    n = 100000
+    tally, _ = orc.flux(desc, k, 0.0, op, (1, 1), n, seed=16, mode=2, grid=og)
+    da = tally[7].sum() / n
+    se_a = math.sqrt(max(tally[8].sum() / n - da * da, 0) / n)
+    out = orc.flux_fd(desc, k, 0.0, op, (1, 1), 4 * n, seed=17, which=2, h=1e-2)
+    dfd = out[0].sum() / (4 * n)
+    se_fd = math.sqrt(max(out[1].sum() / (4 * n) - dfd * dfd, 0) / (4 * n))
+    z = (da - dfd) / math.sqrt(se_a ** 2 + se_fd ** 2)
+    assert abs(z) < 4, (da, se_a, dfd, se_fd)
+    assert da < -4 * se_a               # more absorption, less transmission
+
+
+def test_absorptivity_forward_scattering_closed_form(orc):
+    """With an almost delta-forward phase function (g = 0.9999) photons keep
+    their direction, so T = exp(-alpha tau / mu0) and
+    dT/dalpha = -(tau / mu0) T (up to the tiny angular spread)."""
+    tau, th0, alpha = 1.5, 30.0, 0.2
+    desc, k = _slab(tau)
+    og = orc.OracleGrid(desc, k, tau_tilde=1.0)
+    op = Optics(ssa=1.0 - alpha, g=0.9999, ground_albedo=0.0, sun_zenith_deg=th0, majorant_scale=2.0)
+    n = 100000
+    tally, _ = orc.flux(desc, k, 0.0, op, (1, 1), n, seed=18, mode=2, grid=og)
+    mu0 = math.cos(math.radians(th0))
+    T_exact = math.exp(-alpha * tau / mu0)
+    T = tally[0].sum() / n
+    assert abs(T - T_exact) < 4 * math.sqrt(T_exact * (1 - T_exact) / n) + 1e-3
+    da = tally[7].sum() / n
+    se_a = math.sqrt(max(tally[8].sum() / n - da * da, 0) / n)
+    d_exact = -(tau / mu0) * T_exact
+    assert abs(da - d_exact) < 4 * se_a + 2e-3, (da, d_exact, se_a)
