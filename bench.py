@@ -76,11 +76,12 @@ def parse():
     p.add_argument("--sun", choices=["delta", "ratio", "residual"], default="residual",
                    help="sun-ray transmissivity estimator (residual: decomposition tracking with the voxel minimum)")
     p.add_argument("--no-estimators", action="store_true", help="skip the comparison of sun-ray estimators")
+    p.add_argument("--no-tau-sweep", action="store_true", help="skip the merge-threshold sweep")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
         a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
-        a.no_progressive = a.no_ceiling = a.no_estimators = True
+        a.no_progressive = a.no_ceiling = a.no_estimators = a.no_tau_sweep = True
     return a
 
 
@@ -203,6 +204,8 @@ def main():
         out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
     if not args.no_estimators:
         out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
+    if args.workload == "cumulus" and not args.no_tau_sweep:
+        out["tau_sweep"] = tau_sweep(ctx, sc, kc)
     if args.workload == "cumulus" and not args.no_variants:
         out["grid_variants"] = grid_variants(ctx, sc, kc, spp)
     if fine is not None:
@@ -268,6 +271,37 @@ def estimator_run(ctx, sc, kc, spp, build_ms):
         paths = cam.width * cam.height * spp
         res[name] = {"render_ms": ms, "paths_per_s": paths / (ms / 1e3), "rel_std_err": eps,
                      "time_to_1pct_s": (build_ms + ms) / 1e3 * (eps / 0.01) ** 2}
+    return res
+
+
+def tau_sweep(ctx, sc, kc):
+    """Render time against the merge threshold tau_tilde (Fig. 7), with the
+    split between voxel crossing and collision work: 512^2 view, 32 spp."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    cam = inputs.Camera(**{**vars(sc.camera), "width": 512, "height": 512})
+    spp = 32
+    paths = 512 * 512 * spp
+    res = []
+    for tt in (0.0, 0.03, 0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0, math.inf):
+        g = api.build_grid(ctx, kc, sc.desc, inputs.GridParams(tt, sc.grid.k_gas, 0))
+        cnt = api.new_counters("cuda")
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=sc.sampling.seed + 71, spp=spp, flags=FLAGS),
+                   counters=cnt)
+        e1.record()
+        torch.cuda.synchronize()
+        c = api.counters_dict(cnt)
+        ticks = {k: c["ticks_" + k] for k in ("cross", "collide", "event", "ray", "sample")}
+        tot = max(sum(ticks.values()), 1)
+        res.append({"tau_tilde": tt if math.isfinite(tt) else "inf", "render_ms": e0.elapsed_time(e1),
+                    "leaf_visits_per_path": c["leaf_visits"] / paths, "tentative_per_path": c["tentative"] / paths,
+                    "nulls_per_path": c["nulls"] / paths, "crossing_share": ticks["cross"] / tot,
+                    "collision_share": ticks["collide"] / tot})
+        del g
     return res
 
 

@@ -400,7 +400,11 @@ hipError_t launch_transmittance(const nc_ctx *ctx, const nc_grid *g, const float
 
 
 enum LaneState { kIdle = 0, kPath = 1, kShadow = 2 };
-constexpr int kChunk = 256;   // queue items a wave takes per global atomic
+// Queue items a wave takes per global atomic: one per lane, so that the last
+// chunks are short (paths differ a lot in cost and the launch ends with the
+// slowest wave); 64 atomics per 64 x samples_per_item paths are cheap.
+constexpr int kChunk = 64;
+static_assert(kChunk >= 64, "a chunk must cover every lane of a wave that needs an item");
 
 __device__ inline void camera_ray(const CamView &c, int px, int py, float u1, float u2, float o[3], float d[3])
 {
