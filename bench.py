@@ -77,6 +77,7 @@ def parse():
                    help="sun-ray transmissivity estimator (residual: decomposition tracking with the voxel minimum)")
     p.add_argument("--no-estimators", action="store_true", help="skip the comparison of sun-ray estimators")
     p.add_argument("--no-tau-sweep", action="store_true", help="skip the merge-threshold sweep")
+    p.add_argument("--autotune", action="store_true", help="autotune the launch knobs before timing")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
@@ -118,6 +119,7 @@ def main():
 
     ctx = api.Context(0)
     ctx.set_launch(args.block, args.waves_per_cu, args.spi, args.lds_levels)
+    tuned = None
     kc = torch.from_numpy(sc.kc).cuda()
     torch.cuda.synchronize()
     cnt = api.new_counters("cuda")
@@ -137,6 +139,13 @@ def main():
         ev.append((e0, e1))
         return g, s, s2
 
+    if args.autotune and not args.main_only and not (args.block or args.waves_per_cu or args.spi):
+        # launch knobs for this view (outside the timed region; the choice is reported)
+        g0 = api.build_grid(ctx, kc, sc.desc, sc.grid)
+        launch, best_ms = api.autotune_render(ctx, g0, kc, sc.optics, cam,
+                                              inputs.Sampling(seed=sc.sampling.seed + 3, spp=spp, flags=FLAGS))
+        tuned = {"launch": launch, "best_render_ms": best_ms}
+        del g0
     for i in range(args.warmup):
         step(i)
     torch.cuda.synchronize()
@@ -177,6 +186,7 @@ def main():
                    "field": [sc.desc.nx, sc.desc.ny, sc.desc.nz], "tau_tilde": sc.grid.tau_tilde,
                    "paths_per_step": paths_per_step},
         "render_ms": render_ms,
+        "autotuned": tuned,
         "segments_per_s": c["segments"] / args.steps / (render_ms / 1e3),
         "tentative_per_s": c["tentative"] / args.steps / (render_ms / 1e3),
         "per_path": {k: c[k] / max(c["paths"], 1) for k in ("segments", "tentative", "nulls", "reals",

@@ -655,7 +655,7 @@ nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     const int blocks[] = {64, 128, 256};
     const int waves[] = {12, 16};
     const int ldsl[] = {0, 2, -1};
-    nc_launch cur{256, 12, 4, -1};
+    nc_launch cur{256, 16, 4, -1};   // the library defaults
     hipEvent_t e0 = nullptr, e1 = nullptr;
     DeviceGuard guard(ctx->device);
     hipError_t he = hipEventCreate(&e0);

@@ -928,7 +928,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                     const float kd = g.kscale * kc_hit;
                     kev = kd + g.k_gas;
-                    const float ssa = A.op.ssa * kd / (kd + g.k_gas);
+                    const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + g.k_gas);
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
                     w_nee = ssa * hg_phase(A.op.g, mu);
                     p_cont = ssa;
@@ -944,7 +944,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 } else if (r.d[2] < 0.0f) {
                     // ground hit: Lambertian local estimate
-                    const float tg = -r.o[2] / r.d[2];
+                    const float tg = -r.o[2] * __builtin_amdgcn_rcpf(r.d[2]);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) pd[a] = r.d[a];
                     r.o[0] = r.o[0] + tg * r.d[0];
@@ -1126,13 +1126,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         const volatile JobView &J = R.jobs[job];
                         const int tx = J.tiles_x, ty = J.tiles_y, spi = R.spi, spp = R.spp;
                         const int W = J.cam.W, H = J.cam.H;
-                        const unsigned long long lw = w - J.item_begin;
-                        const unsigned long long tile_px = (unsigned long long)tx * ty * 64ull;
-                        const int blk = (int)(lw / tile_px);
-                        const int rem = (int)(lw - (unsigned long long)blk * tile_px);
+                        // a job has fewer than 2^32 items (checked at launch): 32-bit divisions
+                        const uint32_t lw = (uint32_t)(w - J.item_begin);
+                        const uint32_t tile_px = (uint32_t)tx * (uint32_t)ty * 64u;
+                        const uint32_t blk_u = lw / tile_px;
+                        const int blk = (int)blk_u;
+                        const int rem = (int)(lw - blk_u * tile_px);
                         const int tile = rem >> 6, within = rem & 63;
-                        const int px = (tile % tx) * 8 + (within & 7);
-                        const int py = (tile / tx) * 8 + (within >> 3);
+                        const int trow = (int)((uint32_t)tile / (uint32_t)tx);
+                        const int px = (tile - trow * tx) * 8 + (within & 7);
+                        const int py = trow * 8 + (within >> 3);
                         s = blk * spi;
                         s_end = min(s + spi, spp);
                         if (px < W && py < H && s < s_end) {
@@ -1244,6 +1247,18 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     rare.sample_offset = s.sample_offset;
     rare.spp = s.spp;
     rare.spi = std::max(1, std::min(sh.spi, s.spp));
+    {
+        // the kernel decodes a job's items in 32 bits: take more samples per
+        // item when a job would otherwise have 2^32 items or more
+        unsigned long long tiles64 = 0;
+        for (int j = 0; j < n_jobs; ++j)
+            tiles64 = std::max(tiles64, (unsigned long long)((jobs_host[j].cam.W + 7) / 8) *
+                                            (unsigned long long)((jobs_host[j].cam.H + 7) / 8) * 64ull);
+        const unsigned long long max_blocks = 0xffffffffull / std::max(tiles64, 1ull);
+        if ((unsigned long long)((s.spp + rare.spi - 1) / rare.spi) > max_blocks)
+            rare.spi = (int)std::min<unsigned long long>((unsigned long long)s.spp,
+                                                         ((unsigned long long)s.spp + max_blocks - 1) / max_blocks);
+    }
     rare.sum = sum;
     rare.sumsq = sumsq;
     rare.jobs = jobs_dev;
@@ -1257,7 +1272,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         jobs[j].tiles_x = (jobs[j].cam.W + 7) / 8;
         jobs[j].tiles_y = (jobs[j].cam.H + 7) / 8;
         jobs[j].item_begin = items;
-        items += (unsigned long long)jobs[j].tiles_x * jobs[j].tiles_y * 64ull * blocks;
+        items += (unsigned long long)jobs[j].tiles_x * jobs[j].tiles_y * 64ull * blocks;   // < 2^32 per job
     }
     RenderArgs A;
     A.g = grid_view(g, d_kc);
