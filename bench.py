@@ -223,6 +223,8 @@ def main():
         del fine
     if args.workload == "cumulus" and not args.no_batch:
         out["batch"] = batch_run(ctx, sc, kc, args.batch_spp)
+        if not args.no_guided:
+            out["batch_guided"] = batch_guided_run(ctx, sc, kc, args.batch_spp, args)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
     print(json.dumps(out))
@@ -458,11 +460,84 @@ def batch_run(ctx, sc, kc, spp):
     api.render_batch(ctx, g, kc, jobs, smp)                       # warm-up
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp, flags=FLAGS))
+    s, s2, offs = api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp,
+                                                                     flags=FLAGS))
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    eps = batch_block_err(s, s2, offs, jobs, spp)
     return {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "ms": dt * 1e3,
-            "paths_per_s": px * spp / dt}
+            "paths_per_s": px * spp / dt, "rel_std_err_block8": eps,
+            "time_to_1pct_block8_s": dt * (eps / 0.01) ** 2}
+
+
+def batch_block_err(s, s2, offs, jobs, spp, b=8):
+    """Relative standard error of the batch on 8x8-pixel block means, all images together."""
+    S = s.cpu().numpy()
+    S2 = s2.cpu().numpy()
+    means, errs = [], []
+    for (cam, _), o in zip(jobs, offs):
+        n = cam.width * cam.height
+        m = S[o:o + n].reshape(cam.height, cam.width) / spp
+        v = np.maximum(S2[o:o + n].reshape(cam.height, cam.width) / spp - m * m, 0) * spp / (spp - 1) / spp
+        H, W = (cam.height // b) * b, (cam.width // b) * b
+        mb = m[:H, :W].reshape(H // b, b, W // b, b).mean(axis=(1, 3))
+        vb = v[:H, :W].reshape(H // b, b, W // b, b).sum(axis=(1, 3)) / (b * b) ** 2
+        means.append(mb.ravel())
+        errs.append(vb.ravel())
+    return float(np.sqrt(np.concatenate(errs).mean()) / np.concatenate(means).mean())
+
+
+def batch_guided_run(ctx, sc, kc, spp, args):
+    """The 48 views x 4 suns with guidance: one network per sun (its inputs do
+    not see the sun), trained on vertices of that sun's largest view; one
+    guided launch per sun.  Error on 8x8-pixel block means against the plain
+    batch at the same spp."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    views = inputs.batch_views()
+    suns = sorted({sz for _, sz in views})
+    t0 = time.perf_counter()
+    guides = {}
+    for sz in suns:
+        op = inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})
+        cam = max((c for c, z in views if z == sz), key=lambda c: c.width * c.height)
+        rec, n, _, _ = api.collect_vertices(ctx, g, kc, op, cam,
+                                            inputs.Sampling(seed=sc.sampling.seed + 301, spp=4, flags=FLAGS),
+                                            cam.width * cam.height * 4 * 16)
+        gd = api.Guide(ctx, seed=1)
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(1)
+        for it in range(args.train_steps):
+            idx = torch.randint(0, rec.shape[0], (args.train_batch,), device="cuda", generator=gen)
+            gd.train_step(rec[idx], args.lr * (0.2 if it >= 0.8 * args.train_steps else 1.0))
+        guides[sz] = gd
+        del rec
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    out = {"train_s": train_s}
+    for name in ("plain", "guided"):
+        t_total, errs, means = 0.0, [], []
+        S_all = []
+        for sz in suns:
+            jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": z})) for cam, z in views if z == sz]
+            smp = inputs.Sampling(seed=sc.sampling.seed + 311, spp=spp, flags=FLAGS, guide_frac=args.guide_frac,
+                                  guide_max_order=args.guide_max_order)
+            gd = guides[sz] if name == "guided" else None
+            api.render_batch(ctx, g, kc, jobs, smp, guide=gd)                # warm-up
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            s, s2, offs = api.render_batch(ctx, g, kc, jobs, smp, guide=gd)
+            torch.cuda.synchronize()
+            t_total += time.perf_counter() - t1
+            S_all.append((s, s2, offs, jobs))
+        eps = batch_block_err(torch.cat([x[0] for x in S_all]), torch.cat([x[1] for x in S_all]),
+                              [o + sum(x[0].numel() for x in S_all[:k]) for k, x in enumerate(S_all) for o in x[2]],
+                              [j for x in S_all for j in x[3]], spp)
+        out[name] = {"ms": t_total * 1e3, "rel_std_err_block8": eps,
+                     "time_to_1pct_block8_s": t_total * (eps / 0.01) ** 2 + (train_s if name == "guided" else 0.0)}
+    return out
 
 
 def cpu_baseline(sc, spp, budget_s):

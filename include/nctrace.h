@@ -413,6 +413,14 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, i
                           const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *sampling,
                           double *d_sum, double *d_sumsq, nc_counters *d_counters);
 
+/* nc_render_batch with guided scattering (nc_render_guided) in every job.
+ * The network's inputs do not include the sun, so a guide is trained for one
+ * sun: pass the jobs that share it (one launch per sun). */
+nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs,
+                                 const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                                 const nc_sampling *sampling, const nc_guide *guide, double *d_sum, double *d_sumsq,
+                                 nc_counters *d_counters);
+
 /* Launch-shape knobs of the path-tracing kernels (0 = library default). */
 typedef struct {
     int32_t block;          /* threads per workgroup (multiple of 64) */

@@ -101,6 +101,7 @@ _SIGS = [
     ("nc_gather_rate", C.c_int32, [_P, _P, C.c_uint64, C.c_int32, C.c_int32, _P, C.POINTER(C.c_double)]),
     ("nc_collect_vertices", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P,
                                         C.c_uint64, _P, _P, _P, _P, _P]),
+    ("nc_render_batch_guided", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P, _P]),
     ("nc_render_batch", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_autotune_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
                                        C.POINTER(C.c_double)]),

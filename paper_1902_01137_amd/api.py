@@ -323,8 +323,9 @@ class TransmissionFn(torch.autograd.Function):
 
 
 def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, sampling: Sampling,
-                 counters: torch.Tensor | None = None):
-    """Render many (camera, optics) jobs in one persistent launch (nc_render_batch).
+                 counters: torch.Tensor | None = None, guide: "Guide | None" = None):
+    """Render many (camera, optics) jobs in one persistent launch (nc_render_batch,
+    or nc_render_batch_guided when a guide is given).
 
     Returns (sum, sumsq, offsets): flat float64 buffers holding the images one
     after the other, and each image's first element."""
@@ -339,9 +340,14 @@ def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, samplin
     s = torch.zeros(total, dtype=torch.float64, device=kc.device)
     s2 = torch.zeros_like(s)
     sm = _sampling(sampling)
-    _check(_lib.load().nc_render_batch(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
-                                       C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm), _ptr(s),
-                                       _ptr(s2), _ptr(counters)), ctx.handle)
+    if guide is None:
+        _check(_lib.load().nc_render_batch(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
+                                           C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm), _ptr(s),
+                                           _ptr(s2), _ptr(counters)), ctx.handle)
+    else:
+        _check(_lib.load().nc_render_batch_guided(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
+                                                  C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm),
+                                                  guide.handle, _ptr(s), _ptr(s2), _ptr(counters)), ctx.handle)
     return s, s2, offs
 
 

@@ -600,9 +600,10 @@ nc_status nc_collect_vertices(nc_ctx *ctx, const nc_grid *g, const float *d_kc, 
     return render_one(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, d_counters, nullptr, &cv);
 }
 
-nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
-                          const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *s, double *d_sum,
-                          double *d_sumsq, nc_counters *d_counters)
+static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
+                                     const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                                     const nc_sampling *s, const nc_guide *guide, double *d_sum, double *d_sumsq,
+                                     nc_counters *d_counters)
 {
     if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
     nc_status st = check_grid(ctx, g);
@@ -629,12 +630,33 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int3
             return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
         jobs[j] = make_job(cam, optics + j, out_offsets[j]);
     }
+    if (guide && guide->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
+    if (guide && !(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
+        return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
     DeviceGuard guard(ctx->device);
     hipError_t e = ensure_jobs(ctx, (size_t)n_jobs);
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), jobs.data(), n_jobs, *s, d_sum,
-                              d_sumsq, d_counters, (nc::JobView *)ctx->d_jobs);
+                              d_sumsq, d_counters, (nc::JobView *)ctx->d_jobs, guide, nullptr);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render batch");
+}
+
+nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
+                          const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *s, double *d_sum,
+                          double *d_sumsq, nc_counters *d_counters)
+{
+    return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, nullptr, d_sum, d_sumsq,
+                               d_counters);
+}
+
+nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
+                                 const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                                 const nc_sampling *s, const nc_guide *guide, double *d_sum, double *d_sumsq,
+                                 nc_counters *d_counters)
+{
+    if (!guide) return fail(ctx, NC_ERR_INVALID_ARG, "guide is NULL");
+    return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, guide, d_sum, d_sumsq,
+                               d_counters);
 }
 
 nc_status nc_get_launch(const nc_ctx *ctx, nc_launch *launch)
