@@ -28,6 +28,9 @@
  *   - Determinism: the same seed, sample offset and inputs reproduce every
  *     path exactly (counter-based Philox4x32-10 random numbers); FP64
  *     accumulations may differ in the last bits through atomic ordering.
+ *   - A context owns a small device scratch area (work-queue head, launch
+ *     parameters): calls on one context must not overlap in time on
+ *     different streams.  Use one context per stream for concurrent work.
  */
 #ifndef NCTRACE_H
 #define NCTRACE_H
@@ -423,7 +426,7 @@ nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *grid, const float *
 
 /* Launch-shape knobs of the path-tracing kernels (0 = library default). */
 typedef struct {
-    int32_t block;          /* threads per workgroup (multiple of 64) */
+    int32_t block;          /* threads per workgroup (multiple of 64, at most 256) */
     int32_t waves_per_cu;   /* resident waves per CU the persistent grid is sized for */
     int32_t samples_per_item; /* samples of one pixel taken by one lane per queue item */
     int32_t lds_levels;     /* top grid levels staged in LDS (-1: as many as fit) */

@@ -265,8 +265,8 @@ nc_status nc_set_launch(nc_ctx *ctx, const nc_launch *launch)
         ctx->launch = nc_launch{};
         return NC_OK;
     }
-    if (launch->block < 0 || launch->block > 1024 || (launch->block % 64) != 0)
-        return fail(ctx, NC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64,1024] (or 0)");
+    if (launch->block < 0 || launch->block > 256 || (launch->block % 64) != 0)
+        return fail(ctx, NC_ERR_INVALID_ARG, "block must be a multiple of 64 in [64,256] (or 0)");
     if (launch->waves_per_cu < 0 || launch->waves_per_cu > 32)
         return fail(ctx, NC_ERR_INVALID_ARG, "waves_per_cu must be in [0,32]");
     if (launch->samples_per_item < 0) return fail(ctx, NC_ERR_INVALID_ARG, "samples_per_item must be >= 0");
