@@ -62,12 +62,12 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 48-view x 4-sun batched launch")
     p.add_argument("--batch-spp", type=int, default=4)
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
-    p.add_argument("--collect-spp", type=int, default=4, help="plain samples per pixel whose vertices train the guide")
-    p.add_argument("--train-steps", type=int, default=6000)
-    p.add_argument("--train-batch", type=int, default=8192)
+    p.add_argument("--collect-spp", type=int, default=16, help="plain samples per pixel whose vertices train the guide")
+    p.add_argument("--train-steps", type=int, default=10000)
+    p.add_argument("--train-batch", type=int, default=65536)
     p.add_argument("--lr", type=float, default=3e-3)
-    p.add_argument("--guide-frac", type=float, default=0.35, help="probability of sampling the guide at a scattering")
-    p.add_argument("--guide-max-order", type=int, default=3, help="last guided scattering order (0: all)")
+    p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
+    p.add_argument("--guide-max-order", type=int, default=0, help="last guided scattering order (0: all)")
     p.add_argument("--no-variants", action="store_true", help="skip the grid variants (flat supercells, tau 0, global)")
     p.add_argument("--no-refinement", action="store_true", help="skip the refinement sweep (fields 128^2x40..1024^2x320)")
     p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
@@ -78,11 +78,14 @@ def parse():
     p.add_argument("--no-estimators", action="store_true", help="skip the comparison of sun-ray estimators")
     p.add_argument("--no-tau-sweep", action="store_true", help="skip the merge-threshold sweep")
     p.add_argument("--autotune", action="store_true", help="autotune the launch knobs before timing")
+    p.add_argument("--no-flux", action="store_true", help="skip the forward-photon / adjoint timing (cylinder cumulus)")
+    p.add_argument("--no-guide-kernels", action="store_true", help="skip the network training / inference timing")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
         a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
         a.no_progressive = a.no_ceiling = a.no_estimators = a.no_tau_sweep = True
+        a.no_flux = a.no_guide_kernels = True
     return a
 
 
@@ -214,6 +217,10 @@ def main():
         out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
     if not args.no_estimators:
         out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
+    if not args.no_flux:
+        out["flux"] = flux_run(ctx)
+    if not args.no_guide_kernels:
+        out["guide_kernels"] = guide_kernel_run(ctx, args)
     if args.workload == "cumulus" and not args.no_tau_sweep:
         out["tau_sweep"] = tau_sweep(ctx, sc, kc)
     if args.workload == "cumulus" and not args.no_variants:
@@ -283,6 +290,80 @@ def estimator_run(ctx, sc, kc, spp, build_ms):
         paths = cam.width * cam.height * spp
         res[name] = {"render_ms": ms, "paths_per_s": paths / (ms / 1e3), "rel_std_err": eps,
                      "time_to_1pct_s": (build_ms + ms) / 1e3 * (eps / 0.01) ** 2}
+    return res
+
+
+def flux_run(ctx):
+    """Forward photons and the adjoint replay on the cylinder cumulus (256^3,
+    sun at zenith, 10^7 photons onto 100 x 100 ground pixels)."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    sc = inputs.scene_cylinder()
+    kc = torch.from_numpy(sc.kc).cuda()
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    N = 10_000_000
+    smp = inputs.Sampling(seed=sc.sampling.seed + 81, spp=1)
+    api.flux(ctx, g, kc, sc.optics, (100, 100), 1 << 20, smp)        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tally, glob = api.flux(ctx, g, kc, sc.optics, (100, 100), N, smp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    grad = torch.ones((100, 100), dtype=torch.float64, device="cuda")
+    out = api.flux_adjoint(ctx, g, kc, sc.optics, (100, 100), N, smp, grad)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    f = 100 * 100 / N
+    T = tally[0].cpu().numpy() * f
+    return {"photons": N, "forward_ms": (t1 - t0) * 1e3, "adjoint_ms": (t2 - t1) * 1e3,
+            "photons_per_s": N / (t1 - t0), "mean_T": float(T.mean()),
+            "dmeanT_ds": float(out[0]) * f / 1e4, "dmeanT_dg": float(out[1]) * f / 1e4,
+            "dmeanT_dalpha": float(out[2]) * f / 1e4}
+
+
+def guide_kernel_run(ctx, args):
+    """The network's kernels: one Adam step on a batch, and inference, on the
+    matrix cores (7 -> 64 -> 64 -> 64 -> 40; 11.4 k MACs per record forward,
+    about three times that for a training step)."""
+    import torch
+
+    from paper_1902_01137_amd import api
+    gd = api.Guide(ctx, seed=3)
+    rng = np.random.default_rng(1)
+    n = 1 << 20
+    rec = np.zeros((n, 12), np.float32)
+    rec[:, :3] = rng.uniform(-1, 1, (n, 3))
+    d = rng.standard_normal((n, 3))
+    rec[:, 3:6] = d / np.linalg.norm(d, axis=1, keepdims=True)
+    rec[:, 6] = np.log1p(rng.exponential(20.0, n))
+    o = rng.standard_normal((n, 3))
+    rec[:, 7:10] = o / np.linalg.norm(o, axis=1, keepdims=True)
+    rec[:, 10] = 1.0
+    t = torch.from_numpy(rec).cuda()
+    macs = 7 * 64 + 64 * 64 * 2 + 64 * 40
+    res = {}
+    for batch in (8192, 65536):
+        b = t[:batch].contiguous()
+        for _ in range(5):
+            gd.train_step(b, 1e-4)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps = 200
+        for _ in range(steps):
+            gd.train_step(b, 1e-4)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        res["train_batch_%d" % batch] = {"step_ms": dt * 1e3, "records_per_s": batch / dt,
+                                         "TFLOP_per_s": 3 * 2 * macs * batch / dt / 1e12}
+    gd.forward(t)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    gd.forward(t)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    res["forward_1M"] = {"ms": dt * 1e3, "records_per_s": n / dt, "TFLOP_per_s": 2 * macs * n / dt / 1e12,
+                         "peak_bf16_TFLOP_per_s": 2500.0}
     return res
 
 

@@ -338,7 +338,9 @@ nc_status nc_render_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, 
  * probability guide_frac a direction from the vMF mixture q, else from HG(g)
  * about the incoming direction.  d_in: n rows of 8 floats (the 7 network
  * inputs, of which 3..5 are the incoming direction; one unused); d_u: n rows
- * of 4 uniforms in [0,1) (branch, lobe, cosine, azimuth); d_out: n rows of 8
+ * of 4 uniforms in [0,1): u0 picks the branch (mixture if u0 < guide_frac) and
+ * then u0 / guide_frac the lobe, u1 is ignored, u2 and u3 give the cosine and
+ * the azimuth (the renderer draws three numbers per step); d_out: n rows of 8
  * floats: new direction (3), weight factor p / (c q + (1 - c) p), q and p at
  * the new direction, 2 zeros.  All device float arrays. */
 nc_status nc_guide_sample(nc_ctx *ctx, const nc_guide *guide, const float *d_in, const float *d_u, int32_t n,

@@ -646,4 +646,17 @@ __device__ inline f32x4 mfma16(bf16x4 a, bf16x4 b, f32x4 c)
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
 }
 
+// v_mfma_f32_16x16x32_bf16 (gfx950): as above with eight k values per lane,
+// A[m][k] and B[k][n] from lane group l / 16 and element e alike, and the same
+// D layout.  Callers only rely on A and B pairing lane group and element the
+// same way (the order of k within a product is free).
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+
+__device__ inline f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c)
+{
+    typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                   0, 0);
+}
+
 }  // namespace nc

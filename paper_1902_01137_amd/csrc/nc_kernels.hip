@@ -316,7 +316,7 @@ __device__ inline float ratio_transmittance(const GridView &g, const NodeSrc &ns
 
 __global__ __launch_bounds__(256) void transmittance_kernel(TransArgs A)
 {
-    extern __shared__ float2 s_nodes[];
+    extern __shared__ __align__(16) float2 s_nodes[];
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     stage_levels(A.g, A.lds_first, A.lds_nodes, s_nodes, s_off);
     const NodeSrc ns{A.g.nodes, s_nodes, s_off, A.lds_first, s_off[A.lds_first <= A.g.L ? A.lds_first : 0],
@@ -461,6 +461,7 @@ struct RenderArgs {
     CollectView col;            // collection mode: where vertices go
     int col_spp;                // collection mode: samples per pixel (path slot = pix * spp + sample)
     int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
+    float gpos[3];              // network position input: (x - lo) * gpos - 1 spans [-1, 1] over the box
     nc_counters *counters;
     unsigned long long *queue;
     unsigned long long items;
@@ -472,6 +473,7 @@ struct RenderArgs {
 // (events, ray starts, new samples) thus runs for many lanes at once instead
 // of diverging inside every traversal step.
 enum Phase { kPhCross = 0, kPhCollide = 1, kPhEvent = 2, kPhRay = 3, kPhSample = 4, kPhGuide = 5, kPhIdle = 6 };
+constexpr int kGuideMaxWait = 8;   // trips a partial tile of guided lanes may wait for more
 enum RenderMode { kPlain = 0, kGuided = 1, kCollect = 2 };
 constexpr float kSunRoulette = 0.1f;   // ratio estimators: Russian roulette below this transmissivity
 static_assert(kPhGuide == 5 && kPhIdle == 6, "six running phases, one counter slot each");
@@ -536,91 +538,62 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// Guided scattering (one-sample MIS): with probability c draw the new
-// direction from the network's vMF mixture, otherwise from HG; the path
-// weight is multiplied by p_HG / (c q + (1 - c) p_HG).  zb: the 40 outputs
-// (bf16; the same rounded values define both the sampling and the density).
-__device__ inline void guided_turn(const short *zb, float c, float g, float u_sel, float u_lobe, float u1, float u2,
-                                   float pd[3], float &beta, float &q_out, float &p_out)
+// The network in LDS.  Layer 1 (7 inputs padded to 16) keeps W [out][in]
+// with rows padded to 20 bf16 and runs as 16x16x16 products.  Layers 2..4
+// (K = 64) run as two 16x16x32 products per 16-row block: the B operand of
+// k-block kb is the lane's own outputs of the previous layer's blocks 2 kb and
+// 2 kb + 1, so slot (lane group q, element e) of k-block kb stands for neuron
+// 16 (2 kb + e / 4) + 4 q + e % 4.  The weights are staged with their
+// columns in that order (rows of 72 bf16: 16-byte aligned fragment reads that
+// fall on distinct banks).  The last layer's 40 rows are also permuted, to 48:
+// lane group q of a tile column receives lobes 2 q and 2 q + 1, five values
+// each, in its first ten output slots (the last two are zero rows).
+constexpr int kW1Stride = 20, kWStride = 72;
+constexpr int kWOff[5] = {0, 64 * kW1Stride, 64 * kW1Stride + 64 * kWStride, 64 * kW1Stride + 2 * 64 * kWStride,
+                          64 * kW1Stride + 2 * 64 * kWStride + 48 * kWStride};
+constexpr int kBOff[4] = {0, 64, 128, 192};
+constexpr int kGuideWeightBytes = kWOff[4] * 2 + 240 * 4;                   // 28864
+// per wave: the tile's inputs ([16][16] bf16) and per-vertex floats ([16][8]:
+// incoming direction, the four uniforms of the step)
+constexpr int kGuideInBytes = 16 * 16 * 2;
+constexpr int kGuideScratchPerWave = kGuideInBytes + 16 * 8 * 4;           // 1024
+static_assert(kWOff[1] % 8 == 0 && kWOff[2] % 8 == 0 && kWOff[3] % 8 == 0 && kWOff[4] % 8 == 0,
+              "16-byte aligned weight blocks");
+
+// neuron k of a 64-wide layer -> its column in the K = 32 operand order
+__device__ inline int k32_col(int k)
 {
-    auto z = [zb](int i) { return from_bf16(zb[i]); };
-    float amax = z(0);
-#pragma unroll
-    for (int j = 1; j < kGuideLobes; ++j) amax = fmaxf(amax, z(5 * j));
-    float psum = 0.0f;
-#pragma unroll
-    for (int j = 0; j < kGuideLobes; ++j) psum += __expf(z(5 * j) - amax);
-    const float inv_psum = __builtin_amdgcn_rcpf(psum);
-    float nd[3] = {pd[0], pd[1], pd[2]};
-    if (u_sel < c) {
-        // lobe by its weight, then the stable vMF cosine inversion (Jakob 2012)
-        int pick = kGuideLobes - 1;
-        float cum = 0.0f;
-        const float target = u_lobe * psum;
-#pragma unroll
-        for (int j = 0; j < kGuideLobes; ++j) {
-            cum += __expf(z(5 * j) - amax);
-            if (target < cum && pick == kGuideLobes - 1 && j < kGuideLobes - 1) pick = j;
-        }
-        float m[3] = {z(5 * pick + 1), z(5 * pick + 2), z(5 * pick + 3)};
-        const float inv = rsqrtf(fmaxf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2], 1e-24f));
-        m[0] *= inv;
-        m[1] *= inv;
-        m[2] *= inv;
-        const float kap = __expf(fminf(fmaxf(z(5 * pick + 4), kLogKappaMin), kLogKappaMax));
-        const float t =
-            fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) * __builtin_amdgcn_rcpf(kap)));
-        nd[0] = m[0];
-        nd[1] = m[1];
-        nd[2] = m[2];
-        turn(nd, t, u2);
-    } else {
-        turn(nd, hg_sample_mu(g, u1), u2);
-    }
-    // mixture density of the chosen direction
-    float q = 0.0f;
-#pragma unroll
-    for (int j = 0; j < kGuideLobes; ++j) {
-        const float m0 = z(5 * j + 1), m1 = z(5 * j + 2), m2 = z(5 * j + 3);
-        const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
-        const float cw = (m0 * nd[0] + m1 * nd[1] + m2 * nd[2]) * inv;
-        const float kap = __expf(fminf(fmaxf(z(5 * j + 4), kLogKappaMin), kLogKappaMax));
-        // kappa >= e^-3, so 1 - exp(-2 kappa) >= 0.095 keeps its relative precision
-        const float norm = kap * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - __expf(-2.0f * kap)));
-        q += __expf(z(5 * j) - amax) * inv_psum * norm * __expf(kap * (cw - 1.0f));
-    }
-    const float php = hg_phase(g, pd[0] * nd[0] + pd[1] * nd[1] + pd[2] * nd[2]);
-    beta *= php * __builtin_amdgcn_rcpf(c * q + (1.0f - c) * php);
-    q_out = q;
-    p_out = php;
-    pd[0] = nd[0];
-    pd[1] = nd[1];
-    pd[2] = nd[2];
+    const int blk = k >> 4, r = k & 15;
+    return 32 * (blk >> 1) + 8 * (r >> 2) + 4 * (blk & 1) + (r & 3);
 }
 
-// The network in LDS.  Layer l's weights W_l [out][in] are staged once per
-// workgroup with rows padded by 4 bf16 (row strides of 20 and 68 elements
-// spread a fragment read over the banks), then the biases (fp32).  A wave's
-// tile is one [16][68] bf16 buffer: inputs in, outputs out.
-constexpr int kActStride = 68;
-constexpr int kWOff[5] = {0, 64 * 20, 64 * 20 + 64 * 68, 64 * 20 + 2 * 64 * 68, 64 * 20 + 2 * 64 * 68 + 48 * 68};
-constexpr int kBOff[4] = {0, 64, 128, 192};
-constexpr int kGuideWeightBytes = kWOff[4] * 2 + 240 * 4;                   // 27456
-constexpr int kGuideScratchPerWave = 16 * kActStride * 2;                   // 2176
-
-__device__ inline int w_stride(int l) { return l == 0 ? 20 : 68; }
+// permuted last-layer row m (0..47) -> network output index, or -1 (zero row)
+__device__ inline int out_row_src(int m)
+{
+    const int q = (m & 15) >> 2, s = 4 * (m >> 4) + (m & 3);
+    return s < 10 ? 5 * (2 * q + (s >= 5 ? 1 : 0)) + (s >= 5 ? s - 5 : s) : -1;
+}
 
 // Copy the packed network (W_pad [out_pad][in_pad] bf16 and fp32 biases per
-// layer) into the padded LDS layout; all threads of the block take part.
+// layer) into the LDS layout above; all threads of the block take part.
 __device__ inline void stage_guide(const GuideWeights &W, short *wl, float *bl)
 {
-    for (int l = 0; l < kGuideLayers; ++l) {
-        const int kin = l == 0 ? 16 : 64, nout = l == kGuideLayers - 1 ? 48 : 64, st = w_stride(l);
-        for (int i = threadIdx.x; i < nout * kin; i += blockDim.x) {
-            const int o = i / kin, k = i - o * kin;
-            wl[kWOff[l] + o * st + k] = W.w[l][i];
+    for (int i = threadIdx.x; i < 64 * 16; i += blockDim.x) wl[(i >> 4) * kW1Stride + (i & 15)] = W.w[0][i];
+    for (int l = 1; l < 3; ++l)
+        for (int i = threadIdx.x; i < 64 * 64; i += blockDim.x)
+            wl[kWOff[l] + (i >> 6) * kWStride + k32_col(i & 63)] = W.w[l][i];
+    for (int i = threadIdx.x; i < 48 * 64; i += blockDim.x) {
+        const int m = i >> 6, k = i & 63, src = out_row_src(m);
+        wl[kWOff[3] + m * kWStride + k32_col(k)] = src >= 0 ? W.w[3][src * 64 + k] : (short)0;
+    }
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        bl[kBOff[0] + i] = W.b[0][i];
+        bl[kBOff[1] + i] = W.b[1][i];
+        bl[kBOff[2] + i] = W.b[2][i];
+        if (i < 48) {
+            const int src = out_row_src(i);
+            bl[kBOff[3] + i] = src >= 0 ? W.b[3][src] : 0.0f;
         }
-        for (int i = threadIdx.x; i < nout; i += blockDim.x) bl[kBOff[l] + i] = W.b[l][i];
     }
 }
 
@@ -635,53 +608,207 @@ __device__ inline bf16x4 cvt_bf16x4(float a, float b, float c, float d)
     return r;
 }
 
-// One 16-neuron block of a layer for the 16 vertices of a tile, as D = W X^T:
-// the weights are the A operand (rows = output neurons), the activations the
-// B operand (columns = vertices).  Lane l supplies W[16 nt + l % 16][16 kt + 4 (l / 16) + i]
-// and X[vertex l % 16][16 kt + 4 (l / 16) + i], and receives
-// out[vertex l % 16][16 nt + 4 (l / 16) + i], which is exactly its B operand
-// for block kt = nt of the next layer: activations never leave the registers.
-template <int KT>
-__device__ inline f32x4 guide_block(const short *w, int st, int nt, const bf16x4 *x, int n, int kq)
+// A K = 64 layer for the 16 vertices of a tile is D = W X^T with the weights
+// as the A operand (rows = output neurons) and the activations as the B
+// operand (columns = vertices).  Lane l receives
+// out[vertex l % 16][16 nt + 4 (l / 16) + i] of block nt: the next layer's B slots.
+// Two 16-row blocks nt0, nt0 + 1 of a K = 64 layer: their four weight
+// fragments are read from LDS before the first product, so the read
+// latencies overlap instead of adding up (a whole layer at once would need
+// more registers than the renderer has to spare).
+__device__ inline void guide_pair32(const short *w, const float *b, int nt0, bf16x8 x0, bf16x8 x1, int n, int kq,
+                                    f32x4 &c0, f32x4 &c1)
 {
-    f32x4 c = {0.0f, 0.0f, 0.0f, 0.0f};
+    bf16x8 wa[4];
+    f32x4 bb[2];
 #pragma unroll
-    for (int kt = 0; kt < KT; ++kt)
-        c = mfma16(*reinterpret_cast<const bf16x4 *>(w + (nt * 16 + n) * st + kt * 16 + 4 * kq), x[kt], c);
-    return c;
-}
-
-template <int KT>
-__device__ inline void guide_hidden(const short *w, int st, const float *b, const bf16x4 *x, bf16x4 *y, int n, int kq)
-{
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const f32x4 c = guide_block<KT>(w, st, nt, x, n, kq);
-        const f32x4 bb = *reinterpret_cast<const f32x4 *>(b + nt * 16 + 4 * kq);
-        y[nt] = cvt_bf16x4(fmaxf(c[0] + bb[0], 0.0f), fmaxf(c[1] + bb[1], 0.0f), fmaxf(c[2] + bb[2], 0.0f),
-                           fmaxf(c[3] + bb[3], 0.0f));
+    for (int j = 0; j < 2; ++j) {
+        const short *row = w + ((nt0 + j) * 16 + n) * kWStride + 8 * kq;
+        wa[2 * j] = *reinterpret_cast<const bf16x8 *>(row);
+        wa[2 * j + 1] = *reinterpret_cast<const bf16x8 *>(row + 32);
+        bb[j] = *reinterpret_cast<const f32x4 *>(b + (nt0 + j) * 16 + 4 * kq);
     }
+    __builtin_amdgcn_sched_barrier(0);
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    c0 = mfma32(wa[1], x1, mfma32(wa[0], x0, zero)) + bb[0];
+    c1 = mfma32(wa[3], x1, mfma32(wa[2], x0, zero)) + bb[1];
 }
 
-// The network on one tile of 16 vertices held by one wave.  io: the wave's
-// [16][kActStride] bf16 tile; on entry row r holds vertex r's inputs in
-// columns 0..15, on exit its 40 outputs (bf16) in columns 0..39.
-__device__ inline void guide_tile_forward(const short *wl, const float *bl, short *io, int lane)
+__device__ inline bf16x4 relu_bf16x4(f32x4 c)
+{
+    return cvt_bf16x4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), fmaxf(c[3], 0.0f));
+}
+
+__device__ inline void guide_hidden32(const short *w, const float *b, const bf16x4 *x, bf16x4 *y, int n, int kq)
+{
+    const bf16x8 x0 = __builtin_shufflevector(x[0], x[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 x1 = __builtin_shufflevector(x[2], x[3], 0, 1, 2, 3, 4, 5, 6, 7);
+    f32x4 c0, c1;
+    guide_pair32(w, b, 0, x0, x1, n, kq, c0, c1);
+    y[0] = relu_bf16x4(c0);
+    y[1] = relu_bf16x4(c1);
+    guide_pair32(w, b, 2, x0, x1, n, kq, c0, c1);
+    y[2] = relu_bf16x4(c0);
+    y[3] = relu_bf16x4(c1);
+}
+
+// The network on one tile of 16 vertices held by one wave.  in: the tile's
+// [16][16] bf16 inputs (row = vertex, the 7 inputs then zeros).  On return
+// z[4 nt + i] (bf16-rounded) is permuted output row 16 nt + 4 (lane / 16) + i
+// of vertex lane % 16: z[0..4] and z[5..9] are lobes 2 (lane / 16) and
+// 2 (lane / 16) + 1 (logit, unnormalised mean, log kappa).
+__device__ inline void guide_tile_forward(const short *wl, const float *bl, const short *in, int lane, float z[12])
 {
     const int n = lane & 15, kq = lane >> 4;
     bf16x4 h[4], y[4];
-    h[0] = *reinterpret_cast<const bf16x4 *>(io + n * kActStride + 4 * kq);
-    guide_hidden<1>(wl + kWOff[0], 20, bl + kBOff[0], h, y, n, kq);
-    guide_hidden<4>(wl + kWOff[1], 68, bl + kBOff[1], y, h, n, kq);
-    guide_hidden<4>(wl + kWOff[2], 68, bl + kBOff[2], h, y, n, kq);
+    const bf16x4 x0 = *reinterpret_cast<const bf16x4 *>(in + n * 16 + 4 * kq);
+    bf16x4 w1[4];
+    f32x4 b1[4];
 #pragma unroll
-    for (int nt = 0; nt < 3; ++nt) {
-        const f32x4 c = guide_block<4>(wl + kWOff[3], 68, nt, y, n, kq);
-        const f32x4 bb = *reinterpret_cast<const f32x4 *>(bl + kBOff[3] + nt * 16 + 4 * kq);
-        *reinterpret_cast<bf16x4 *>(io + n * kActStride + nt * 16 + 4 * kq) =
-            cvt_bf16x4(c[0] + bb[0], c[1] + bb[1], c[2] + bb[2], c[3] + bb[3]);
+    for (int nt = 0; nt < 4; ++nt) {
+        w1[nt] = *reinterpret_cast<const bf16x4 *>(wl + (nt * 16 + n) * kW1Stride + 4 * kq);
+        b1[nt] = *reinterpret_cast<const f32x4 *>(bl + kBOff[0] + nt * 16 + 4 * kq);
     }
-    wave_sync();
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int nt = 0; nt < 4; ++nt) {
+        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+        const f32x4 c = mfma16(w1[nt], x0, zero);
+        y[nt] = cvt_bf16x4(fmaxf(c[0] + b1[nt][0], 0.0f), fmaxf(c[1] + b1[nt][1], 0.0f), fmaxf(c[2] + b1[nt][2], 0.0f),
+                           fmaxf(c[3] + b1[nt][3], 0.0f));
+    }
+    guide_hidden32(wl + kWOff[1], bl + kBOff[1], y, h, n, kq);
+    guide_hidden32(wl + kWOff[2], bl + kBOff[2], h, y, n, kq);
+    const bf16x8 y0 = __builtin_shufflevector(y[0], y[1], 0, 1, 2, 3, 4, 5, 6, 7);
+    const bf16x8 y1 = __builtin_shufflevector(y[2], y[3], 0, 1, 2, 3, 4, 5, 6, 7);
+    f32x4 c0, c1;
+    guide_pair32(wl + kWOff[3], bl + kBOff[3], 0, y0, y1, n, kq, c0, c1);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        z[i] = from_bf16(to_bf16(c0[i]));
+        z[4 + i] = from_bf16(to_bf16(c1[i]));
+    }
+    // rows 32..47: slots 8..11 (the last two are zero rows)
+    const short *row = wl + kWOff[3] + (32 + n) * kWStride + 8 * kq;
+    const bf16x8 wa0 = *reinterpret_cast<const bf16x8 *>(row), wa1 = *reinterpret_cast<const bf16x8 *>(row + 32);
+    const f32x4 b2 = *reinterpret_cast<const f32x4 *>(bl + kBOff[3] + 32 + 4 * kq);
+    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
+    const f32x4 c2 = mfma32(wa1, y1, mfma32(wa0, y0, zero)) + b2;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) z[8 + i] = from_bf16(to_bf16(c2[i]));
+}
+
+// Guided scattering (one-sample MIS): with probability c the new direction
+// comes from the network's vMF mixture, otherwise from HG; the path weight is
+// multiplied by p_HG / (c q + (1 - c) p_HG).  The step runs where the last
+// product leaves the outputs: the four lanes n, n + 16, n + 32, n + 48 of
+// tile column n hold two lobes each (z from guide_tile_forward).  The lobe
+// sums, the choice of lobe and the mixture density are shared across the four
+// lanes; all four end with the same direction and factor.  slot: the
+// column's floats (incoming direction, u_sel, u_lobe, u1, u2).  The whole
+// wave calls it.
+struct GuidedStep {
+    float d[3];   // new direction
+    float w;      // weight factor p / (c q + (1 - c) p)
+    float q, p;   // mixture and HG densities at d
+};
+
+// The value lane l ^ 16 (or l ^ 32) holds, by the gfx950 row swaps: of the
+// pair the swap returns, one is the lane's own value, the other its partner's
+// (equal bits make the choice immaterial).
+__device__ inline float lane_xor16(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(r[0] == u ? r[1] : r[0]);
+}
+
+__device__ inline float lane_xor32(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(r[0] == u ? r[1] : r[0]);
+}
+
+__device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, float g, int kq)
+{
+    float amax = fmaxf(z[0], z[5]);
+    amax = fmaxf(amax, lane_xor16(amax));
+    amax = fmaxf(amax, lane_xor32(amax));
+    const float e0 = __expf(z[0] - amax), e1 = __expf(z[5] - amax);
+    // the four group sums in lobe order, accumulated the same way in all four lanes
+    const float loc = e0 + e1, loc16 = lane_xor16(loc);
+    const float lev = (kq & 1) ? loc16 : loc, lod = (kq & 1) ? loc : loc16;   // groups 2 (kq / 2) and 2 (kq / 2) + 1
+    const float xev = lane_xor32(lev), xod = lane_xor32(lod);
+    const bool lowh = kq < 2;
+    const float l0 = lowh ? lev : xev, l1 = lowh ? lod : xod, l2 = lowh ? xev : lev, l3 = lowh ? xod : lod;
+    const float c1 = l0, c2 = c1 + l1, c3 = c2 + l2, psum = c3 + l3;
+    const float pd[3] = {slot[0], slot[1], slot[2]};
+    const float u_sel = slot[3], u_lobe = slot[4], u1 = slot[5], u2 = slot[6];
+    const bool mix = u_sel < c;
+    // the lobe: the first whose cumulative weight exceeds u_lobe * sum
+    const float target = u_lobe * psum;
+    const int qs = (target >= c1 ? 1 : 0) + (target >= c2 ? 1 : 0) + (target >= c3 ? 1 : 0);
+    // both candidates in every lane, without branches, so that their
+    // dependent chains interleave: the vMF draw from this lane's lobe that
+    // the choice would fall on (used only in lane group qs) and the HG draw
+    const float lo = kq == 0 ? 0.0f : kq == 1 ? c1 : kq == 2 ? c2 : c3;
+    const bool second = target >= lo + e0;
+    const float m[3] = {second ? z[6] : z[1], second ? z[7] : z[2], second ? z[8] : z[3]};
+    const float inv = rsqrtf(fmaxf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2], 1e-24f));
+    const float kap = __expf(fminf(fmaxf(second ? z[9] : z[4], kLogKappaMin), kLogKappaMax));
+    // the stable vMF cosine inversion (Jakob 2012)
+    const float t =
+        fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) * __builtin_amdgcn_rcpf(kap)));
+    float v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
+    turn(v, t, u2);
+    float hgd[3] = {pd[0], pd[1], pd[2]};
+    turn(hgd, hg_sample_mu(g, u1), u2);
+    GuidedStep o;
+    // the chosen lobe's direction from lane group qs of the column
+    const int rel = qs ^ kq;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        const float v16 = lane_xor16(v[a]), v32 = lane_xor32(v[a]), v48 = lane_xor32(v16);
+        const float vs = rel == 0 ? v[a] : rel == 1 ? v16 : rel == 2 ? v32 : v48;
+        o.d[a] = mix ? vs : hgd[a];
+    }
+    // mixture density at the new direction: two lobes per lane, then the column sum
+    float qp = 0.0f;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float m0 = z[5 * h + 1], m1 = z[5 * h + 2], m2 = z[5 * h + 3];
+        const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
+        const float cw = (m0 * o.d[0] + m1 * o.d[1] + m2 * o.d[2]) * inv;
+        const float kap = __expf(fminf(fmaxf(z[5 * h + 4], kLogKappaMin), kLogKappaMax));
+        // kappa >= e^-3, so 1 - exp(-2 kappa) >= 0.095 keeps its relative precision
+        const float norm = kap * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - __expf(-2.0f * kap)));
+        qp += (h == 0 ? e0 : e1) * norm * __expf(kap * (cw - 1.0f));
+    }
+    qp += lane_xor16(qp);   // a + b == b + a: the same sum in every lane of the column
+    qp += lane_xor32(qp);
+    o.q = qp * __builtin_amdgcn_rcpf(psum);
+    o.p = hg_phase(g, pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2]);
+    o.w = o.p * __builtin_amdgcn_rcpf(c * o.q + (1.0f - c) * o.p);
+    return o;
+}
+
+// The number that picks the lobe: given u_sel < c, u_sel / c is uniform on
+// [0, 1) and independent of the branch taken (unused otherwise).
+__device__ inline float lobe_uniform(float u_sel, float c)
+{
+    return fminf(u_sel * __builtin_amdgcn_rcpf(c), 0.99999994f);
+}
+
+// A tile row's inputs as bf16 (7 values, then zeros) in two 16-byte stores.
+__device__ inline void put_guide_inputs(short *row, const float x[7])
+{
+    bf16x8 a, b;
+    for (int k = 0; k < 7; ++k) a[k] = to_bf16(x[k]);
+    a[7] = 0;
+    for (int k = 0; k < 8; ++k) b[k] = 0;
+    reinterpret_cast<bf16x8 *>(row)[0] = a;
+    reinterpret_cast<bf16x8 *>(row)[1] = b;
 }
 
 // The renderer's guided scattering step on given vertices (one wave per 64):
@@ -694,33 +821,44 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
 {
     __shared__ __align__(16) short wl[kWOff[4]];
     __shared__ __align__(16) float bl[240];
-    __shared__ __align__(16) short act0[16 * kActStride];
+    __shared__ __align__(16) char tile[kGuideScratchPerWave];
     stage_guide(W, wl, bl);
     __syncthreads();
-    const int lane = threadIdx.x, mrow = lane & 15, kq = lane >> 4;
+    short *tin = reinterpret_cast<short *>(tile);
+    float *tf = reinterpret_cast<float *>(tile + kGuideInBytes);
+    const int lane = threadIdx.x, col = lane & 15, kq = lane >> 4;
     for (int base = blockIdx.x * 64; base < n; base += gridDim.x * 64) {
-        const int r = base + lane;
-        const bool active = r < n;
         for (int t = 0; t < 4; ++t) {
-            if (kq == t) {
-#pragma unroll
-                for (int k = 0; k < 16; ++k)
-                    act0[mrow * kActStride + k] = to_bf16(active && k < kGuideIn ? in[(size_t)r * 8 + k] : 0.0f);
+            const int r = base + 16 * t + col;
+            const bool valid = r < n;
+            if (kq == 0) {
+                float x[7];
+                for (int k = 0; k < 7; ++k) x[k] = valid ? in[(size_t)r * 8 + k] : 0.0f;
+                if (!valid) x[5] = 1.0f;
+                put_guide_inputs(tin + col * 16, x);
+                float *f = tf + col * 8;
+                f[0] = x[3];
+                f[1] = x[4];
+                f[2] = x[5];
+                const float u_sel = valid ? u[(size_t)r * 4] : 0.5f;
+                f[3] = u_sel;
+                f[4] = lobe_uniform(u_sel, c);
+                f[5] = valid ? u[(size_t)r * 4 + 2] : 0.5f;
+                f[6] = valid ? u[(size_t)r * 4 + 3] : 0.5f;
+                f[7] = 0.0f;
             }
             wave_sync();
-            guide_tile_forward(wl, bl, act0, lane);
-            if (kq == t && active) {
-                float pd[3] = {in[(size_t)r * 8 + 3], in[(size_t)r * 8 + 4], in[(size_t)r * 8 + 5]};
-                float beta = 1.0f, q = 0.0f, p = 0.0f;
-                const float *uu = u + (size_t)r * 4;
-                guided_turn(act0 + mrow * kActStride, c, g, uu[0], uu[1], uu[2], uu[3], pd, beta, q, p);
+            float z[12];
+            guide_tile_forward(wl, bl, tin, lane, z);
+            const GuidedStep st = guided_turn_tile(z, tf + col * 8, c, g, kq);
+            if (kq == 0 && valid) {
                 float *o = out + (size_t)r * 8;
-                o[0] = pd[0];
-                o[1] = pd[1];
-                o[2] = pd[2];
-                o[3] = beta;
-                o[4] = q;
-                o[5] = p;
+                o[0] = st.d[0];
+                o[1] = st.d[1];
+                o[2] = st.d[2];
+                o[3] = st.w;
+                o[4] = st.q;
+                o[5] = st.p;
                 o[6] = 0.0f;
                 o[7] = 0.0f;
             }
@@ -741,7 +879,7 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
 template <int kWavesPerEU, int kMode, int kSun>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
-    extern __shared__ float2 s_nodes[];
+    extern __shared__ __align__(16) float2 s_nodes[];
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     __shared__ unsigned long long s_cnt[kNumBlockCounters];
     for (int i = threadIdx.x; i < kNumBlockCounters; i += blockDim.x) s_cnt[i] = 0ull;
@@ -784,6 +922,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
     int chunk_left = 0;
     bool queue_done = false;
+    int guide_wait = 0;                  // wave-uniform: trips that lanes have waited for the network
 
     for (;;) {
         const int n_cross = __popcll(__ballot(phase == kPhCross));
@@ -791,12 +930,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         const int n_event = __popcll(__ballot(phase == kPhEvent));
         const int n_ray = __popcll(__ballot(phase == kPhRay));
         const int n_sample = __popcll(__ballot(phase == kPhSample));
-        if (n_cross + n_coll + n_event + n_ray + n_sample == 0) break;
+        const int n_guide = kMode == kGuided ? __popcll(__ballot(phase == kPhGuide)) : 0;
+        const int n_other = n_cross + n_coll + n_event + n_ray + n_sample;
+        if (n_other + n_guide == 0) break;
         int run = kPhCross, best = n_cross;
         if (n_coll >= best) { run = kPhCollide; best = n_coll; }
         if (n_event >= best) { run = kPhEvent; best = n_event; }
         if (n_ray >= best) { run = kPhRay; best = n_ray; }
         if (n_sample > best) { run = kPhSample; best = n_sample; }
+        if (kMode == kGuided && n_guide > 0) {
+            // lanes waiting for the network run as full tiles of 16; a partial
+            // tile only when nothing else is left or the wait grows long
+            const bool flush = n_other == 0 || guide_wait >= kGuideMaxWait;
+            if (n_guide >= 16 || flush) {
+                run = kPhGuide;
+                best = flush ? n_guide : (n_guide & ~15);
+                guide_wait = 0;
+            } else {
+                ++guide_wait;
+            }
+        }
         if (lane == 0) {
             atomicAdd(s_cnt + kCTrips0 + run, 1ull);
             atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
@@ -913,7 +1066,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             wave_count(s_cnt, kCTrunc, trunc);
         } else if (run == kPhEvent) {
             if (phase == kPhEvent) {
-                rng.need(3, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+                // three numbers cover an event (absorption, then two for the new
+                // direction); a guided step takes absorption plus three
+                rng.need(kMode == kGuided ? 4 : 3, (uint32_t)pix, A.sample_base + (uint32_t)s,
+                         A.stream_base + (uint32_t)job, A.key0, A.key1);
                 bool cont = false;               // go on to the scatter / reflect decision
                 if (shadow) {
                     if (res == kExit) Lp += beta * w_nee * (kSun != 0 ? t_sun : 1.0f);   // the sun ray got through
@@ -976,7 +1132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         phase = kPhSample;       // absorbed (volume) or not reflected (ground)
                     } else if (kMode == kGuided && !ground_ev &&
                                (A.guide_max_order == 0 || order <= A.guide_max_order)) {
-                        phase = kPhGuide;        // the network proposes the new direction
+                        phase = kPhGuide;        // the network proposes the new direction (a later trip)
                     } else {
                         const float u1 = rng.take(), u2 = rng.take();
                         const float win[3] = {pd[0], pd[1], pd[2]};
@@ -992,7 +1148,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                                 float *q = A.col.records + k * kGuideRecord;
 #pragma unroll
                                 for (int a = 0; a < 3; ++a) {
-                                    q[a] = 2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f;
+                                    q[a] = (r.o[a] - g.lo[a]) * A.gpos[a] - 1.0f;
                                     q[3 + a] = win[a];
                                     q[7 + a] = pd[a];
                                 }
@@ -1002,51 +1158,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                             }
                         }
                     }
-                }
-            }
-            if (kMode == kGuided && __ballot(phase == kPhGuide) != 0ull) {
-                const unsigned long long t_guide = wall_clock64();
-                // ---- lanes that scatter with guidance: network inference on the
-                // matrix cores, then MIS sampling, in the same trip.  The lanes are
-                // packed into tiles of 16 by their rank.
-                const bool active = phase == kPhGuide;
-                extern __shared__ float2 s_dyn[];
-                char *gb = reinterpret_cast<char *>(s_dyn) + A.guide_lds;
-                const short *wl = reinterpret_cast<const short *>(gb);
-                const float *bl = reinterpret_cast<const float *>(gb + kWOff[4] * 2);
-                short *act0 = reinterpret_cast<short *>(gb + kGuideWeightBytes + (threadIdx.x >> 6) * kGuideScratchPerWave);
-                if (active) rng.need(4, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
-                const unsigned long long want = __ballot(active);
-                const int rank = __popcll(want & ((1ull << lane) - 1ull));
-                const int ntiles = (__popcll(want) + 15) >> 4;
-                for (int t = 0; t < ntiles; ++t) {
-                    const bool owner = active && (rank >> 4) == t;
-                    const int row = rank & 15;
-                    if (owner) {
-                        short *x = act0 + row * kActStride;
-#pragma unroll
-                        for (int a = 0; a < 3; ++a) {
-                            x[a] = to_bf16(2.0f * (r.o[a] - g.lo[a]) * g.inv_h[a] / (float)g.n[a] - 1.0f);
-                            x[3 + a] = to_bf16(pd[a]);
-                        }
-                        x[6] = to_bf16(__logf(1.0f + kev));
-#pragma unroll
-                        for (int k = 7; k < 16; ++k) x[k] = 0;
-                    }
-                    wave_sync();
-                    guide_tile_forward(wl, bl, act0, lane);
-                    if (owner) {
-                        const float u_sel = rng.take(), u_lobe = rng.take(), u1 = rng.take(), u2 = rng.take();
-                        float q, p;
-                        guided_turn(act0 + row * kActStride, A.guide_frac, A.op.g, u_sel, u_lobe, u1, u2, pd, beta, q, p);
-                        phase = kPhRay;
-                    }
-                    wave_sync();
-                }
-                if (lane == 0) {
-                    atomicAdd(s_cnt + kCTrips0 + kPhGuide, 1ull);
-                    atomicAdd(s_cnt + kCLanes0 + kPhGuide, (unsigned long long)__popcll(want));
-                    atomicAdd(s_cnt + kCCycles0 + kPhGuide, (unsigned long long)(wall_clock64() - t_guide));
                 }
             }
         } else if (run == kPhRay) {
@@ -1067,6 +1178,62 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             wave_count(s_cnt, kCNee, active && shadow);
             wave_count(s_cnt, kCLeaf, hit);
+        } else if (kMode == kGuided && run == kPhGuide) {
+            // ---- guided scattering: network inference on the matrix cores,
+            // then the MIS step in the same layout.  The first `best` waiting
+            // lanes (by rank) are packed into tiles of 16.
+            const bool waiting = phase == kPhGuide;
+            const unsigned long long want = __ballot(waiting);
+            const int rank = __popcll(want & ((1ull << lane) - 1ull));
+            const bool active = waiting && rank < best;
+            extern __shared__ __align__(16) float2 s_dyn[];
+            char *gb = reinterpret_cast<char *>(s_dyn) + A.guide_lds;
+            const short *wl = reinterpret_cast<const short *>(gb);
+            const float *bl = reinterpret_cast<const float *>(gb + kWOff[4] * 2);
+            char *wt = gb + kGuideWeightBytes + (threadIdx.x >> 6) * kGuideScratchPerWave;
+            short *tin = reinterpret_cast<short *>(wt);
+            float *tf = reinterpret_cast<float *>(wt + kGuideInBytes);
+            const int ntiles = (best + 15) >> 4;
+            const int row = rank & 15, col = lane & 15, kq = lane >> 4;
+            for (int t = 0; t < ntiles; ++t) {
+                const bool owner = active && (rank >> 4) == t;
+                if (owner) {
+                    float x[7];
+#pragma unroll
+                    for (int a = 0; a < 3; ++a) {
+                        x[a] = (r.o[a] - g.lo[a]) * A.gpos[a] - 1.0f;
+                        x[3 + a] = pd[a];
+                    }
+                    x[6] = __logf(1.0f + kev);
+                    put_guide_inputs(tin + row * 16, x);
+                    // the event trip left three numbers for this step
+                    float *f = tf + row * 8;
+                    const float u_sel = rng.take();
+                    f[0] = pd[0];
+                    f[1] = pd[1];
+                    f[2] = pd[2];
+                    f[3] = u_sel;
+                    f[4] = lobe_uniform(u_sel, A.guide_frac);
+                    f[5] = rng.take();   // u1
+                    f[6] = rng.take();   // u2
+                }
+                wave_sync();
+                float z[12];
+                guide_tile_forward(wl, bl, tin, lane, z);
+                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.g, kq);
+                // each owner takes its column's result
+                const int src = owner ? row : lane;
+                const float d0 = __shfl(st.d[0], src), d1 = __shfl(st.d[1], src), d2 = __shfl(st.d[2], src);
+                const float wf = __shfl(st.w, src);
+                if (owner) {
+                    pd[0] = d0;
+                    pd[1] = d1;
+                    pd[2] = d2;
+                    beta *= wf;
+                    phase = kPhRay;
+                }
+                wave_sync();
+            }
         } else {
             // ---- finish the lane's path, then start its next sample or item
             bool need_item = false;
@@ -1289,6 +1456,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.lds_nodes = sh.lds_nodes;
     const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
     A.guide_lds = (int)node_bytes;
+    for (int a = 0; a < 3; ++a) A.gpos[a] = (float)(2.0 / ((double)g->n[a] * g->h[a]));
     A.guide_frac = s.guide_frac;
     A.guide_max_order = (int)std::min<uint32_t>(s.guide_max_order, 1u << 30);
     A.col_spp = s.spp;

@@ -167,7 +167,7 @@ def test_autograd_function():
     t = tally.cpu().numpy()
     f = 100 * 100 / N
     wn = w.cpu().numpy()
-    assert float(L) == pytest.approx((wn * t[0]).sum() * f, rel=1e-12)
+    assert float(L.detach()) == pytest.approx((wn * t[0]).sum() * f, rel=1e-12)
     assert float(s.grad) == pytest.approx((wn * t[3]).sum() * f, rel=1e-9)
     assert float(gg.grad) == pytest.approx((wn * t[5]).sum() * f, rel=1e-9)
     assert float(aa.grad) == pytest.approx((wn * t[7]).sum() * f, rel=1e-9)
