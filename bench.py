@@ -62,8 +62,9 @@ def parse():
     p.add_argument("--no-batch", action="store_true", help="skip the 48-view x 4-sun batched launch")
     p.add_argument("--batch-spp", type=int, default=4)
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
-    p.add_argument("--collect-spp", type=int, default=16, help="plain samples per pixel whose vertices train the guide")
-    p.add_argument("--train-steps", type=int, default=10000)
+    p.add_argument("--collect-spp", type=int, default=64, help="plain samples per pixel whose vertices train the guide")
+    p.add_argument("--train-steps", type=int, default=40000)
+    p.add_argument("--batch-train-steps", type=int, default=10000, help="Adam steps of each per-sun network of the batch")
     p.add_argument("--train-batch", type=int, default=65536)
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
@@ -324,7 +325,7 @@ def flux_run(ctx):
 
 def guide_kernel_run(ctx, args):
     """The network's kernels: one Adam step on a batch, and inference, on the
-    matrix cores (7 -> 64 -> 64 -> 64 -> 40; 11.4 k MACs per record forward,
+    matrix cores (15 -> 64 -> 64 -> 64 -> 40; 11.9 k MACs per record forward,
     about three times that for a training step)."""
     import torch
 
@@ -341,7 +342,7 @@ def guide_kernel_run(ctx, args):
     rec[:, 7:10] = o / np.linalg.norm(o, axis=1, keepdims=True)
     rec[:, 10] = 1.0
     t = torch.from_numpy(rec).cuda()
-    macs = 7 * 64 + 64 * 64 * 2 + 64 * 40
+    macs = 15 * 64 + 64 * 64 * 2 + 64 * 40
     res = {}
     for batch in (8192, 65536):
         b = t[:batch].contiguous()
@@ -505,6 +506,7 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
             losses.append(l)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
+    del rec
     smp = inputs.Sampling(seed=sc.sampling.seed + 202, spp=spp, flags=FLAGS, guide_frac=args.guide_frac,
                           guide_max_order=args.guide_max_order)
     api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)         # warm-up
@@ -585,14 +587,14 @@ def batch_guided_run(ctx, sc, kc, spp, args):
         op = inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})
         cam = max((c for c, z in views if z == sz), key=lambda c: c.width * c.height)
         rec, n, _, _ = api.collect_vertices(ctx, g, kc, op, cam,
-                                            inputs.Sampling(seed=sc.sampling.seed + 301, spp=4, flags=FLAGS),
-                                            cam.width * cam.height * 4 * 16)
+                                            inputs.Sampling(seed=sc.sampling.seed + 301, spp=16, flags=FLAGS),
+                                            cam.width * cam.height * 16 * 16)
         gd = api.Guide(ctx, seed=1)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(1)
-        for it in range(args.train_steps):
+        for it in range(args.batch_train_steps):
             idx = torch.randint(0, rec.shape[0], (args.train_batch,), device="cuda", generator=gen)
-            gd.train_step(rec[idx], args.lr * (0.2 if it >= 0.8 * args.train_steps else 1.0))
+            gd.train_step(rec[idx], args.lr * (0.2 if it >= 0.8 * args.batch_train_steps else 1.0))
         guides[sz] = gd
         del rec
     torch.cuda.synchronize()

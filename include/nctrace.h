@@ -286,19 +286,21 @@ nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, c
 
 /* ---------------------------------------------------------------------------
  * Learned proposal for scattering directions (path guiding).  An MLP
- * 7 -> 64 -> 64 -> 64 -> 40 (ReLU) maps a scattering vertex to a mixture of
- * 8 von Mises-Fisher lobes over the outgoing direction; its inputs are the
- * position normalised to [-1, 1]^3 over the field's box, the incoming
- * direction, and ln(1 + k / 1 km^-1) at the vertex.  Output j*5 + {0,1,2,3,4}:
+ * 15 -> 64 -> 64 -> 64 -> 40 (ReLU) maps a scattering vertex to a mixture of
+ * 8 von Mises-Fisher lobes over the outgoing direction.  A vertex is 7
+ * values: the position normalised to [-1, 1]^3 over the field's box, the
+ * incoming direction, and ln(1 + k / 1 km^-1) at the vertex; the network's
+ * 15 inputs are those 7, then sin and cos of 8 pi x, 8 pi y, 16 pi x and
+ * 16 pi y of the normalised position.  Output j*5 + {0,1,2,3,4}:
  * lobe logit, unnormalised mean direction (3), log concentration (clamped to
  * [-3, 8]).  Products run in bf16 on the matrix cores with fp32
  * accumulation; master weights and Adam moments are fp32.  Parameters are
- * flat fp32, layer by layer: W [out][in] row-major, then b [out] (11432).
- * A training record is 12 floats: inputs (7), outgoing direction (3),
+ * flat fp32, layer by layer: W [out][in] row-major, then b [out] (11944).
+ * A training record is 12 floats: vertex values (7), outgoing direction (3),
  * weight (1), unused (1); the loss is -sum w ln q(w_out) / sum w.
  * ------------------------------------------------------------------------- */
 typedef struct nc_guide nc_guide;
-#define NC_GUIDE_PARAMS 11432
+#define NC_GUIDE_PARAMS 11944
 #define NC_GUIDE_RECORD 12
 
 /* New network with He-uniform weights from `seed` and zero biases. */
@@ -336,8 +338,8 @@ nc_status nc_render_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, 
 /* The guided scattering step of nc_render_guided on n given vertices (for
  * testing and inspection): the network on the matrix cores, then with
  * probability guide_frac a direction from the vMF mixture q, else from HG(g)
- * about the incoming direction.  d_in: n rows of 8 floats (the 7 network
- * inputs, of which 3..5 are the incoming direction; one unused); d_u: n rows
+ * about the incoming direction.  d_in: n rows of 8 floats (the vertex's 7
+ * values, of which 3..5 are the incoming direction; one unused); d_u: n rows
  * of 4 uniforms in [0,1): u0 picks the branch (mixture if u0 < guide_frac) and
  * then u0 / guide_frac the lobe, u1 is ignored, u2 and u3 give the cosine and
  * the azimuth (the renderer draws three numbers per step); d_out: n rows of 8

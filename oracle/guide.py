@@ -12,9 +12,14 @@ Everything here is plain numpy in float64 on inputs and weights first
 rounded to bfloat16 (the precision the GPU kernels store them in).  This file
 shares no code with the HIP path.
 
-Network: 7 -> 64 -> 64 -> 64 -> 8*5, ReLU on the hidden layers.  Output lobe
-j: (logit a_j, m_j in R^3, log kappa_j); weights pi = softmax(a), mean
-direction mu_j = m_j / |m_j|, concentration kappa_j = exp(clamp(s_j)).
+Network: 15 -> 64 -> 64 -> 64 -> 8*5, ReLU on the hidden layers.  Its 15
+inputs are the vertex's 7 values (position scaled to [-1, 1]^3, incoming
+direction, ln(1 + k)) followed by 8 features of the horizontal position,
+sin and cos of 8 pi x, 8 pi y, 16 pi x and 16 pi y (a fixed Fourier
+encoding, after Tancik et al. 2020, that lets a small MLP resolve the
+kilometre-scale structure of a cloud field).  Output lobe j: (logit a_j,
+m_j in R^3, log kappa_j); weights pi = softmax(a), mean direction
+mu_j = m_j / |m_j|, concentration kappa_j = exp(clamp(s_j)).
 """
 from __future__ import annotations
 
@@ -22,7 +27,8 @@ import math
 
 import numpy as np
 
-N_IN, WIDTH, DEPTH, N_LOBES = 7, 64, 3, 8
+N_RAW, N_FEAT, WIDTH, DEPTH, N_LOBES = 7, 8, 64, 3, 8
+N_IN = N_RAW + N_FEAT
 N_OUT = 5 * N_LOBES
 LOG_KAPPA_MIN, LOG_KAPPA_MAX = -3.0, 8.0
 
@@ -72,13 +78,22 @@ def init_params(seed):
     return np.concatenate(parts).astype(np.float32)
 
 
+def features(X):
+    """The network's 15 inputs from the vertex's 7 (n, 7) -> (n, 15)."""
+    X = np.asarray(X, dtype=np.float64)
+    x, y = X[:, 0], X[:, 1]
+    enc = [f(math.pi * k * v) for k in (8.0, 16.0) for v in (x, y) for f in (np.sin, np.cos)]
+    return np.concatenate([X[:, :N_RAW], np.stack(enc, axis=1)], axis=1)
+
+
 def forward(params, X):
     """MLP output (n, 40) and the per-layer pre-activations (for backward).
 
-    Weights and the input are rounded to bfloat16, hidden activations too
-    (the GPU feeds them to the next bf16 product); arithmetic is float64."""
+    X: the vertices' 7 inputs.  Weights and the network inputs are rounded to
+    bfloat16, hidden activations too (the GPU feeds them to the next bf16
+    product); arithmetic is float64."""
     layers = unpack(bf16_round(params))
-    h = bf16_round(X)
+    h = bf16_round(features(X))
     cache = [h]
     for li, (W, b) in enumerate(layers):
         z = h @ W.T + b

@@ -804,7 +804,7 @@ nc_status nc_guide_create(nc_ctx *ctx, uint64_t seed, nc_guide **out)
         z ^= z >> 31;
         return (double)(z >> 11) * (1.0 / 9007199254740992.0);
     };
-    const int ins[4] = {7, 64, 64, 64}, outs[4] = {64, 64, 64, 40};
+    const int ins[4] = {nc::kGuideIn, 64, 64, 64}, outs[4] = {64, 64, 64, 40};
     size_t k = 0;
     for (int l = 0; l < 4; ++l) {
         const double lim = std::sqrt(6.0 / ins[l]);
@@ -878,7 +878,7 @@ nc_status nc_guide_forward(nc_ctx *ctx, const nc_guide *gd, const float *d_in, i
 {
     nc_status st = guide_check(ctx, gd);
     if (st != NC_OK) return st;
-    if (n < 0 || stride < nc::kGuideIn) return fail(ctx, NC_ERR_INVALID_ARG, "bad size or stride");
+    if (n < 0 || stride < nc::kGuideRaw) return fail(ctx, NC_ERR_INVALID_ARG, "bad size or stride");
     if (n == 0) return NC_OK;
     if (!d_in || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     DeviceGuard guard(ctx->device);

@@ -408,14 +408,15 @@ __device__ inline float hg_sample_mu(float g, float xi)
 // Orthonormal basis around unit n (Duff et al., "Building an orthonormal
 // basis, revisited", JCGT 2017), then the direction at cosine mu, azimuth
 // 2 pi u about n.
-__device__ inline void turn(float d[3], float mu, float u)
+// (sp, cp: sine and cosine of the azimuth; the final normalisation absorbs the
+// rounding of the basis.)
+__device__ inline void turn_sc(float d[3], float mu, float sp, float cp)
 {
     const float sgn = copysignf(1.0f, d[2]);
-    const float a = -1.0f / (sgn + d[2]);
+    const float a = -__builtin_amdgcn_rcpf(sgn + d[2]);
     const float b = d[0] * d[1] * a;
     const float b1[3] = {1.0f + sgn * d[0] * d[0] * a, sgn * b, -sgn * d[0]};
     const float b2[3] = {b, sgn + d[1] * d[1] * a, -d[1]};
-    const float sp = __builtin_amdgcn_sinf(u), cp = __builtin_amdgcn_cosf(u);   // sin, cos of 2 pi u
     const float st = __builtin_amdgcn_sqrtf(fmaxf(0.0f, 1.0f - mu * mu));
     float n[3];
 #pragma unroll
@@ -423,6 +424,11 @@ __device__ inline void turn(float d[3], float mu, float u)
     const float inv = rsqrtf(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
 #pragma unroll
     for (int k = 0; k < 3; ++k) d[k] = n[k] * inv;
+}
+
+__device__ inline void turn(float d[3], float mu, float u)
+{
+    turn_sc(d, mu, __builtin_amdgcn_sinf(u), __builtin_amdgcn_cosf(u));   // sin, cos of 2 pi u
 }
 
 // Cosine-weighted direction about +z (Lambertian reflection).

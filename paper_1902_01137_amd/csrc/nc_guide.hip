@@ -3,8 +3,9 @@
 // von Mises-Fisher lobes over the outgoing direction, trained on the
 // tracer's own vertices by weighted maximum likelihood.
 //
-// Network 7 -> 64 -> 64 -> 64 -> 40 (8 lobes x (logit, mean direction 3,
-// log concentration)), ReLU on hidden layers.  Products run on the matrix
+// Network 15 -> 64 -> 64 -> 64 -> 40 (8 lobes x (logit, mean direction 3,
+// log concentration)), ReLU on hidden layers; its inputs are a vertex's 7
+// values and 8 Fourier features of its horizontal position (guide_feature).  Products run on the matrix
 // cores (v_mfma_f32_16x16x16_bf16: bf16 operands, fp32 accumulation); master
 // weights, Adam moments and gradients are fp32.  Padded layer shapes (in x
 // out): 16x64, 64x64, 64x64, 64x48.
@@ -42,7 +43,8 @@ static int param_offset(int l)
 // ---------------------------------------------------------------------------
 // Forward over tiles of 16 records.  One wave per block; the tile's hidden
 // activations go through LDS between layers.  X: records as rows of
-// `rec_stride` floats, the 7 inputs first.  Outputs: Z (n x 48, fp32, before
+// `rec_stride` floats, the vertex's 7 values first (the 15 network inputs
+// are formed from them).  Outputs: Z (n x 48, fp32, before
 // any activation of the last layer) and, for training, the hidden
 // activations H_l (n x 64, fp32, after ReLU) of layers 0..2.
 // ---------------------------------------------------------------------------
@@ -61,7 +63,7 @@ __global__ __launch_bounds__(64) void guide_forward_kernel(GuideWeights W, const
         for (int e = l; e < 16 * 16; e += 64) {
             const int m = e >> 4, k = e & 15;
             const int r = r0 + m;
-            act[m][k] = (r < n && k < kGuideIn) ? X[(size_t)r * rec_stride + k] : 0.0f;
+            act[m][k] = (r < n && k < kGuideIn) ? guide_feature(X + (size_t)r * rec_stride, k) : 0.0f;
         }
         __syncthreads();
         for (int layer = 0; layer < kGuideLayers; ++layer) {
@@ -236,7 +238,7 @@ __global__ __launch_bounds__(64) void guide_backprop_kernel(const short *__restr
 __global__ __launch_bounds__(64) void guide_wgrad_kernel(const float *__restrict__ dZ, int out_pad, int out_n,
                                                          const float *__restrict__ H, int h_stride, int in_n,
                                                          int in_pad, int n, int chunk, float *__restrict__ gW,
-                                                         float *__restrict__ gb)
+                                                         float *__restrict__ gb, int features)
 {
     const int l = threadIdx.x;
     const int mrow = l & 15, kq = l >> 4;
@@ -252,7 +254,10 @@ __global__ __launch_bounds__(64) void guide_wgrad_kernel(const float *__restrict
             const bool ok = r < rend;
             const int col = it * 16 + mrow;
             const float dz = ok ? dZ[(size_t)r * out_pad + ot * 16 + mrow] : 0.0f;     // A[m=o][k=r]
-            const float hv = (ok && col < in_n) ? H[(size_t)r * h_stride + col] : 0.0f; // B[k=r][n=i]
+            // B[k=r][n=i]: layer 0 reads the records and forms the network inputs
+            const float hv = !(ok && col < in_n) ? 0.0f
+                             : features ? guide_feature(H + (size_t)r * h_stride, col)
+                                        : H[(size_t)r * h_stride + col];
             a[i] = to_bf16(dz);
             b[i] = to_bf16(hv);
             if (it == 0) bsum += dz;
@@ -396,7 +401,7 @@ hipError_t guide_train_step(const nc_ctx *ctx, nc_guide *gd, const float *rec, i
         float *gW = gd->d_grad + param_offset(l);
         float *gb = gW + (size_t)on * in_n;
         hipLaunchKernelGGL(guide_wgrad_kernel, grid, dim3(64), 0, ctx->stream, dZ_cur, out_pad, on, Hin, hstride,
-                           in_n, ip, n, chunk, gW, gb);
+                           in_n, ip, n, chunk, gW, gb, l == 0 ? 1 : 0);
         if (l > 0) {
             hipLaunchKernelGGL(guide_backprop_kernel, dim3(tiles), dim3(64), 0, ctx->stream,
                                (const short *)gd->d_wt[l], out_pad, dZ_cur, (const float *)H[l - 1], dZh[l - 1], n);

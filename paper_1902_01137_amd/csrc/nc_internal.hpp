@@ -34,12 +34,24 @@ struct nc_grid {
 };
 
 namespace nc {
-constexpr int kGuideIn = 7;
+constexpr int kGuideRaw = 7;    // a vertex's inputs: position in [-1, 1]^3, incoming direction, ln(1 + k)
+constexpr int kGuideIn = 15;    // the network's: those 7, then 8 features of the horizontal position
+
+// Network input k (0..14) from a vertex's 7 values x: x[k] for k < 7, then
+// sin and cos of 8 pi x, 8 pi y, 16 pi x, 16 pi y (a fixed Fourier encoding
+// of the position; v_sin / v_cos take revolutions).
+__device__ inline float guide_feature(const float *x, int k)
+{
+    if (k < kGuideRaw) return x[k];
+    const int j = k - kGuideRaw;
+    const float v = x[(j >> 1) & 1] * (j < 4 ? 4.0f : 8.0f);
+    return (j & 1) ? __builtin_amdgcn_cosf(v) : __builtin_amdgcn_sinf(v);
+}
 constexpr int kGuideWidth = 64;
 constexpr int kGuideLayers = 4;
 constexpr int kGuideLobes = 8;
 constexpr int kGuideOut = 5 * kGuideLobes;
-constexpr int kGuideParams = 7 * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 40 + 40;   // 11432
+constexpr int kGuideParams = kGuideIn * 64 + 64 + 2 * (64 * 64 + 64) + 64 * 40 + 40;   // 11944
 constexpr int kGuideRecord = 12;   // floats per training record
 constexpr float kLogKappaMin = -3.0f, kLogKappaMax = 8.0f;
 }  // namespace nc

@@ -538,7 +538,7 @@ __device__ inline void wave_sync()
     __builtin_amdgcn_wave_barrier();
 }
 
-// The network in LDS.  Layer 1 (7 inputs padded to 16) keeps W [out][in]
+// The network in LDS.  Layer 1 (15 inputs padded to 16) keeps W [out][in]
 // with rows padded to 20 bf16 and runs as 16x16x16 products.  Layers 2..4
 // (K = 64) run as two 16x16x32 products per 16-row block: the B operand of
 // k-block kb is the lane's own outputs of the previous layer's blocks 2 kb and
@@ -612,6 +612,11 @@ __device__ inline bf16x4 cvt_bf16x4(float a, float b, float c, float d)
 // as the A operand (rows = output neurons) and the activations as the B
 // operand (columns = vertices).  Lane l receives
 // out[vertex l % 16][16 nt + 4 (l / 16) + i] of block nt: the next layer's B slots.
+__device__ inline bf16x4 relu_bf16x4(f32x4 c)
+{
+    return cvt_bf16x4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), fmaxf(c[3], 0.0f));
+}
+
 // Two 16-row blocks nt0, nt0 + 1 of a K = 64 layer: their four weight
 // fragments are read from LDS before the first product, so the read
 // latencies overlap instead of adding up (a whole layer at once would need
@@ -629,14 +634,9 @@ __device__ inline void guide_pair32(const short *w, const float *b, int nt0, bf1
         bb[j] = *reinterpret_cast<const f32x4 *>(b + (nt0 + j) * 16 + 4 * kq);
     }
     __builtin_amdgcn_sched_barrier(0);
-    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    c0 = mfma32(wa[1], x1, mfma32(wa[0], x0, zero)) + bb[0];
-    c1 = mfma32(wa[3], x1, mfma32(wa[2], x0, zero)) + bb[1];
-}
-
-__device__ inline bf16x4 relu_bf16x4(f32x4 c)
-{
-    return cvt_bf16x4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), fmaxf(c[3], 0.0f));
+    // the bias is the accumulator's starting value
+    c0 = mfma32(wa[1], x1, mfma32(wa[0], x0, bb[0]));
+    c1 = mfma32(wa[3], x1, mfma32(wa[2], x0, bb[1]));
 }
 
 __device__ inline void guide_hidden32(const short *w, const float *b, const bf16x4 *x, bf16x4 *y, int n, int kq)
@@ -653,7 +653,7 @@ __device__ inline void guide_hidden32(const short *w, const float *b, const bf16
 }
 
 // The network on one tile of 16 vertices held by one wave.  in: the tile's
-// [16][16] bf16 inputs (row = vertex, the 7 inputs then zeros).  On return
+// [16][16] bf16 inputs (row = vertex, the 15 network inputs then a zero).  On return
 // z[4 nt + i] (bf16-rounded) is permuted output row 16 nt + 4 (lane / 16) + i
 // of vertex lane % 16: z[0..4] and z[5..9] are lobes 2 (lane / 16) and
 // 2 (lane / 16) + 1 (logit, unnormalised mean, log kappa).
@@ -671,12 +671,7 @@ __device__ inline void guide_tile_forward(const short *wl, const float *bl, cons
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-        const f32x4 c = mfma16(w1[nt], x0, zero);
-        y[nt] = cvt_bf16x4(fmaxf(c[0] + b1[nt][0], 0.0f), fmaxf(c[1] + b1[nt][1], 0.0f), fmaxf(c[2] + b1[nt][2], 0.0f),
-                           fmaxf(c[3] + b1[nt][3], 0.0f));
-    }
+    for (int nt = 0; nt < 4; ++nt) y[nt] = relu_bf16x4(mfma16(w1[nt], x0, b1[nt]));
     guide_hidden32(wl + kWOff[1], bl + kBOff[1], y, h, n, kq);
     guide_hidden32(wl + kWOff[2], bl + kBOff[2], h, y, n, kq);
     const bf16x8 y0 = __builtin_shufflevector(y[0], y[1], 0, 1, 2, 3, 4, 5, 6, 7);
@@ -692,8 +687,7 @@ __device__ inline void guide_tile_forward(const short *wl, const float *bl, cons
     const short *row = wl + kWOff[3] + (32 + n) * kWStride + 8 * kq;
     const bf16x8 wa0 = *reinterpret_cast<const bf16x8 *>(row), wa1 = *reinterpret_cast<const bf16x8 *>(row + 32);
     const f32x4 b2 = *reinterpret_cast<const f32x4 *>(bl + kBOff[3] + 32 + 4 * kq);
-    const f32x4 zero = {0.0f, 0.0f, 0.0f, 0.0f};
-    const f32x4 c2 = mfma32(wa1, y1, mfma32(wa0, y0, zero)) + b2;
+    const f32x4 c2 = mfma32(wa1, y1, mfma32(wa0, y0, b2));
 #pragma unroll
     for (int i = 0; i < 4; ++i) z[8 + i] = from_bf16(to_bf16(c2[i]));
 }
@@ -730,11 +724,39 @@ __device__ inline float lane_xor32(float v)
     return __uint_as_float(r[0] == u ? r[1] : r[0]);
 }
 
+// Sum and maximum of the lane's value and that of lane l ^ 16 (l ^ 32): the
+// swap returns both values, in the same order in the two lanes of a pair.
+__device__ inline float lane_sum16(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ inline float lane_sum32(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ inline float lane_max16(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane16_swap(u, u, false, false);
+    return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
+__device__ inline float lane_max32(float v)
+{
+    const uint32_t u = __float_as_uint(v);
+    const auto r = __builtin_amdgcn_permlane32_swap(u, u, false, false);
+    return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+
 __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, float g, int kq)
 {
-    float amax = fmaxf(z[0], z[5]);
-    amax = fmaxf(amax, lane_xor16(amax));
-    amax = fmaxf(amax, lane_xor32(amax));
+    const float amax = lane_max32(lane_max16(fmaxf(z[0], z[5])));
     const float e0 = __expf(z[0] - amax), e1 = __expf(z[5] - amax);
     // the four group sums in lobe order, accumulated the same way in all four lanes
     const float loc = e0 + e1, loc16 = lane_xor16(loc);
@@ -760,10 +782,11 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     // the stable vMF cosine inversion (Jakob 2012)
     const float t =
         fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) * __builtin_amdgcn_rcpf(kap)));
+    const float sp = __builtin_amdgcn_sinf(u2), cp = __builtin_amdgcn_cosf(u2);   // the azimuth of both candidates
     float v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
-    turn(v, t, u2);
+    turn_sc(v, t, sp, cp);
     float hgd[3] = {pd[0], pd[1], pd[2]};
-    turn(hgd, hg_sample_mu(g, u1), u2);
+    turn_sc(hgd, hg_sample_mu(g, u1), sp, cp);
     GuidedStep o;
     // the chosen lobe's direction from lane group qs of the column
     const int rel = qs ^ kq;
@@ -785,8 +808,7 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
         const float norm = kap * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - __expf(-2.0f * kap)));
         qp += (h == 0 ? e0 : e1) * norm * __expf(kap * (cw - 1.0f));
     }
-    qp += lane_xor16(qp);   // a + b == b + a: the same sum in every lane of the column
-    qp += lane_xor32(qp);
+    qp = lane_sum32(lane_sum16(qp));   // the same sum in every lane of the column
     o.q = qp * __builtin_amdgcn_rcpf(psum);
     o.p = hg_phase(g, pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2]);
     o.w = o.p * __builtin_amdgcn_rcpf(c * o.q + (1.0f - c) * o.p);
@@ -800,20 +822,23 @@ __device__ inline float lobe_uniform(float u_sel, float c)
     return fminf(u_sel * __builtin_amdgcn_rcpf(c), 0.99999994f);
 }
 
-// A tile row's inputs as bf16 (7 values, then zeros) in two 16-byte stores.
+// A tile row's network inputs as bf16 (the 15 from the vertex's 7 values,
+// then a zero) in two 16-byte stores.
 __device__ inline void put_guide_inputs(short *row, const float x[7])
 {
     bf16x8 a, b;
-    for (int k = 0; k < 7; ++k) a[k] = to_bf16(x[k]);
-    a[7] = 0;
-    for (int k = 0; k < 8; ++k) b[k] = 0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = to_bf16(guide_feature(x, k));
+#pragma unroll
+    for (int k = 0; k < 7; ++k) b[k] = to_bf16(guide_feature(x, 8 + k));
+    b[7] = 0;
     reinterpret_cast<bf16x8 *>(row)[0] = a;
     reinterpret_cast<bf16x8 *>(row)[1] = b;
 }
 
 // The renderer's guided scattering step on given vertices (one wave per 64):
-// in rows of 8 floats (the 7 network inputs; the incoming direction is
-// inputs 3..5), u rows of 4 uniforms, out rows of 8 floats (new direction,
+// in rows of 8 floats (the vertex's 7 values; the incoming direction is
+// values 3..5), u rows of 4 uniforms, out rows of 8 floats (new direction,
 // weight factor, q, p_HG, 0, 0).
 __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const float *__restrict__ in,
                                                           const float *__restrict__ u, float c, float g, int n,

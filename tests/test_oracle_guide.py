@@ -69,7 +69,7 @@ def test_parameter_gradient_finite_differences(monkeypatch):
     rng = np.random.default_rng(3)
     params = G.init_params(4).astype(np.float64) * 0.5
     n = 16
-    X = rng.uniform(-1, 1, (n, G.N_IN))
+    X = rng.uniform(-1, 1, (n, G.N_RAW))
     w_out = rng.standard_normal((n, 3))
     w_out /= np.linalg.norm(w_out, axis=1, keepdims=True)
     weight = rng.random(n) + 0.1
@@ -84,7 +84,31 @@ def test_parameter_gradient_finite_differences(monkeypatch):
 
 
 def test_parameter_count():
-    assert G.n_params() == 11432
+    # 15 x 64 + 64, 2 x (64 x 64 + 64), 64 x 40 + 40
+    assert G.n_params() == 11944
+
+
+def test_position_features():
+    """The Fourier features against identities they must obey: unit circle
+    per pair, the double angle between the two frequencies, periodicity of
+    1/4 (8 pi) in x and y, and the raw inputs passed through."""
+    rng = np.random.default_rng(9)
+    X = rng.uniform(-1, 1, (500, G.N_RAW))
+    F = G.features(X)
+    assert F.shape == (500, 15) and np.array_equal(F[:, :7], X)
+    for j in range(4):
+        assert np.allclose(F[:, 7 + 2 * j] ** 2 + F[:, 8 + 2 * j] ** 2, 1.0)
+    # sin 16 pi x = 2 sin 8 pi x cos 8 pi x, cos 16 pi y = cos^2 8 pi y - sin^2 8 pi y
+    assert np.allclose(F[:, 11], 2 * F[:, 7] * F[:, 8])
+    assert np.allclose(F[:, 14], F[:, 10] ** 2 - F[:, 9] ** 2)
+    Xs = X.copy()
+    Xs[:, 0] += 0.25
+    Xs[:, 1] -= 0.25
+    assert np.allclose(G.features(Xs)[:, 7:], F[:, 7:])
+    # x = 1/16: 8 pi x = pi / 2
+    Z = np.zeros((1, G.N_RAW))
+    Z[0, 0] = 1.0 / 16.0
+    assert np.allclose(G.features(Z)[0, 7:], [1, 0, 0, 1, 0, -1, 0, 1], atol=1e-12)
 
 
 def test_mis_weight_is_unbiased():
