@@ -91,6 +91,12 @@ def parse():
 
 
 FLAGS = 0   # sun-ray estimator of every render in the run (set from --sun)
+T_START = time.perf_counter()
+
+
+def note(leg):
+    """One progress line on stderr per finished leg (the JSON line goes to stdout)."""
+    print("bench: %s done at %.1f s" % (leg, time.perf_counter() - T_START), file=sys.stderr, flush=True)
 
 
 def main():
@@ -157,11 +163,17 @@ def main():
     t0 = time.perf_counter()
     last = None
     for i in range(args.steps):
-        last = step(args.warmup + i, cnt)
+        last = step(args.warmup + i)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_step = (t1 - t0) * 1e3 / args.steps
     render_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    note("timed steps")
+    # the event counts of one step, from a repeat of the last timed step (the
+    # same seed traces the same paths) outside the timed region: the kernel
+    # keeps no statistics unless counters are passed
+    step(args.warmup + args.steps - 1, cnt)
+    torch.cuda.synchronize()
     c = api.counters_dict(cnt)
     _, s, s2 = last
     sm = s.cpu().numpy().ravel() / spp
@@ -171,7 +183,7 @@ def main():
     t_1pct = ms_step / 1e3 * (eps / 0.01) ** 2
 
     paths_s = paths_per_step / (ms_step / 1e3)
-    gathers_per_launch = (c["gathers"] + c["node_reads"]) / args.steps
+    gathers_per_launch = c["gathers"] + c["node_reads"]
     achieved = gathers_per_launch * GRANULE / (render_ms / 1e3) / 1e9
     out = {
         "metric": METRIC,
@@ -191,8 +203,8 @@ def main():
                    "paths_per_step": paths_per_step},
         "render_ms": render_ms,
         "autotuned": tuned,
-        "segments_per_s": c["segments"] / args.steps / (render_ms / 1e3),
-        "tentative_per_s": c["tentative"] / args.steps / (render_ms / 1e3),
+        "segments_per_s": c["segments"] / (render_ms / 1e3),
+        "tentative_per_s": c["tentative"] / (render_ms / 1e3),
         "per_path": {k: c[k] / max(c["paths"], 1) for k in ("segments", "tentative", "nulls", "reals",
                                                             "leaf_visits", "gathers", "node_reads", "nee_rays")},
         "truncated": c["truncated"],
@@ -211,30 +223,42 @@ def main():
     if not args.no_guided:
         out["guided"], gd = guided_run(ctx, sc, kc, spp, args, build_ms=ms_step - render_ms)
         out["time_to_1pct_s"]["guided"] = out["guided"]["time_to_1pct_s"]
+        note("guided")
     if not args.no_ceiling:
         out["gather_ceiling"] = gather_ceiling(ctx)
         out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
+        note("gather_ceiling")
     if not args.no_progressive:
         out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
+        note("progressive")
     if not args.no_estimators:
         out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
+        note("sun_estimators")
     if not args.no_flux:
         out["flux"] = flux_run(ctx)
+        note("flux")
     if not args.no_guide_kernels:
         out["guide_kernels"] = guide_kernel_run(ctx, args)
+        note("guide_kernels")
     if args.workload == "cumulus" and not args.no_tau_sweep:
         out["tau_sweep"] = tau_sweep(ctx, sc, kc)
+        note("tau_sweep")
     if args.workload == "cumulus" and not args.no_variants:
         out["grid_variants"] = grid_variants(ctx, sc, kc, spp)
+        note("grid_variants")
     if fine is not None:
         out["refinement"] = refinement_sweep(ctx, sc, fine)
+        note("refinement")
         del fine
     if args.workload == "cumulus" and not args.no_batch:
         out["batch"] = batch_run(ctx, sc, kc, args.batch_spp)
+        note("batch")
         if not args.no_guided:
             out["batch_guided"] = batch_guided_run(ctx, sc, kc, args.batch_spp, args)
+            note("batch_guided")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
+        note("cpu_baseline")
     print(json.dumps(out))
 
 
@@ -381,12 +405,13 @@ def tau_sweep(ctx, sc, kc):
     for tt in (0.0, 0.03, 0.1, 0.3, 1.0, 3.0, 10.0, 30.0, 100.0, math.inf):
         g = api.build_grid(ctx, kc, sc.desc, inputs.GridParams(tt, sc.grid.k_gas, 0))
         cnt = api.new_counters("cuda")
+        smp = inputs.Sampling(seed=sc.sampling.seed + 71, spp=spp, flags=FLAGS)
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=sc.sampling.seed + 71, spp=spp, flags=FLAGS),
-                   counters=cnt)
+        api.render(ctx, g, kc, sc.optics, cam, smp)
         e1.record()
+        api.render(ctx, g, kc, sc.optics, cam, smp, counters=cnt)   # the same paths, with statistics
         torch.cuda.synchronize()
         c = api.counters_dict(cnt)
         ticks = {k: c["ticks_" + k] for k in ("cross", "collide", "event", "ray", "sample")}
@@ -417,8 +442,9 @@ def grid_variants(ctx, sc, kc, spp):
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp, counters=cnt)
+        s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp)
         e1.record()
+        api.render(ctx, g, kc, sc.optics, cam, smp, counters=cnt)   # the same paths, with statistics
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
         c = api.counters_dict(cnt)

@@ -80,6 +80,7 @@ nc::OptView make_opt(const nc_optics *o, double k_gas)
     const double th = o->sun_zenith_deg * M_PI / 180.0, ph = o->sun_azimuth_deg * M_PI / 180.0;
     v.ssa = (float)o->ssa;
     v.g = (float)o->g;
+    v.hg = nc::make_hg(o->g);
     v.rho = (float)o->ground_albedo;
     v.S = (float)o->sun_irradiance;
     v.mscale = (float)o->majorant_scale;

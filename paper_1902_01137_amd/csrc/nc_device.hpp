@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <cmath>
+
 #include "nctrace.h"
 
 namespace nc {
@@ -390,18 +392,43 @@ __device__ inline size_t collision_cell(const GridView &g, const Ray &r, float t
 // ---------------------------------------------------------------------------
 // (reciprocals by v_rcp/v_rsq: a relative error of ~1e-7 in a Monte Carlo
 // weight is far below the statistical error)
-__device__ inline float hg_phase(float g, float mu)
+//
+// The constants of one asymmetry g are formed once on the host and reach the
+// kernels as arguments (scalar registers), so that no vector register holds
+// them through the persistent loop.
+struct HGc {
+    float a;     // 1 + g^2
+    float b;     // 2 g
+    float c;     // (1 - g^2) / (4 pi)
+    float e;     // 1 - g^2
+    float d;     // 1 - g
+    float r2g;   // 1 / (2 g); 0 when |g| < 1e-4 (then the cosine is uniform)
+};
+
+inline HGc make_hg(double g)
 {
-    const float den = 1.0f + g * g - 2.0f * g * mu;
-    return (1.0f - g * g) * kInv4Pi * __builtin_amdgcn_rsqf(den) * __builtin_amdgcn_rcpf(den);
+    HGc h;
+    h.a = (float)(1.0 + g * g);
+    h.b = (float)(2.0 * g);
+    h.c = (float)((1.0 - g * g) / (4.0 * 3.14159265358979323846));
+    h.e = (float)(1.0 - g * g);
+    h.d = (float)(1.0 - g);
+    h.r2g = std::fabs(g) < 1e-4 ? 0.0f : (float)(1.0 / (2.0 * g));
+    return h;
+}
+
+__device__ inline float hg_phase(const HGc &h, float mu)
+{
+    const float den = h.a - h.b * mu;
+    return h.c * __builtin_amdgcn_rsqf(den) * __builtin_amdgcn_rcpf(den);
 }
 
 // Inverse-CDF sample of the HG cosine.
-__device__ inline float hg_sample_mu(float g, float xi)
+__device__ inline float hg_sample_mu(const HGc &h, float xi)
 {
-    if (fabsf(g) < 1e-4f) return 2.0f * xi - 1.0f;
-    const float s = (1.0f - g * g) * __builtin_amdgcn_rcpf(1.0f - g + 2.0f * g * xi);
-    const float mu = (1.0f + g * g - s * s) * __builtin_amdgcn_rcpf(2.0f * g);
+    if (h.r2g == 0.0f) return 2.0f * xi - 1.0f;
+    const float s = h.e * __builtin_amdgcn_rcpf(h.d + h.b * xi);
+    const float mu = (h.a - s * s) * h.r2g;
     return fminf(1.0f, fmaxf(-1.0f, mu));
 }
 

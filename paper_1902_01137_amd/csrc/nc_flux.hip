@@ -134,7 +134,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                 }
                 if (g.k_gas > 0.0f) sig_s += g.k_gas / (g.kscale * k);
                 sig_a += dln_alpha;
-                const float mu = hg_sample_mu(A.op.g, rng.u01());
+                const float mu = hg_sample_mu(A.op.hg, rng.u01());
                 sig_g += hg_dlng(A.op.g, mu);
                 float nd[3] = {r.d[0], r.d[1], r.d[2]};
                 turn(nd, mu, rng.u01());

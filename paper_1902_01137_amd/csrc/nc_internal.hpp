@@ -85,6 +85,7 @@ struct CamView {
 
 struct OptView {
     float ssa, g, rho, S, mscale;
+    HGc hg;              // the phase function's constants
     float sun[3];
     float ground_w;      // rho / pi * S * cos(theta_sun): ground local estimate before transmissivity
     int max_scatter, max_segments;

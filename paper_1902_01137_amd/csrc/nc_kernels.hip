@@ -493,6 +493,7 @@ enum BlockCounter {
 
 __device__ inline void wave_count(unsigned long long *s_cnt, int k, bool pred)
 {
+    if (!s_cnt) return;   // no counters asked for
     const unsigned long long m = __ballot(pred);
     if (m && __lane_id() == 0) atomicAdd(s_cnt + k, (unsigned long long)__popcll(m));
 }
@@ -754,7 +755,7 @@ __device__ inline float lane_max32(float v)
     return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
-__device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, float g, int kq)
+__device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, const HGc &g, int kq)
 {
     const float amax = lane_max32(lane_max16(fmaxf(z[0], z[5])));
     const float e0 = __expf(z[0] - amax), e1 = __expf(z[5] - amax);
@@ -841,7 +842,7 @@ __device__ inline void put_guide_inputs(short *row, const float x[7])
 // values 3..5), u rows of 4 uniforms, out rows of 8 floats (new direction,
 // weight factor, q, p_HG, 0, 0).
 __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const float *__restrict__ in,
-                                                          const float *__restrict__ u, float c, float g, int n,
+                                                          const float *__restrict__ u, float c, HGc g, int n,
                                                           float *__restrict__ out)
 {
     __shared__ __align__(16) short wl[kWOff[4]];
@@ -896,8 +897,8 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
                                float g, int n, float *out)
 {
     const int blocks = std::max(1, std::min((n + 63) / 64, 4096));
-    hipLaunchKernelGGL(guide_sample_kernel, dim3(blocks), dim3(64), 0, ctx->stream, guide_weights(gd), in, u, c, g, n,
-                       out);
+    hipLaunchKernelGGL(guide_sample_kernel, dim3(blocks), dim3(64), 0, ctx->stream, guide_weights(gd), in, u, c,
+                       make_hg(g), n, out);
     return hipGetLastError();
 }
 
@@ -918,6 +919,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                      g.n[1]};
     const volatile RenderRare &R = *A.rare;
     const int lane = __lane_id();
+    // statistics (ballots, LDS atomics, clock reads) only when counters are asked for
+    const bool stats = A.counters != nullptr;
+    unsigned long long *const cnt = stats ? s_cnt : nullptr;
     int job = 0;                           // the lane's current view x sun
     float sun[3] = {0.0f, 0.0f, 1.0f};     // that job's sun direction (its irradiance is applied at the flush)
 
@@ -975,11 +979,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 ++guide_wait;
             }
         }
-        if (lane == 0) {
+        if (stats && lane == 0) {
             atomicAdd(s_cnt + kCTrips0 + run, 1ull);
             atomicAdd(s_cnt + kCLanes0 + run, (unsigned long long)best);
         }
-        const long long t_trip = wall_clock64();
+        const long long t_trip = stats ? wall_clock64() : 0;
 
         if (run == kPhCross) {
             // ---- move to the next voxel, carrying the optical thickness
@@ -1012,9 +1016,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 }
             }
-            wave_count(s_cnt, kCSegments, active);
-            wave_count(s_cnt, kCLeaf, leaf);
-            wave_count(s_cnt, kCTrunc, trunc);
+            wave_count(cnt, kCSegments, active);
+            wave_count(cnt, kCLeaf, leaf);
+            wave_count(cnt, kCTrunc, trunc);
         } else if (run == kPhCollide) {
             // ---- tentative collision in the current voxel: real or null
             const bool active = phase == kPhCollide;
@@ -1083,12 +1087,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 }
             }
-            wave_count(s_cnt, kCSegments, active);
-            wave_count(s_cnt, kCTentative, active);
-            wave_count(s_cnt, kCReals, real);
-            wave_count(s_cnt, kCNulls, active && !real);
-            wave_count(s_cnt, kCGathers, gathered);
-            wave_count(s_cnt, kCTrunc, trunc);
+            wave_count(cnt, kCSegments, active);
+            wave_count(cnt, kCTentative, active);
+            wave_count(cnt, kCReals, real);
+            wave_count(cnt, kCNulls, active && !real);
+            wave_count(cnt, kCGathers, gathered);
+            wave_count(cnt, kCTrunc, trunc);
         } else if (run == kPhEvent) {
             if (phase == kPhEvent) {
                 // three numbers cover an event (absorption, then two for the new
@@ -1111,7 +1115,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     kev = kd + g.k_gas;
                     const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + g.k_gas);
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * hg_phase(A.op.g, mu);
+                    w_nee = ssa * hg_phase(A.op.hg, mu);
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
@@ -1164,7 +1168,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         if (ground_ev)
                             lambert(pd, u1, u2);
                         else
-                            turn(pd, hg_sample_mu(A.op.g, u1), u2);
+                            turn(pd, hg_sample_mu(A.op.hg, u1), u2);
                         phase = kPhRay;
                         if (kMode == kCollect && !ground_ev) {
                             // training record: vertex, incoming and outgoing directions, radiance so far
@@ -1201,8 +1205,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 tau = rng.take_exp1();
                 phase = voxel_phase(r, tau);
             }
-            wave_count(s_cnt, kCNee, active && shadow);
-            wave_count(s_cnt, kCLeaf, hit);
+            wave_count(cnt, kCNee, active && shadow);
+            wave_count(cnt, kCLeaf, hit);
         } else if (kMode == kGuided && run == kPhGuide) {
             // ---- guided scattering: network inference on the matrix cores,
             // then the MIS step in the same layout.  The first `best` waiting
@@ -1245,7 +1249,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 wave_sync();
                 float z[12];
                 guide_tile_forward(wl, bl, tin, lane, z);
-                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.g, kq);
+                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.hg, kq);
                 // each owner takes its column's result
                 const int src = owner ? row : lane;
                 const float d0 = __shfl(st.d[0], src), d1 = __shfl(st.d[1], src), d2 = __shfl(st.d[2], src);
@@ -1283,7 +1287,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 }
             }
             const bool finished = phase == kPhSample && traced;
-            wave_count(s_cnt, kCPaths, finished);
+            wave_count(cnt, kCPaths, finished);
             if (phase == kPhSample) traced = false;   // only lanes in this phase: others are mid-path
             // queue refill in uniform control flow: ballot + prefix count over
             // the wave's chunk, one global atomic per kChunk items
@@ -1381,7 +1385,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 }
             }
         }
-        if (lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
+        if (stats && lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
     }
     // per-lane reads, then the block's counters to global memory
     const unsigned long long rsum = wave_sum(reads);
@@ -1509,9 +1513,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
              : est == 1 ? (const void *)render_kernel<3, kGuided, 1>
                         : (const void *)render_kernel<3, kGuided, 2>;
     } else if (mode == kCollect) {
-        fn = est == 0 ? (const void *)render_kernel<3, kCollect, 0>
-             : est == 1 ? (const void *)render_kernel<3, kCollect, 1>
-                        : (const void *)render_kernel<3, kCollect, 2>;
+        fn = est == 0 ? (const void *)render_kernel<4, kCollect, 0>
+             : est == 1 ? (const void *)render_kernel<4, kCollect, 1>
+                        : (const void *)render_kernel<4, kCollect, 2>;
     } else if (est == 0) {
         fn = wpe == 3   ? (const void *)render_kernel<3, kPlain, 0>
              : wpe == 4 ? (const void *)render_kernel<4, kPlain, 0>
