@@ -150,7 +150,15 @@ static double cell_kd(const orc_field *f, int i, int j, int m)
  *   criterion 2: l <= flat_level (no test on the field: a flat grid of
  *                supercells of 2^flat_level cells, the single-level majorant
  *                grid the paper sets against its hierarchy, Sections 2.4 and 3)
- * evaluated in double precision.  Both are monotone (a merged node has merged
+ *   criterion 3: the node lies wholly above or below the cloudy layer, or
+ *                l <= flat_level: the layered grid the paper cites as the
+ *                step before its hierarchy (Section 3.1.1: the cloudy layer
+ *                split from the clear layers above and below it, each with
+ *                its own fixed resolution).  The cloudy layer is the range of
+ *                z indices holding a cell with k_c > 0; clear layers get the
+ *                coarsest nodes that stay clear, the cloudy layer supercells
+ *                of 2^flat_level cells
+ * evaluated in double precision.  All are monotone (a merged node has merged
  * children), so the bottom-up merging of groups of 2^3 children gives the
  * same voxels as taking, for each cell, its coarsest ancestor that passes the
  * criterion; that ancestor's level is the cell's leaf level (0: the cell
@@ -190,6 +198,18 @@ orc_grid *orc_grid_build(const orc_field *f, double tau_tilde, int criterion, in
     if (f->nz > nmax) nmax = f->nz;
     g->L = 0;
     while ((1 << g->L) < nmax) g->L++;
+    /* criterion 3: z extent [zc_lo, zc_hi] of the cells with k_c > 0 (empty if none) */
+    int zc_lo = f->nz, zc_hi = -1;
+    if (criterion == 3) {
+        int ci, cj, cm;
+        for (cm = 0; cm < f->nz; ++cm)
+            for (cj = 0; cj < f->ny; ++cj)
+                for (ci = 0; ci < f->nx; ++ci)
+                    if (cell_kc(f, ci, cj, cm) > 0.0) {
+                        if (cm < zc_lo) zc_lo = cm;
+                        if (cm > zc_hi) zc_hi = cm;
+                    }
+    }
     for (l = 1; l <= g->L; ++l) {
         int a, i, j, m;
         size_t nn;
@@ -222,6 +242,12 @@ orc_grid *orc_grid_build(const orc_field *f, double tau_tilde, int criterion, in
                     dz_node = f->dz * (double)(1 << l);
                     if (criterion == 2) {
                         g->merged[l][id] = (unsigned char)(l <= flat_level);
+                        continue;
+                    }
+                    if (criterion == 3) {
+                        /* cells ma .. mb-1 in z: clear if wholly below or above the cloudy layer */
+                        const int clear = (mb - 1 < zc_lo) || (ma > zc_hi);
+                        g->merged[l][id] = (unsigned char)(clear || l <= flat_level);
                         continue;
                     }
                     if (criterion == 0) {

@@ -144,3 +144,60 @@ def test_flat_supercell_grid(orc, shape, flat):
         for m, j, i in [(0, 0, 0), (dz_ - 1, dy_ - 1, dx_ - 1), (dz_ // 2, dy_ // 2, dx_ // 2)]:
             blk = k[m * s:(m + 1) * s, j * s:(j + 1) * s, i * s:(i + 1) * s]
             assert kmin[m, j, i] == blk.min() and kmax[m, j, i] == blk.max()
+
+
+def test_layered_grid_hand_case(orc):
+    """Criterion 3 on a 4 x 4 x 16 field whose only cloud cells sit at z = 5
+    and z = 9, supercells of 2 cells (flat_level 1) in the cloudy layer.
+    Per z index, the voxel level follows from the node ranges by hand: z 0-3
+    and 12-15 lie in clear level-2 nodes (z 0-3, 12-15) whose level-3 parents
+    (z 0-7, 8-15) reach the cloud; z 4-11 have no clear level-2 ancestor and
+    stop at level 1."""
+    k = np.zeros((16, 4, 4), np.float32)
+    k[5, 1, 2] = 30.0
+    k[9, 3, 0] = 0.5
+    desc = FieldDesc(4, 4, 16, 0, 0, 0, 0.05, 0.05, 0.05)
+    g = orc.OracleGrid(desc, k, tau_tilde=0.0, k_gas=0.05, criterion=3, flat_level=1)
+    leaf = g.leaf_levels()
+    expect_z = [2, 2, 2, 2, 1, 1, 1, 1, 1, 1, 1, 1, 2, 2, 2, 2]
+    for z in range(16):
+        assert (leaf[z] == expect_z[z]).all(), (z, leaf[z])
+
+
+def _layered_leaf_by_definition(k, flat):
+    """Brute force: for each cell, the coarsest level l whose node either has
+    no cloud cell anywhere in its z range's layers or has l <= flat."""
+    nz, ny, nx = k.shape
+    cloudy_z = np.nonzero((k > 0).any(axis=(1, 2)))[0]
+    L = max(int(math.ceil(math.log2(max(nx, ny, nz)))), 0)
+    leaf = np.zeros(k.shape, np.int64)
+    for z in range(nz):
+        best = 0
+        for l in range(1, L + 1):
+            za, zb = (z >> l) << l, min(((z >> l) + 1) << l, nz) - 1
+            clear = not np.any((cloudy_z >= za) & (cloudy_z <= zb))
+            if clear or l <= flat:
+                best = l
+        leaf[z] = best
+    return leaf
+
+
+@pytest.mark.parametrize("shape,flat,layer", [((40, 24, 32), 2, (11, 23)), ((33, 17, 9), 0, (3, 3)),
+                                              ((64, 8, 8), 3, (20, 47)), ((16, 16, 16), 1, None)])
+def test_layered_grid_matches_definition(orc, shape, flat, layer):
+    """Criterion 3 against a cell-by-cell restatement of its definition on
+    ragged fields with a random cloud layer (or none: then one voxel)."""
+    rng = np.random.default_rng(sum(shape) + flat)
+    nz, ny, nx = shape
+    k = np.zeros(shape, np.float32)
+    if layer is not None:
+        z0, z1 = layer
+        blob = (rng.random((z1 - z0 + 1, ny, nx)) ** 6 * 40).astype(np.float32)
+        blob[rng.random(blob.shape) < 0.7] = 0.0
+        blob[0, 0, 0], blob[-1, -1, -1] = 1.0, 2.0        # the layer's bottom and top hold cloud
+        k[z0:z1 + 1] = blob
+    desc = FieldDesc(nx, ny, nz, 0, 0, 0, 0.025, 0.025, 0.025)
+    g = orc.OracleGrid(desc, k, tau_tilde=1.0, k_gas=0.05, criterion=3, flat_level=flat)
+    assert np.array_equal(g.leaf_levels(), _layered_leaf_by_definition(k, flat))
+    if layer is None:
+        assert (g.leaf_levels() == g.L).all()
