@@ -426,7 +426,9 @@ def tau_sweep(ctx, sc, kc):
 
 def grid_variants(ctx, sc, kc, spp):
     """The same render over other majorant grids: the flat grid of 8^3-cell
-    supercells, tau_tilde = 0 (every cell a voxel) and one global voxel."""
+    supercells, the layered grids (clear layers split from the cloudy one,
+    which holds 8^3-cell supercells or single cells), tau_tilde = 0 (every
+    cell a voxel) and one global voxel."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -434,6 +436,8 @@ def grid_variants(ctx, sc, kc, spp):
     res = {}
     for name, gp in (("hier_tau1", sc.grid),
                      ("flat_8cube", inputs.GridParams(0.0, sc.grid.k_gas, 2, 3)),
+                     ("layered_8cube", inputs.GridParams(0.0, sc.grid.k_gas, 3, 3)),
+                     ("layered_cells", inputs.GridParams(0.0, sc.grid.k_gas, 3, 0)),
                      ("tau0", inputs.GridParams(0.0, sc.grid.k_gas, 0)),
                      ("global", inputs.GridParams(math.inf, sc.grid.k_gas, 0))):
         g = api.build_grid(ctx, kc, sc.desc, gp)

@@ -70,12 +70,18 @@ typedef struct {
  *   criterion 2: l <= flat_level, whatever the field: the flat, single-level
  *                majorant grid of 2^flat_level-cell supercells that the
  *                hierarchy is compared with (Sections 2.4, 3); tau_tilde unused
+ *   criterion 3: the node lies wholly below or above the cloudy layer (the z
+ *                range of the cells with k_c > 0), or l <= flat_level: the
+ *                layered grid of Section 3.1.1's comparison (clear layers
+ *                split from the cloudy one, a resolution for each); clear
+ *                layers take the coarsest nodes that stay clear, the cloudy
+ *                layer 2^flat_level-cell supercells; tau_tilde unused
  * tau_tilde = 0 keeps the raw resolution; tau_tilde = +inf gives one voxel. */
 typedef struct {
     double tau_tilde;
     double k_gas;
     int32_t criterion;
-    int32_t flat_level;     /* criterion 2 only, 0..NC_MAX_LEVELS */
+    int32_t flat_level;     /* criteria 2 and 3, 0..NC_MAX_LEVELS */
 } nc_grid_params;
 
 /* Medium, ground and sun.  ssa is the droplets' single-scattering albedo

@@ -290,9 +290,9 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
     if (!(params->tau_tilde >= 0.0)) return fail(ctx, NC_ERR_RANGE, "tau_tilde must be >= 0");
     if (!(params->k_gas >= 0.0) || !std::isfinite(params->k_gas))
         return fail(ctx, NC_ERR_RANGE, "k_gas must be finite and >= 0");
-    if (params->criterion < 0 || params->criterion > 2)
-        return fail(ctx, NC_ERR_INVALID_ARG, "criterion must be 0, 1 or 2");
-    if (params->criterion == 2 && (params->flat_level < 0 || params->flat_level > NC_MAX_LEVELS))
+    if (params->criterion < 0 || params->criterion > 3)
+        return fail(ctx, NC_ERR_INVALID_ARG, "criterion must be 0, 1, 2 or 3");
+    if (params->criterion >= 2 && (params->flat_level < 0 || params->flat_level > NC_MAX_LEVELS))
         return fail(ctx, NC_ERR_INVALID_ARG, "flat_level must lie in [0, NC_MAX_LEVELS]");
     DeviceGuard guard(ctx->device);
     nc_grid *g = new (std::nothrow) nc_grid();
@@ -342,7 +342,8 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
     unsigned int *d_bad = reinterpret_cast<unsigned int *>(ctx->d_scratch + 1);
     unsigned int h_bad = 0;
     if (e == hipSuccess) e = hipMemcpyAsync(d_bad, &h_bad, sizeof(unsigned int), hipMemcpyHostToDevice, ctx->stream);
-    if (e == hipSuccess) e = nc::launch_build(ctx, g, d_kc, d_bad);
+    int *d_zc = reinterpret_cast<int *>(ctx->d_scratch + 2);
+    if (e == hipSuccess) e = nc::launch_build(ctx, g, d_kc, d_bad, d_zc);
     if (e == hipSuccess && L == 0) {
         // a single cell: validate it on the host
         float v = 0.0f;

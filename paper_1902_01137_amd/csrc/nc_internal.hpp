@@ -72,7 +72,7 @@ struct nc_guide {
 
 namespace nc {
 
-constexpr int kScratchWords = 256;   // [0] queue head, [1] validation flag, [8..] launch parameters
+constexpr int kScratchWords = 256;   // [0] queue head, [1] validation flag, [2] cloudy layer, [8..] launch parameters
 constexpr int kScratchRare = 8;
 constexpr int kScratchErr = 240;     // [240..242] image error accumulators (float64)
 
@@ -129,7 +129,7 @@ struct Shape {
 GridView grid_view(const nc_grid *g, const float *d_kc);
 Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve = 0, int waves_default = 0);
 
-hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad);
+hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad, int *d_zc);
 hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int level, float *kmin, float *kmax, uint8_t *mg);
 hipError_t launch_leaf_levels(const nc_ctx *ctx, const nc_grid *g, uint8_t *out);
 hipError_t launch_trace_leaves(const nc_ctx *ctx, const nc_grid *g, const float *rays, int n, int maxv, int *leaf,

@@ -21,6 +21,47 @@ __device__ inline bool merge_criterion(float kmin, float kmax, double k_gas, dou
     return s * dz_node < tau;
 }
 
+// The layered grid (criterion 3): a node covering z cells za..zb is one voxel
+// when it lies wholly below or above the cloudy layer zc[0]..zc[1] (the z
+// range of the cells with k_c > 0), or when its level is <= flat_level.
+struct LayerRule {
+    const int *zc;     // device: cloudy layer's lowest and highest z index (null: not criterion 3)
+    int flat_level;
+};
+
+__device__ inline bool node_merged_rule(float kmin, float kmax, double k_gas, double dz_node, double tau, int crit,
+                                        const LayerRule &lr, int level, int za, int zb)
+{
+    if (lr.zc) return zb < lr.zc[0] || za > lr.zc[1] || level <= lr.flat_level;
+    return merge_criterion(kmin, kmax, k_gas, dz_node, tau, crit);
+}
+
+// z extent of the cells with k_c > 0 (zc starts at {nz, -1})
+__global__ void cloud_layer_kernel(const float *__restrict__ kc, long long n, int nxy, int *__restrict__ zc)
+{
+    int lo = 0x7fffffff, hi = -1;
+    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < n;
+         id += (long long)gridDim.x * blockDim.x) {
+        if (kc[id] > 0.0f) {
+            const int z = (int)(id / nxy);
+            lo = min(lo, z);
+            hi = max(hi, z);
+        }
+    }
+    if (hi >= 0) {
+        atomicMin(zc, lo);
+        atomicMax(zc + 1, hi);
+    }
+}
+
+__global__ void set_cloud_layer_kernel(int *zc, int nz)
+{
+    if (threadIdx.x == 0) {
+        zc[0] = nz;
+        zc[1] = -1;
+    }
+}
+
 __device__ inline float2 encode_node(float kmin, float kmax, bool merged)
 {
     const uint32_t b = (__float_as_uint(kmin) & 0x7fffffffu) | (merged ? 0x80000000u : 0u);
@@ -31,7 +72,7 @@ __device__ inline float2 encode_node(float kmin, float kmax, bool merged)
 // cells and validates them (finite, >= 0).
 __global__ void build_level1_kernel(const float *__restrict__ kc, int nx, int ny, int nz, float2 *__restrict__ out,
                                     int d0, int d1, int d2, double k_gas, double dz_node, double tau, int crit,
-                                    unsigned int *bad)
+                                    LayerRule lr, unsigned int *bad)
 {
     const long long total = (long long)d0 * d1 * d2;
     bool flag = false;
@@ -58,14 +99,16 @@ __global__ void build_level1_kernel(const float *__restrict__ kc, int nx, int ny
                 }
             }
         }
-        out[id] = encode_node(lo, hi, merge_criterion(lo, hi, k_gas, dz_node, tau, crit));
+        out[id] = encode_node(lo, hi, node_merged_rule(lo, hi, k_gas, dz_node, tau, crit, lr, 1, 2 * m,
+                                                       min(2 * m + 2, nz) - 1));
     }
     if (flag) atomicOr(bad, 1u);
 }
 
 // Level l >= 2 from level l-1: min and max of the (up to) 8 children.
 __global__ void build_level_kernel(const float2 *__restrict__ child, int c0, int c1, int c2, float2 *__restrict__ out,
-                                   int d0, int d1, int d2, double k_gas, double dz_node, double tau, int crit)
+                                   int d0, int d1, int d2, double k_gas, double dz_node, double tau, int crit,
+                                   LayerRule lr, int level, int nz)
 {
     const long long total = (long long)d0 * d1 * d2;
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
@@ -89,7 +132,8 @@ __global__ void build_level_kernel(const float2 *__restrict__ child, int c0, int
                 }
             }
         }
-        out[id] = encode_node(lo, hi, merge_criterion(lo, hi, k_gas, dz_node, tau, crit));
+        out[id] = encode_node(lo, hi, node_merged_rule(lo, hi, k_gas, dz_node, tau, crit, lr, level, m << level,
+                                                       min((m + 1) << level, nz) - 1));
     }
 }
 
@@ -152,9 +196,17 @@ static int blocks_for(long long n, int block, int cap = 65536)
     return (int)std::max<long long>(1, std::min<long long>(b, cap));
 }
 
-hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad)
+hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad, int *d_zc)
 {
     const int block = 256;
+    LayerRule lr{nullptr, g->params.flat_level};
+    if (g->params.criterion == 3) {
+        const long long cells = (long long)g->n[0] * g->n[1] * g->n[2];
+        hipLaunchKernelGGL(set_cloud_layer_kernel, dim3(1), dim3(64), 0, ctx->stream, d_zc, g->n[2]);
+        hipLaunchKernelGGL(cloud_layer_kernel, dim3(blocks_for(cells, block, 4096)), dim3(block), 0, ctx->stream, d_kc,
+                           cells, g->n[0] * g->n[1], d_zc);
+        lr.zc = d_zc;
+    }
     for (int l = 1; l <= g->L; ++l) {
         const int d0 = level_dim(g->n[0], l), d1 = level_dim(g->n[1], l), d2 = level_dim(g->n[2], l);
         const long long total = (long long)d0 * d1 * d2;
@@ -167,13 +219,13 @@ hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsign
         float2 *out = g->d_nodes + g->off[l];
         if (l == 1) {
             hipLaunchKernelGGL(build_level1_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream, d_kc,
-                               g->n[0], g->n[1], g->n[2], out, d0, d1, d2, g->params.k_gas, dz_node, tau, crit,
+                               g->n[0], g->n[1], g->n[2], out, d0, d1, d2, g->params.k_gas, dz_node, tau, crit, lr,
                                d_bad);
         } else {
             const int c0 = level_dim(g->n[0], l - 1), c1 = level_dim(g->n[1], l - 1), c2 = level_dim(g->n[2], l - 1);
             hipLaunchKernelGGL(build_level_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream,
                                (const float2 *)(g->d_nodes + g->off[l - 1]), c0, c1, c2, out, d0, d1, d2,
-                               g->params.k_gas, dz_node, tau, crit);
+                               g->params.k_gas, dz_node, tau, crit, lr, l, g->n[2]);
         }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

@@ -53,8 +53,8 @@ class FieldDesc:
 class GridParams:
     tau_tilde: float = 1.0
     k_gas: float = 0.0
-    criterion: int = 0          # 0: kmax*dz_node < tau_tilde, 1: (kmax-kmin)*dz_node < tau_tilde, 2: flat
-    flat_level: int = 3         # criterion 2: every node of level <= flat_level is a voxel (2^3-cell supercells)
+    criterion: int = 0          # 0: kmax*dz_node < tau_tilde, 1: (kmax-kmin)*dz_node < tau_tilde, 2: flat, 3: layered
+    flat_level: int = 3         # criteria 2, 3: every node of level <= flat_level is a voxel (2^3-cell supercells)
 
 
 @dataclass

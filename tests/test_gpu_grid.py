@@ -58,6 +58,31 @@ def test_flat_supercells(flat):
     _compare(FieldDesc(12, 9, 5, 0, 0, 0, 0.05, 0.05, 0.05), k2, 0.0, 0.02, 2, flat)
 
 
+@pytest.mark.parametrize("flat", [0, 1, 3])
+def test_layered_grid(flat):
+    """Criterion 3 (clear layers split from the cloudy layer): bit for bit
+    against the oracle on the cumulus field (clear air above and below its
+    cloud layer), on ragged fields with a random layer, on a field without
+    cloud (one voxel) and on the blob (cloud in every layer)."""
+    desc, k = inputs.cumulus_field(fine=(80, 256, 256), pool=2)
+    _compare(desc, k, 0.0, 0.05, 3, flat)
+    rng = np.random.default_rng(40 + flat)
+    for shape, layer in (((33, 17, 65), (9, 20)), ((64, 8, 8), (0, 5)), ((20, 6, 10), (19, 19))):
+        nz, ny, nx = shape
+        k2 = np.zeros(shape, np.float32)
+        z0, z1 = layer
+        blob = (rng.random((z1 - z0 + 1, ny, nx)) ** 6 * 40).astype(np.float32)
+        blob[rng.random(blob.shape) < 0.6] = 0.0
+        blob[0, 0, 0], blob[-1, -1, -1] = 1.0, 3.0
+        k2[z0:z1 + 1] = blob
+        _compare(FieldDesc(nx, ny, nz, 0, 0, 0, 0.05, 0.05, 0.05), k2, 1.0, 0.02, 3, flat)
+    g = _compare(FieldDesc(12, 9, 5, 0, 0, 0, 0.05, 0.05, 0.05), np.zeros((5, 9, 12), np.float32), 0.0, 0.02, 3, flat)
+    assert (g.leaf_levels().cpu().numpy() == g.L).all()
+    bd, bk = inputs.lognormal_blob()
+    g = _compare(bd, bk, 0.0, 0.01, 3, flat)
+    assert (g.leaf_levels().cpu().numpy() == min(flat, g.L)).all()
+
+
 def test_cylinder_256():
     desc, k = inputs.cylinder_cumulus()
     _compare(desc, k, 1.0)

@@ -169,6 +169,31 @@ def test_small_cloud_flat_supercell_grid():
     assert res["ok"], res
 
 
+def test_cumulus_layered_grid_image_equals_hierarchy():
+    """The layered grid is a valid majorant: a small cumulus view rendered
+    over it agrees with the same view over the hierarchical grid (whose
+    images are checked against the oracle above) within 3 combined standard
+    errors per 8x8 block."""
+    desc, k = inputs.cumulus_field(fine=(80, 256, 256), pool=2)
+    (xa, xb), (ya, yb), (za, zb) = desc.box
+    cam = inputs.Camera(type=0, pos=(xa - 1.5, (ya + yb) / 2, 1.5), target=((xa + xb) / 2, (ya + yb) / 2, 0.75),
+                        up=(0.0, 0.0, 1.0), fov_y_deg=50.0, width=64, height=64)
+    op = inputs.Optics(ssa=0.999, g=0.86, ground_albedo=0.2, sun_zenith_deg=45.0, sun_azimuth_deg=0.0)
+    c = ctx()
+    kd = device_field(k)
+    spp = 256
+    out = {}
+    for name, gp in (("hier", GridParams(1.0, 0.05, 0)), ("layered", GridParams(0.0, 0.05, 3, 1))):
+        g = api.build_grid(c, kd, desc, gp)
+        cnt = api.new_counters("cuda")
+        s, s2 = api.render(c, g, kd, op, cam, Sampling(seed=71 if name == "hier" else 72, spp=spp), counters=cnt)
+        torch.cuda.synchronize()
+        out[name] = mean_se(s.cpu().numpy().ravel(), s2.cpu().numpy().ravel(), spp)
+        assert api.counters_dict(cnt)["truncated"] == 0
+    res = compare(*block(*out["layered"], (64, 64)), *block(*out["hier"], (64, 64)))
+    assert res["ok"], res
+
+
 def test_resume_with_sample_offset():
     sc = inputs.scene_small()
     c = ctx()
