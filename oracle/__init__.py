@@ -42,7 +42,7 @@ class OpticsC(C.Structure):
     _fields_ = [("ssa", C.c_double), ("g", C.c_double), ("rho", C.c_double),
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double),
                 ("S", C.c_double), ("majorant_scale", C.c_double),
-                ("max_scatter", C.c_int32), ("max_segments", C.c_int32)]
+                ("max_scatter", C.c_int32), ("max_segments", C.c_int32), ("sun_half_angle_deg", C.c_double)]
 
 
 class CameraC(C.Structure):
@@ -107,7 +107,7 @@ def make_field(desc, kc: np.ndarray, k_gas: float = 0.0, kscale: float = 1.0):
 
 def make_optics(op) -> OpticsC:
     return OpticsC(op.ssa, op.g, op.ground_albedo, op.sun_zenith_deg, op.sun_azimuth_deg, op.sun_irradiance,
-                   op.majorant_scale, op.max_scatter, op.max_segments)
+                   op.majorant_scale, op.max_scatter, op.max_segments, getattr(op, "sun_half_angle_deg", 0.0))
 
 
 def make_camera(cam) -> CameraC:

@@ -109,6 +109,7 @@ typedef struct {
 typedef struct {
     double ssa, g, rho, sun_zenith_deg, sun_azimuth_deg, S, majorant_scale;
     int32_t max_scatter, max_segments;
+    double sun_half_angle_deg;   /* angular radius of the solar disc; 0: directional sun */
 } orc_optics;
 
 typedef struct {
@@ -793,6 +794,39 @@ static void sun_dir(const orc_optics *op, double s[3])
     s[2] = cos(t);
 }
 
+/* The sun as a disc of angular radius alpha about s with uniform radiance
+ * L_s, its irradiance through a plane normal to s being S = L_s pi sin^2
+ * alpha (the sun model of Appendix A's "solar cone"; alpha = 0 is the
+ * directional sun).  The local estimate draws its direction uniformly over
+ * the cone (solid angle 2 pi (1 - cos alpha)), so the estimate of an event
+ * carries S times cone_gain = 2 pi (1 - cos alpha) / (pi sin^2 alpha) =
+ * 2 / (1 + cos alpha). */
+static double cone_gain(const orc_optics *op)
+{
+    return 2.0 / (1.0 + cos(op->sun_half_angle_deg * ORC_PI / 180.0));
+}
+
+static void sun_sample(const orc_optics *op, const double s[3], orc_rng *r, double w[3])
+{
+    double ca, mu, phi;
+    if (op->sun_half_angle_deg <= 0.0) {     /* directional sun: no draw */
+        w[0] = s[0]; w[1] = s[1]; w[2] = s[2];
+        return;
+    }
+    ca = cos(op->sun_half_angle_deg * ORC_PI / 180.0);
+    mu = 1.0 - rng_u01(r) * (1.0 - ca);     /* uniform over the cap's solid angle */
+    phi = 2.0 * ORC_PI * rng_u01(r);
+    rotate_about(s, mu, phi, w);
+}
+
+/* radiance of the disc seen along d (units of S): S / (pi sin^2 alpha) inside it */
+static double sun_seen(const orc_optics *op, const double s[3], const double d[3])
+{
+    double a = op->sun_half_angle_deg * ORC_PI / 180.0;
+    if (a <= 0.0) return 0.0;
+    return (d[0] * s[0] + d[1] * s[1] + d[2] * s[2] >= cos(a)) ? op->S / (ORC_PI * sin(a) * sin(a)) : 0.0;
+}
+
 /* ========================================================================
  * Camera (Section 4.1 and Table 3): pinhole with a vertical field of view,
  * or orthographic; row 0 is the top of the image; the direction is sampled
@@ -844,7 +878,10 @@ void orc_camera_ray(const orc_camera *c, int px, int py, double u1, double u2, d
  * 1 - ssa(x) (analog absorption); the ground terminates with probability
  * 1 - rho; otherwise a new direction is drawn from the HG phase function or
  * the Lambertian (cosine) law.  Paths escaping upward contribute nothing
- * more (the delta sun is never hit by a sampled direction).
+ * more, except a camera ray that escapes without any event inside the
+ * solar disc (Section 4.1's direct sun; the scattered paths' sun is counted
+ * by the local estimates only).  With a solar disc the local estimate's
+ * direction is drawn uniformly in its cone (sun_sample).
  *
  * The oracle finds the next collision by path tracking (regular tracking,
  * an exact free path in the true field) and evaluates the sun's
@@ -854,7 +891,8 @@ void orc_camera_ray(const orc_camera *c, int px, int py, double u1, double u2, d
  *
  * A camera of type 2 is a horizontal sensor of the downward irradiance E
  * at its plane, reported as S times the transmissivity E / (S mu_sun): per
- * path, S times the sun's direct transmissivity to the point, plus
+ * path, S times the sun's direct transmissivity to the point (with a disc:
+ * along a direction w drawn in the cone, times cone_gain w_z / mu_sun), plus
  * pi / mu_sun times the radiance of a path started from the point in a
  * cosine-distributed upward direction (the cosine density is mu / pi, so
  * pi L estimates the diffuse irradiance).
@@ -871,9 +909,9 @@ static double sun_transmissivity(const orc_field *f, const double x[3], const do
 }
 
 static double radiance_path(const orc_field *f, const orc_optics *op, const double s[3], double o_in[3],
-                            double d_in[3], orc_rng *r, uint64_t *cnt)
+                            double d_in[3], int primary, orc_rng *r, uint64_t *cnt)
 {
-    double o[3], d[3], L = 0.0;
+    double o[3], d[3], L = 0.0, gain = cone_gain(op);
     int order = 0, a, segs = 0;
     for (a = 0; a < 3; ++a) { o[a] = o_in[a]; d[a] = d_in[a]; }
     for (;;) {
@@ -886,8 +924,12 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             if (cnt) cnt[0]++;
             order++;
             if (op->max_scatter >= 0 && order > op->max_scatter) break;
-            mu_sun = d[0] * s[0] + d[1] * s[1] + d[2] * s[2];
-            L += ssa * orc_hg_phase(op->g, mu_sun) * op->S * sun_transmissivity(f, x, s);
+            {
+                double w[3];
+                sun_sample(op, s, r, w);
+                mu_sun = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
+                L += ssa * orc_hg_phase(op->g, mu_sun) * op->S * gain * sun_transmissivity(f, x, w);
+            }
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
             if (rng_u01(r) >= ssa) break;
             {
@@ -903,8 +945,12 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             if (cnt) cnt[1]++;
             order++;
             if (op->max_scatter >= 0 && order > op->max_scatter) break;
-            if (s[2] > 0.0)
-                L += (op->rho / ORC_PI) * op->S * s[2] * sun_transmissivity(f, x, s);
+            {
+                double w[3];
+                sun_sample(op, s, r, w);
+                if (w[2] > 0.0)
+                    L += (op->rho / ORC_PI) * op->S * gain * w[2] * sun_transmissivity(f, x, w);
+            }
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
             if (rng_u01(r) >= op->rho) break;
             {
@@ -916,6 +962,8 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             }
             for (a = 0; a < 3; ++a) { o[a] = x[a]; d[a] = nd[a]; }
         } else {
+            /* escaped upward; a camera ray that met nothing may look into the sun's disc */
+            if (primary && order == 0) L += sun_seen(op, s, d);
             break;
         }
     }
@@ -940,16 +988,19 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
                 camera_ray(cam, px, py, u1, u2, o, d);
             }
             if (cam->type == 2) {
-                L = s[2] > 0.0 ? op->S * sun_transmissivity(f, o, s) : 0.0;
+                double w[3];
+                sun_sample(op, s, &r, w);
+                L = (s[2] > 0.0 && w[2] > 0.0) ? op->S * cone_gain(op) * (w[2] / s[2]) * sun_transmissivity(f, o, w)
+                                               : 0.0;
                 if (op->max_scatter != 0 && s[2] > 0.0) {
                     double v1 = rng_u01(&r), v2 = rng_u01(&r), rr = sqrt(v1), phi = 2.0 * ORC_PI * v2;
                     d[0] = rr * cos(phi);
                     d[1] = rr * sin(phi);
                     d[2] = sqrt(fmax(0.0, 1.0 - v1));
-                    L += ORC_PI / s[2] * radiance_path(f, op, s, o, d, &r, counters);
+                    L += ORC_PI / s[2] * radiance_path(f, op, s, o, d, 0, &r, counters);
                 }
             } else {
-                L = radiance_path(f, op, s, o, d, &r, counters);
+                L = radiance_path(f, op, s, o, d, 1, &r, counters);
             }
             if (counters) counters[2]++;
             acc += L;

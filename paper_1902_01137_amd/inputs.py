@@ -68,6 +68,7 @@ class Optics:
     majorant_scale: float = 1.0
     max_scatter: int = -1          # -1: unlimited
     max_segments: int = 1_000_000  # per path, counted when hit
+    sun_half_angle_deg: float = 0.0  # angular radius of the solar disc (0: directional sun)
 
 
 @dataclass

@@ -259,3 +259,95 @@ def test_sensor_reciprocity_with_forward_photons(orc):
     assert np.abs(z).max() < 4.0, z
     zg = (Tb.mean() - Tf.mean()) / math.sqrt((sef ** 2).sum() + (seb ** 2).sum()) * n * n
     assert abs(zg) < 4.0, zg
+
+
+# ---------------------------------------------------------------- the solar disc
+
+def _cone_mean(tau, alpha_deg):
+    """E over a direction w drawn uniformly in a cone of half-angle alpha about
+    the zenith of gain w_z exp(-tau / w_z), gain = 2 / (1 + cos alpha): the
+    solar disc's irradiance on a horizontal plane under a pure absorber of
+    vertical optical depth tau, per unit S (quadrature of the cap integral)."""
+    ca = math.cos(math.radians(alpha_deg))
+    val, _ = integrate.quad(lambda m: m * math.exp(-tau / m), ca, 1.0, epsabs=1e-14, epsrel=1e-12)
+    return 2.0 / (1.0 + ca) * val / (1.0 - ca)
+
+
+@pytest.mark.parametrize("alpha", [0.265, 5.0, 30.0])
+def test_disc_sun_over_lambertian_ground(orc, alpha):
+    """Pure absorber over a Lambertian ground, sun disc at the zenith: the
+    ground's local estimate averages the cap integral of the disc's radiance
+    times cos exp(-tau / cos); the camera sees it through exp(-tau / mu)."""
+    tau, H, rho, mu = 0.8, 0.4, 0.3, 0.7
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=rho, sun_zenith_deg=0.0, sun_half_angle_deg=alpha)
+    cam = _slab_camera(mu, H)
+    spp = 40000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=13)
+    exact = rho / math.pi * _cone_mean(tau, alpha) * math.exp(-tau / mu)
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / spp)
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact), (m, e, exact)
+    if alpha == 0.265:
+        # a quarter-degree disc is the directional sun to 1e-5
+        assert _cone_mean(tau, alpha) == pytest.approx(math.exp(-tau), rel=1e-4)
+
+
+def test_disc_sun_seen_by_the_camera(orc):
+    """A camera looking straight up at a zenith sun disc through a pure
+    absorber: radiance S / (pi sin^2 alpha) exp(-tau) (Section 4.1's direct
+    sun), Bernoulli with probability exp(-tau); looking 2 alpha away: zero."""
+    tau, H, alpha = 0.5, 0.4, 4.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.0, sun_zenith_deg=0.0, sun_half_angle_deg=alpha, sun_irradiance=1.5)
+    Ls = 1.5 / (math.pi * math.sin(math.radians(alpha)) ** 2)
+    spp = 20000
+    up = Camera(type=1, pos=(0.0, 0.0, -0.2), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                width=2, height=2)
+    s, s2, _ = orc.render(desc, k, 0.0, op, up, spp, seed=14)
+    p = math.exp(-tau)
+    se = Ls * math.sqrt(p * (1 - p) / spp)
+    for m in s / spp:
+        assert z_ok(m, se, Ls * p)
+    t = math.radians(2 * alpha)
+    off = Camera(type=1, pos=(0.0, 0.0, -0.2), target=(math.sin(t), 0.0, -0.2 + math.cos(t)), up=(0.0, 1.0, 0.0),
+                 ortho_w=0.1, ortho_h=0.1, width=2, height=2)
+    s, _, _ = orc.render(desc, k, 0.0, op, off, 200, seed=15)
+    assert np.all(s == 0.0)
+
+
+def test_disc_sun_sensor(orc):
+    """The irradiance sensor under a pure absorber with a zenith sun disc:
+    each path's direct term is S gain w_z exp(-tau / w_z) for a w drawn in
+    the cone; its mean is the cap integral."""
+    tau, H, alpha = 0.8, 0.4, 20.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.0, sun_zenith_deg=0.0, sun_half_angle_deg=alpha, sun_irradiance=2.0)
+    cam = Camera(type=2, pos=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                 width=2, height=2)
+    spp = 20000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=16)
+    exact = 2.0 * _cone_mean(tau, alpha)
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / spp)
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact), (m, e, exact)
+
+
+def test_disc_sun_tends_to_the_directional_sun(orc):
+    """On the small cloud, a 0.01-degree disc gives the directional sun's image
+    within the combined standard errors (8x8 blocks)."""
+    from paper_1902_01137_amd import inputs
+    from stats import block, compare, mean_se
+    sc = inputs.scene_small()
+    cam = Camera(**{**vars(sc.camera), "width": 16, "height": 16, "ortho_w": sc.camera.ortho_w,
+                    "ortho_h": sc.camera.ortho_h})
+    spp = 64
+    a = orc.render(sc.desc, sc.kc, sc.grid.k_gas, sc.optics, cam, spp, seed=21)
+    op = Optics(**{**vars(sc.optics), "sun_half_angle_deg": 0.01})
+    b = orc.render(sc.desc, sc.kc, sc.grid.k_gas, op, cam, spp, seed=22)
+    ma, sa = mean_se(a[0], a[1], spp)
+    mb, sb = mean_se(b[0], b[1], spp)
+    res = compare(*block(ma, sa, (16, 16)), *block(mb, sb, (16, 16)))
+    assert res["ok"], res
