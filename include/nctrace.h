@@ -92,13 +92,22 @@ typedef struct {
  * majorant_scale * (kmax_c + k_gas), majorant_scale >= 1.  max_scatter >= 0
  * limits the number of scattering/reflection events whose sun contribution
  * is counted (-1: unlimited); max_segments caps tracking steps per path
- * (paths reaching it are stopped and counted as truncated). */
+ * (paths reaching it are stopped and counted as truncated).
+ * sun_half_angle_deg > 0 makes the sun a disc of that angular radius (the
+ * solar cone of Section 4.1) with uniform radiance S / (pi sin^2 alpha), S =
+ * sun_irradiance through a plane normal to its centre: local estimates go
+ * along a direction drawn uniformly in the cone (weight 2 / (1 + cos alpha)),
+ * and a camera ray that escapes without any event inside the disc sees it;
+ * 0 is the directional sun; [0, 90) degrees, and for a sensor (camera type 2)
+ * zenith + half angle < 90.  nc_flux and nc_flux_adjoint take the directional
+ * sun only (NC_ERR_UNSUPPORTED otherwise). */
 typedef struct {
     double ssa, g, ground_albedo;
     double sun_zenith_deg, sun_azimuth_deg, sun_irradiance;
     double majorant_scale;
     int32_t max_scatter;
     int32_t max_segments;
+    double sun_half_angle_deg;
 } nc_optics;
 
 /* Camera (Section 4.1, Table 3): type 0 pinhole with vertical field of view

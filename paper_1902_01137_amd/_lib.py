@@ -37,7 +37,8 @@ class GridParams(C.Structure):
 class Optics(C.Structure):
     _fields_ = [("ssa", C.c_double), ("g", C.c_double), ("ground_albedo", C.c_double),
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double), ("sun_irradiance", C.c_double),
-                ("majorant_scale", C.c_double), ("max_scatter", C.c_int32), ("max_segments", C.c_int32)]
+                ("majorant_scale", C.c_double), ("max_scatter", C.c_int32), ("max_segments", C.c_int32),
+                ("sun_half_angle_deg", C.c_double)]
 
 
 class Camera(C.Structure):

@@ -30,7 +30,7 @@ def _desc(d: FieldDesc):
 
 def _optics(o: Optics):
     return _lib.Optics(o.ssa, o.g, o.ground_albedo, o.sun_zenith_deg, o.sun_azimuth_deg, o.sun_irradiance,
-                       o.majorant_scale, o.max_scatter, o.max_segments)
+                       o.majorant_scale, o.max_scatter, o.max_segments, o.sun_half_angle_deg)
 
 
 def _camera(c: Camera):

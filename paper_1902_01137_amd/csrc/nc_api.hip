@@ -63,7 +63,15 @@ nc_status check_optics(nc_ctx *ctx, const nc_optics *o)
     if (!(o->majorant_scale >= 1.0) || !std::isfinite(o->majorant_scale))
         return fail(ctx, NC_ERR_RANGE, "majorant_scale must be finite and >= 1");
     if (o->max_segments < 1) return fail(ctx, NC_ERR_INVALID_ARG, "max_segments must be >= 1");
+    if (!(o->sun_half_angle_deg >= 0.0 && o->sun_half_angle_deg < 90.0))
+        return fail(ctx, NC_ERR_RANGE, "sun half angle must be in [0,90) degrees");
     return NC_OK;
+}
+
+// an irradiance sensor needs the whole sun above the horizon
+bool sensor_sun_ok(const nc_optics *o)
+{
+    return o->sun_zenith_deg + o->sun_half_angle_deg < 90.0;
 }
 
 nc_status check_grid(nc_ctx *ctx, const nc_grid *g)
@@ -81,6 +89,11 @@ nc::OptView make_opt(const nc_optics *o, double k_gas)
     v.ssa = (float)o->ssa;
     v.g = (float)o->g;
     v.hg = nc::make_hg(o->g);
+    const double a = o->sun_half_angle_deg * M_PI / 180.0;
+    v.cone = a > 0.0 ? 1 : 0;
+    v.cone_cos = (float)std::cos(a);
+    v.cone_gain = (float)(2.0 / (1.0 + std::cos(a)));
+    v.cone_L = a > 0.0 ? (float)(1.0 / (M_PI * std::sin(a) * std::sin(a))) : 0.0f;
     v.rho = (float)o->ground_albedo;
     v.S = (float)o->sun_irradiance;
     v.mscale = (float)o->majorant_scale;
@@ -461,7 +474,7 @@ static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, co
         return fail(ctx, NC_ERR_INVALID_ARG, "sample_offset + spp must fit in 32 bits");
     if (!d_kc || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL buffer");
     DeviceGuard guard(ctx->device);
-    if (cam.type == 2 && !(std::cos(optics->sun_zenith_deg * M_PI / 180.0) > 0.0))
+    if (cam.type == 2 && !sensor_sun_ok(optics))
         return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
     if ((s->flags & NC_SUN_ESTIMATOR_MASK) == 3) return fail(ctx, NC_ERR_INVALID_ARG, "unknown sun estimator");
     if (guide && guide->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
@@ -624,11 +637,11 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
         if ((st = check_optics(ctx, optics + j)) != NC_OK) return st;
         const nc_optics &a = optics[0], &b = optics[j];
         if (a.ssa != b.ssa || a.g != b.g || a.majorant_scale != b.majorant_scale || a.max_scatter != b.max_scatter ||
-            a.max_segments != b.max_segments)
+            a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg)
             return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
         nc::CamView cam;
         if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;
-        if (cam.type == 2 && !(std::cos(optics[j].sun_zenith_deg * M_PI / 180.0) > 0.0))
+        if (cam.type == 2 && !sensor_sun_ok(optics + j))
             return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
         jobs[j] = make_job(cam, optics + j, out_offsets[j]);
     }
@@ -735,6 +748,8 @@ static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     nc_status st = check_grid(ctx, g);
     if (st != NC_OK) return st;
     if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    if (optics->sun_half_angle_deg != 0.0)
+        return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the directional sun only");
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (!(scale > 0.0) || !std::isfinite(scale)) return fail(ctx, NC_ERR_RANGE, "extinction_scale must be > 0");
     if (px_nx < 1 || px_ny < 1 || (long long)px_nx * px_ny > (1ll << 28))

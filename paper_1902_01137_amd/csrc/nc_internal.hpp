@@ -86,6 +86,10 @@ struct CamView {
 struct OptView {
     float ssa, g, rho, S, mscale;
     HGc hg;              // the phase function's constants
+    int cone;            // the sun is a disc (else directional)
+    float cone_cos;      // cos of its angular radius
+    float cone_gain;     // 2 / (1 + cos alpha): a local estimate's weight for a direction drawn in the cone
+    float cone_L;        // its radiance per unit irradiance, 1 / (pi sin^2 alpha)
     float sun[3];
     float ground_w;      // rho / pi * S * cos(theta_sun): ground local estimate before transmissivity
     int max_scatter, max_segments;

@@ -868,6 +868,16 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     return o;
 }
 
+// A direction drawn uniformly in the solar disc's cone about s (cosine
+// uniform on [cos alpha, 1], azimuth 2 pi u2).
+__device__ inline void cone_dir(const float s[3], float cos_a, float u1, float u2, float w[3])
+{
+    w[0] = s[0];
+    w[1] = s[1];
+    w[2] = s[2];
+    turn(w, 1.0f - u1 * (1.0f - cos_a), u2);
+}
+
 // The number that picks the lobe: given u_sel < c, u_sel / c is uniform on
 // [0, 1) and independent of the branch taken (unused otherwise).
 __device__ inline float lobe_uniform(float u_sel, float c)
@@ -1166,8 +1176,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     const float kd = g.kscale * kc_hit;
                     kev = kd + g.k_gas;
                     const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + g.k_gas);
+                    float gain = 1.0f;
+                    if (A.op.cone) {
+                        // solar disc: the local estimate's direction drawn in its cone
+                        const volatile JobView &J = R.jobs[job];
+                        const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
+                        const float c1 = rng.take(), c2 = rng.take();
+                        float w[3];
+                        cone_dir(s0, A.op.cone_cos, c1, c2, w);
+                        sun[0] = w[0];
+                        sun[1] = w[1];
+                        sun[2] = w[2];
+                        gain = A.op.cone_gain;
+                    }
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * hg_phase(A.op.hg, mu);
+                    w_nee = ssa * hg_phase(A.op.hg, mu) * gain;
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
@@ -1188,7 +1211,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     r.o[1] = r.o[1] + tg * r.d[1];
                     r.o[2] = 0.0f;
                     const float rho = R.jobs[job].rho;
-                    w_nee = rho * (1.0f / kPi) * sun[2];
+                    float gain = 1.0f;
+                    if (A.op.cone) {
+                        const volatile JobView &J = R.jobs[job];
+                        const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
+                        const float c1 = rng.take(), c2 = rng.take();
+                        float w[3];
+                        cone_dir(s0, A.op.cone_cos, c1, c2, w);
+                        sun[0] = w[0];
+                        sun[1] = w[1];
+                        sun[2] = w[2];
+                        gain = A.op.cone_gain;
+                    }
+                    w_nee = rho * (1.0f / kPi) * sun[2] * gain;   // <= 0 (no sun ray) when the direction is below the horizon
                     p_cont = rho;
                     ground_ev = true;
                     vc.lev = g.L;
@@ -1203,10 +1238,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         cont = true;
                     }
                 } else {
-                    phase = kPhSample;           // escaped upward
+                    // escaped upward: a camera ray that met nothing may look into the solar disc
+                    if (A.op.cone && order == 0 && !ground_ev) {
+                        const volatile JobView &J = R.jobs[job];
+                        if (r.d[0] * J.sun[0] + r.d[1] * J.sun[1] + r.d[2] * J.sun[2] >= A.op.cone_cos)
+                            Lp += beta * A.op.cone_L;
+                    }
+                    phase = kPhSample;
                 }
                 if (cont) {
                     shadow = false;
+                    // (the disc's draw may have left too few numbers for the scattering)
+                    if (A.op.cone)
+                        rng.need(kMode == kGuided ? 4 : 3, (uint32_t)pix, A.sample_base + (uint32_t)s,
+                                 A.stream_base + (uint32_t)job, A.key0, A.key1);
                     if (A.op.max_scatter >= 0 && order >= A.op.max_scatter) {
                         phase = kPhSample;
                     } else if (rng.take() >= p_cont) {
@@ -1414,6 +1459,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 sun[0] = J.sun[0];
                 sun[1] = J.sun[1];
                 sun[2] = J.sun[2];
+                ground_ev = false;
 #pragma unroll
                 for (int a = 0; a < 3; ++a) r.o[a] = o[a];
                 Lp = 0.0f;
@@ -1430,7 +1476,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     // weight 1), then, as after a ground reflection that always
                     // happens, a cosine-distributed upward path of weight pi / mu_sun
                     beta = kPi / sun[2];
-                    w_nee = sun[2] * (1.0f / kPi);
+                    float gain = 1.0f;
+                    if (A.op.cone) {
+                        // the direct beam along a direction drawn in the disc's cone
+                        const float s0[3] = {sun[0], sun[1], sun[2]};
+                        const float c1 = rng.take(), c2 = rng.take();
+                        float w[3];
+                        cone_dir(s0, A.op.cone_cos, c1, c2, w);
+                        sun[0] = w[0];
+                        sun[1] = w[1];
+                        sun[2] = w[2];
+                        gain = A.op.cone_gain;
+                    }
+                    w_nee = sun[2] * (1.0f / kPi) * gain;
                     p_cont = 1.0f;
                     ground_ev = true;
                     shadow = true;

@@ -352,3 +352,103 @@ def test_unknown_sun_estimator_is_rejected():
     with pytest.raises(_lib.NcError) as e:
         api.render(c, g, kd, sc.optics, sc.camera, Sampling(seed=1, spp=1, flags=3))
     assert e.value.status == _lib.NC_ERR_INVALID_ARG
+
+
+# ---------------------------------------------------------------- the solar disc (Section 4.1's solar cone)
+
+def _cone_mean(tau, alpha_deg):
+    """E over w uniform in a cone of half-angle alpha about the zenith of
+    gain w_z exp(-tau / w_z), gain = 2 / (1 + cos alpha) (cap quadrature)."""
+    from scipy import integrate
+    ca = math.cos(math.radians(alpha_deg))
+    val, _ = integrate.quad(lambda m: m * math.exp(-tau / m), ca, 1.0, epsabs=1e-14, epsrel=1e-12)
+    return 2.0 / (1.0 + ca) * val / (1.0 - ca)
+
+
+@pytest.mark.parametrize("alpha", [0.265, 10.0, 30.0])
+def test_disc_sun_over_lambertian_ground(alpha):
+    """Pure absorber over a Lambertian ground, zenith sun disc: the ground's
+    local estimate averages the cap integral (delta-tracked sun rays)."""
+    tau, H, rho, mu = 0.8, 0.4, 0.3, 0.7
+    desc, k = inputs.slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=rho, sun_zenith_deg=0.0, sun_half_angle_deg=alpha)
+    spp = 50000
+    s, s2 = _render(desc, k, 0.0, 1.0, op, _slab_camera(mu, H), spp, seed=77)
+    exact = rho / math.pi * _cone_mean(tau, alpha) * math.exp(-tau / mu)
+    m, se = mean_se(s, s2, spp)
+    assert np.all(np.abs(m - exact) < 4.5 * se), (m, exact, se)
+
+
+def test_disc_sun_seen_by_the_camera():
+    """Looking straight up at a zenith disc through a pure absorber:
+    S / (pi sin^2 alpha) exp(-tau); looking 2 alpha away: nothing."""
+    tau, H, alpha = 0.5, 0.4, 4.0
+    desc, k = inputs.slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.0, sun_zenith_deg=0.0, sun_half_angle_deg=alpha, sun_irradiance=1.5)
+    Ls = 1.5 / (math.pi * math.sin(math.radians(alpha)) ** 2)
+    spp = 20000
+    up = Camera(type=1, pos=(0.0, 0.0, -0.2), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                width=4, height=4)
+    s, s2 = _render(desc, k, 0.0, 1.0, op, up, spp, seed=78)
+    p = math.exp(-tau)
+    se = Ls * math.sqrt(p * (1 - p) / spp)
+    assert np.all(np.abs(s / spp - Ls * p) < 4.5 * se), (s / spp, Ls * p, se)
+    t = math.radians(2 * alpha)
+    off = Camera(type=1, pos=(0.0, 0.0, -0.2), target=(math.sin(t), 0.0, -0.2 + math.cos(t)), up=(0.0, 1.0, 0.0),
+                 ortho_w=0.1, ortho_h=0.1, width=4, height=4)
+    s, _ = _render(desc, k, 0.0, 1.0, op, off, 512, seed=79)
+    assert np.all(s == 0.0)
+
+
+def test_disc_sun_sensor():
+    """Irradiance sensor under a pure absorber, zenith disc: the direct
+    term's mean is S times the cap integral."""
+    tau, H, alpha = 0.8, 0.4, 20.0
+    desc, k = inputs.slab_field([tau / H], H)
+    op = Optics(ssa=0.0, g=0.85, ground_albedo=0.0, sun_zenith_deg=0.0, sun_half_angle_deg=alpha, sun_irradiance=2.0)
+    cam = Camera(type=2, pos=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                 width=4, height=4)
+    spp = 20000
+    s, s2 = _render(desc, k, 0.0, 1.0, op, cam, spp, seed=80)
+    m, se = mean_se(s, s2, spp)
+    exact = 2.0 * _cone_mean(tau, alpha)
+    assert np.all(np.abs(m - exact) < 4.5 * se), (m, exact, se)
+
+
+def test_small_cloud_disc_sun_vs_oracle():
+    """A 5-degree disc on the small cloud scene (nadir view: the disc enters
+    through the local estimates at every event): GPU image against the
+    oracle's."""
+    sc = inputs.scene_small()
+    op = Optics(**{**vars(sc.optics), "sun_half_angle_deg": 5.0})
+    spp_g, spp_o = 256, 128
+    s, s2 = _render(sc.desc, sc.kc, sc.grid.k_gas, sc.grid.tau_tilde, op, sc.camera, spp_g, seed=1011)
+    os_, os2, _ = oracle.render(sc.desc, sc.kc, sc.grid.k_gas, op, sc.camera, spp_o, inputs.SEED_ORACLE_BASE + 11)
+    gm, gse = mean_se(s, s2, spp_g)
+    om, ose = mean_se(os_, os2, spp_o)
+    res = compare(*block(gm, gse, (64, 64)), *block(om, ose, (64, 64)))
+    assert res["ok"], res
+    res_px = compare(gm, gse, om, ose)
+    assert res_px["ok"], res_px
+
+
+def test_disc_sun_argument_checks():
+    sc = inputs.scene_small()
+    c = ctx()
+    kd = device_field(sc.kc)
+    g = api.build_grid(c, kd, sc.desc, sc.grid)
+    for bad in (-1.0, 90.0, float("nan")):
+        op = Optics(**{**vars(sc.optics), "sun_half_angle_deg": bad})
+        with pytest.raises(_lib.NcError) as e:
+            api.render(c, g, kd, op, sc.camera, Sampling(seed=1, spp=1))
+        assert e.value.status == _lib.NC_ERR_RANGE
+    op = Optics(**{**vars(sc.optics), "sun_half_angle_deg": 1.0})
+    with pytest.raises(_lib.NcError) as e:
+        api.flux(c, g, kd, op, (4, 4), 1000, Sampling(seed=1, spp=1))
+    assert e.value.status == _lib.NC_ERR_UNSUPPORTED
+    sensor = Camera(type=2, pos=(0.0, 0.0, 0.0), target=(0.0, 0.0, 1.0), up=(0.0, 1.0, 0.0), ortho_w=0.1, ortho_h=0.1,
+                    width=2, height=2)
+    op = Optics(**{**vars(sc.optics), "sun_zenith_deg": 80.0, "sun_half_angle_deg": 15.0})
+    with pytest.raises(_lib.NcError) as e:
+        api.render(c, g, kd, op, sensor, Sampling(seed=1, spp=1))
+    assert e.value.status == _lib.NC_ERR_RANGE
