@@ -294,20 +294,25 @@ def progressive_run(ctx, sc, kc, gd, args):
 
 
 def estimator_run(ctx, sc, kc, spp, build_ms):
-    """The same step with each sun-ray estimator: render time, error and time to 1 %."""
+    """The same step with each sun-ray estimator, and with the solar disc:
+    render time, error and time to 1 %."""
     import torch
 
     from paper_1902_01137_amd import _lib, api, inputs
     g = api.build_grid(ctx, kc, sc.desc, sc.grid)
     cam = sc.camera
     res = {}
-    for name, fl in (("delta", _lib.NC_SUN_DELTA), ("ratio", _lib.NC_SUN_RATIO), ("residual", _lib.NC_SUN_RESIDUAL)):
+    # the last line: the sun as the 0.265-degree disc it is (the solar cone of Section 4.1)
+    disc = inputs.Optics(**{**vars(sc.optics), "sun_half_angle_deg": 0.265})
+    for name, fl, op in (("delta", _lib.NC_SUN_DELTA, sc.optics), ("ratio", _lib.NC_SUN_RATIO, sc.optics),
+                         ("residual", _lib.NC_SUN_RESIDUAL, sc.optics),
+                         ("residual_disc_0.265deg", _lib.NC_SUN_RESIDUAL, disc)):
         smp = inputs.Sampling(seed=sc.sampling.seed + 61, spp=spp, flags=fl)
-        api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=1, spp=1, flags=fl))   # warm-up
+        api.render(ctx, g, kc, op, cam, inputs.Sampling(seed=1, spp=1, flags=fl))   # warm-up
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record()
-        s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp)
+        s, s2 = api.render(ctx, g, kc, op, cam, smp)
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
