@@ -42,7 +42,8 @@ class OpticsC(C.Structure):
     _fields_ = [("ssa", C.c_double), ("g", C.c_double), ("rho", C.c_double),
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double),
                 ("S", C.c_double), ("majorant_scale", C.c_double),
-                ("max_scatter", C.c_int32), ("max_segments", C.c_int32), ("sun_half_angle_deg", C.c_double)]
+                ("max_scatter", C.c_int32), ("max_segments", C.c_int32), ("sun_half_angle_deg", C.c_double),
+                ("tab_n", C.c_int32), ("tab_pad_", C.c_int32), ("tab_mu", C.c_void_p), ("tab_p", C.c_void_p)]
 
 
 class CameraC(C.Structure):
@@ -79,6 +80,10 @@ def lib():
         L.orc_hg_phase.restype = C.c_double
         L.orc_hg_sample_mu.argtypes = [C.c_double, C.c_double]
         L.orc_hg_sample_mu.restype = C.c_double
+        L.orc_tab_phase.argtypes = [_P, _P, C.c_int32, C.c_double]
+        L.orc_tab_phase.restype = C.c_double
+        L.orc_tab_sample.argtypes = [_P, _P, C.c_int32, C.c_double]
+        L.orc_tab_sample.restype = C.c_double
         L.orc_camera_ray.argtypes = [C.POINTER(CameraC), C.c_int, C.c_int, C.c_double, C.c_double, _P]
         L.orc_render.argtypes = [C.POINTER(Field), C.POINTER(OpticsC), C.POINTER(CameraC), C.c_int32, C.c_uint64,
                                  _P, C.c_int32, _P, _P, _P]
@@ -106,8 +111,30 @@ def make_field(desc, kc: np.ndarray, k_gas: float = 0.0, kscale: float = 1.0):
 
 
 def make_optics(op) -> OpticsC:
-    return OpticsC(op.ssa, op.g, op.ground_albedo, op.sun_zenith_deg, op.sun_azimuth_deg, op.sun_irradiance,
-                   op.majorant_scale, op.max_scatter, op.max_segments, getattr(op, "sun_half_angle_deg", 0.0))
+    """The optics record; a tabulated phase function (op.phase_table = (mu, p)) replaces HG."""
+    o = OpticsC(op.ssa, op.g, op.ground_albedo, op.sun_zenith_deg, op.sun_azimuth_deg, op.sun_irradiance,
+                op.majorant_scale, op.max_scatter, op.max_segments, getattr(op, "sun_half_angle_deg", 0.0))
+    tab = getattr(op, "phase_table", None)
+    if tab is not None:
+        mu = np.ascontiguousarray(tab[0], dtype=np.float64)
+        p = np.ascontiguousarray(tab[1], dtype=np.float64)
+        o.tab_n = len(mu)
+        o.tab_mu = mu.ctypes.data
+        o.tab_p = p.ctypes.data
+        o._keep = (mu, p)
+    return o
+
+
+def tab_phase(mu, p, m):
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    return lib().orc_tab_phase(_ptr(mu), _ptr(p), len(mu), float(m))
+
+
+def tab_sample(mu, p, xi):
+    mu = np.ascontiguousarray(mu, dtype=np.float64)
+    p = np.ascontiguousarray(p, dtype=np.float64)
+    return lib().orc_tab_sample(_ptr(mu), _ptr(p), len(mu), float(xi))
 
 
 def make_camera(cam) -> CameraC:

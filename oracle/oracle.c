@@ -110,6 +110,9 @@ typedef struct {
     double ssa, g, rho, sun_zenith_deg, sun_azimuth_deg, S, majorant_scale;
     int32_t max_scatter, max_segments;
     double sun_half_angle_deg;   /* angular radius of the solar disc; 0: directional sun */
+    int32_t tab_n, tab_pad_;     /* tabulated phase function (n >= 2 nodes) instead of HG; 0: HG */
+    const double *tab_mu;        /* node cosines, -1 = mu_0 < ... < mu_{n-1} = 1 */
+    const double *tab_p;         /* phase function at the nodes (any positive scale) */
 } orc_optics;
 
 typedef struct {
@@ -754,6 +757,61 @@ double orc_hg_sample_mu(double g, double xi)
     }
 }
 
+/* A tabulated phase function (Section 4.1 takes the droplets' phase
+ * function from Mie tables): values p_i at cosines mu_i, linear in mu between
+ * nodes, scaled so that 2 pi times its integral over [-1, 1] is 1 (per
+ * steradian).  tab_scale returns that scale. */
+static double tab_scale(const double *mu, const double *p, int n)
+{
+    double a = 0.0;
+    int i;
+    for (i = 0; i + 1 < n; ++i) a += 0.5 * (p[i] + p[i + 1]) * (mu[i + 1] - mu[i]);
+    return 1.0 / (2.0 * ORC_PI * a);
+}
+
+double orc_tab_phase(const double *mu, const double *p, int32_t n, double m)
+{
+    int i = 0;
+    double t;
+    while (i + 2 < n && mu[i + 1] <= m) ++i;      /* the node interval holding m */
+    t = (m - mu[i]) / (mu[i + 1] - mu[i]);
+    return ((1.0 - t) * p[i] + t * p[i + 1]) * tab_scale(mu, p, n);
+}
+
+/* Inverse CDF: the cosine m with 2 pi int_{-1}^{m} p = xi, by bisection on
+ * the exact (piecewise quadratic) CDF. */
+double orc_tab_sample(const double *mu, const double *p, int32_t n, double xi)
+{
+    double c = tab_scale(mu, p, n), acc = 0.0, lo, hi, base;
+    int i = 0, it;
+    for (;;) {
+        double seg = 2.0 * ORC_PI * c * 0.5 * (p[i] + p[i + 1]) * (mu[i + 1] - mu[i]);
+        if (xi < acc + seg || i + 2 >= n) break;
+        acc += seg;
+        ++i;
+    }
+    base = acc;
+    lo = mu[i];
+    hi = mu[i + 1];
+    for (it = 0; it < 64; ++it) {
+        double m = 0.5 * (lo + hi), x = m - mu[i];
+        double pm = p[i] + (p[i + 1] - p[i]) * x / (mu[i + 1] - mu[i]);
+        double F = base + 2.0 * ORC_PI * c * 0.5 * (p[i] + pm) * x;
+        if (F < xi) lo = m; else hi = m;
+    }
+    return 0.5 * (lo + hi);
+}
+
+static double phase_eval(const orc_optics *op, double mu)
+{
+    return op->tab_n >= 2 ? orc_tab_phase(op->tab_mu, op->tab_p, op->tab_n, mu) : orc_hg_phase(op->g, mu);
+}
+
+static double phase_sample(const orc_optics *op, double xi)
+{
+    return op->tab_n >= 2 ? orc_tab_sample(op->tab_mu, op->tab_p, op->tab_n, xi) : orc_hg_sample_mu(op->g, xi);
+}
+
 static void normalize3(double v[3])
 {
     double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
@@ -928,12 +986,12 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
                 double w[3];
                 sun_sample(op, s, r, w);
                 mu_sun = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
-                L += ssa * orc_hg_phase(op->g, mu_sun) * op->S * gain * sun_transmissivity(f, x, w);
+                L += ssa * phase_eval(op, mu_sun) * op->S * gain * sun_transmissivity(f, x, w);
             }
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
             if (rng_u01(r) >= ssa) break;
             {
-                double mu = orc_hg_sample_mu(op->g, rng_u01(r));
+                double mu = phase_sample(op, rng_u01(r));
                 double phi = 2.0 * ORC_PI * rng_u01(r);
                 rotate_about(d, mu, phi, nd);
             }

@@ -69,6 +69,7 @@ class Optics:
     max_scatter: int = -1          # -1: unlimited
     max_segments: int = 1_000_000  # per path, counted when hit
     sun_half_angle_deg: float = 0.0  # angular radius of the solar disc (0: directional sun)
+    phase_table: object = None       # (mu, p): tabulated phase function instead of HG (cosines -1..1, values)
 
 
 @dataclass
@@ -285,6 +286,20 @@ def random_rays(desc: FieldDesc, n: int, seed: int, inside_frac=0.5, axis_frac=0
     d = r32[:, 3:].astype(np.float64)
     r32[:, 3:] = (d / np.linalg.norm(d, axis=1, keepdims=True)).astype(np.float32)
     return r32
+
+
+def phase_table_tthg(g1=0.92, g2=-0.35, w=0.96, n=181):
+    """A synthetic tabulated phase function with the shape of a droplet Mie
+    function (strong forward peak, weak backward lobe): a two-term HG mixture
+    sampled at n cosines whose angles are uniform in [0, pi] (dense near the
+    peak).  Returns (mu ascending from -1 to 1, p) in float64."""
+    th = np.linspace(np.pi, 0.0, n)
+    mu = np.cos(th)
+    mu[0], mu[-1] = -1.0, 1.0
+
+    def hg(g):
+        return (1 - g * g) / (4 * np.pi * (1 + g * g - 2 * g * mu) ** 1.5)
+    return mu, w * hg(g1) + (1 - w) * hg(g2)
 
 
 def sun_direction(zenith_deg, azimuth_deg):

@@ -351,3 +351,75 @@ def test_disc_sun_tends_to_the_directional_sun(orc):
     mb, sb = mean_se(b[0], b[1], spp)
     res = compare(*block(ma, sa, (16, 16)), *block(mb, sb, (16, 16)))
     assert res["ok"], res
+
+
+# ---------------------------------------------------------------- tabulated phase function
+
+def test_tabulated_phase_normalisation_and_nodes(orc):
+    from paper_1902_01137_amd.inputs import phase_table_tthg
+    mu, p = phase_table_tthg()
+    scale = 1.0 / (2 * math.pi * np.trapezoid(p, mu))       # the table is linear between nodes: trapezoid is exact
+    for i in (0, 17, 90, 179, 180):
+        assert orc.tab_phase(mu, p, mu[i]) == pytest.approx(p[i] * scale, rel=1e-12)
+    m = 0.3 * mu[40] + 0.7 * mu[41]
+    assert orc.tab_phase(mu, p, m) == pytest.approx((0.3 * p[40] + 0.7 * p[41]) * scale, rel=1e-12)
+    tot, _ = integrate.quad(lambda x: 2 * math.pi * orc.tab_phase(mu, p, x), -1, 1, points=list(mu[1:-1]), limit=400)
+    assert tot == pytest.approx(1.0, rel=1e-9)
+
+
+def test_tabulated_phase_sampler_inverts_cdf(orc):
+    from paper_1902_01137_amd.inputs import phase_table_tthg
+    mu, p = phase_table_tthg(n=61)
+    for xi in (1e-6, 0.01, 0.2, 0.5, 0.8, 0.97, 0.999999):
+        m = orc.tab_sample(mu, p, xi)
+        assert -1.0 <= m <= 1.0
+        F, _ = integrate.quad(lambda x: 2 * math.pi * orc.tab_phase(mu, p, x), -1, m, points=[v for v in mu if v < m],
+                              limit=400)
+        assert F == pytest.approx(xi, abs=1e-9)
+
+
+def test_tabulated_single_scattering_slab(orc):
+    """The single-scattering slab closed form with the table's value at the
+    scattering cosine."""
+    from paper_1902_01137_amd.inputs import phase_table_tthg
+    tab = phase_table_tthg()
+    tau, H, ssa, mu, th0, phi0 = 1.3, 0.5, 0.9, 0.55, 35.0, 60.0
+    desc, k = slab_field([tau / H], H)
+    op = Optics(ssa=ssa, g=0.0, ground_albedo=0.0, sun_zenith_deg=th0, sun_azimuth_deg=phi0, max_scatter=1,
+                phase_table=tab)
+    cam = _slab_camera(mu, H)
+    spp = 20000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=24)
+    mu0 = math.cos(math.radians(th0))
+    sv = np.array([math.sin(math.radians(th0)) * math.cos(math.radians(phi0)),
+                   math.sin(math.radians(th0)) * math.sin(math.radians(phi0)), mu0])
+    d = np.array([math.sqrt(1 - mu * mu), 0.0, -mu])
+    pv = orc.tab_phase(tab[0], tab[1], float(d @ sv))
+    exact = ssa * pv * mu0 / (mu0 + mu) * (1 - math.exp(-tau * (1 / mu0 + 1 / mu)))
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / spp)
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact), (m, e, exact)
+
+
+def test_tabulated_hg_matches_hg_image(orc):
+    """HG tabulated at 2001 cosines renders the small cloud as HG itself."""
+    from paper_1902_01137_amd import inputs
+    from stats import block, compare, mean_se
+    sc = inputs.scene_small()
+    th = np.linspace(np.pi, 0.0, 2001)
+    mu = np.cos(th)
+    mu[0], mu[-1] = -1.0, 1.0
+    g = sc.optics.g
+    ptab = (1 - g * g) / (4 * np.pi * (1 + g * g - 2 * g * mu) ** 1.5)
+    cam = Camera(**{**vars(sc.camera), "width": 16, "height": 16})
+    spp = 64
+    a = orc.render(sc.desc, sc.kc, sc.grid.k_gas, sc.optics, cam, spp, seed=31)
+    op = Optics(**{**vars(sc.optics), "phase_table": (mu, ptab)})
+    b = orc.render(sc.desc, sc.kc, sc.grid.k_gas, op, cam, spp, seed=32)
+    ma, sa = mean_se(a[0], a[1], spp)
+    mb, sb = mean_se(b[0], b[1], spp)
+    res = compare(*block(ma, sa, (16, 16)), *block(mb, sb, (16, 16)))
+    assert res["ok"], res
+    res = compare(ma, sa, mb, sb)
+    assert res["ok"], res
