@@ -55,6 +55,7 @@ typedef int32_t nc_status;
 
 typedef struct nc_ctx nc_ctx;
 typedef struct nc_grid nc_grid;
+typedef struct nc_phase nc_phase;
 
 /* Voxel field geometry: box [x0, x0+nx dx] x [y0, y0+ny dy] x [z0, z0+nz dz]. */
 typedef struct {
@@ -100,7 +101,11 @@ typedef struct {
  * and a camera ray that escapes without any event inside the disc sees it;
  * 0 is the directional sun; [0, 90) degrees, and for a sensor (camera type 2)
  * zenith + half angle < 90.  nc_flux and nc_flux_adjoint take the directional
- * sun only (NC_ERR_UNSUPPORTED otherwise). */
+ * sun only (NC_ERR_UNSUPPORTED otherwise).
+ * phase: a tabulated phase function (nc_phase_create) that replaces HG(g) in
+ * the renderers (local estimates, scattering, the guided step's MIS weight
+ * and its phase-function candidate); NULL = HG.  It must live on the
+ * context's device; nc_flux and nc_flux_adjoint take HG only. */
 typedef struct {
     double ssa, g, ground_albedo;
     double sun_zenith_deg, sun_azimuth_deg, sun_irradiance;
@@ -108,6 +113,7 @@ typedef struct {
     int32_t max_scatter;
     int32_t max_segments;
     double sun_half_angle_deg;
+    const nc_phase *phase;
 } nc_optics;
 
 /* Camera (Section 4.1, Table 3): type 0 pinhole with vertical field of view
@@ -185,6 +191,21 @@ typedef struct {
                                 summed over the trips, [12..17] wave wall-clock ticks spent in the
                                 phase, [18..23] unused */
 } nc_counters;
+
+/* A tabulated phase function (Section 4.1 takes the droplets' phase function
+ * from Mie tables): values h_p[i] >= 0 at cosines h_mu[i] (host arrays, n >= 2,
+ * h_mu[0] = -1 < ... < h_mu[n-1] = 1), linear in the cosine between nodes,
+ * scaled by the library so that 2 pi times its integral is 1 (per
+ * steradian).  Sampling inverts its piecewise-quadratic CDF.  The object holds
+ * device copies (float32 cosines, values and CDF at the nodes) and may be
+ * shared by any number of nc_optics on its device.  NC_ERR_RANGE for a bad
+ * table. */
+nc_status nc_phase_create(nc_ctx *ctx, const double *h_mu, const double *h_p, int32_t n, nc_phase **out);
+void nc_phase_destroy(nc_phase *phase);
+/* The phase function's sampler and value on the GPU (for testing): for n
+ * uniforms d_u in [0,1), d_out[2i] = the sampled cosine, d_out[2i+1] = the
+ * phase function at it (per steradian).  Device float arrays. */
+nc_status nc_phase_sample(nc_ctx *ctx, const nc_phase *phase, const float *d_u, int32_t n, float *d_out);
 
 /* Library ABI version (NC_ABI_VERSION). */
 uint32_t nc_abi_version(void);

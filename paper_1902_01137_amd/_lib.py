@@ -38,7 +38,7 @@ class Optics(C.Structure):
     _fields_ = [("ssa", C.c_double), ("g", C.c_double), ("ground_albedo", C.c_double),
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double), ("sun_irradiance", C.c_double),
                 ("majorant_scale", C.c_double), ("max_scatter", C.c_int32), ("max_segments", C.c_int32),
-                ("sun_half_angle_deg", C.c_double)]
+                ("sun_half_angle_deg", C.c_double), ("phase", C.c_void_p)]
 
 
 class Camera(C.Structure):
@@ -80,6 +80,9 @@ class ProgressReport(C.Structure):
 _P = C.c_void_p
 _SIGS = [
     ("nc_abi_version", C.c_uint32, []),
+    ("nc_phase_create", C.c_int32, [_P, _P, _P, C.c_int32, C.POINTER(_P)]),
+    ("nc_phase_destroy", None, [_P]),
+    ("nc_phase_sample", C.c_int32, [_P, _P, _P, C.c_int32, _P]),
     ("nc_ctx_create", C.c_int32, [C.c_int32, _P, C.POINTER(_P)]),
     ("nc_ctx_set_stream", C.c_int32, [_P, _P]),
     ("nc_ctx_destroy", None, [_P]),

@@ -8,6 +8,8 @@ from __future__ import annotations
 import ctypes as C
 from dataclasses import asdict
 
+import numpy as np
+
 import torch
 
 from . import _lib
@@ -28,9 +30,64 @@ def _desc(d: FieldDesc):
     return _lib.FieldDesc(d.nx, d.ny, d.nz, 0, d.x0, d.y0, d.z0, d.dx, d.dy, d.dz)
 
 
-def _optics(o: Optics):
+class PhaseTable:
+    """A tabulated phase function on the device (nc_phase_*): values p at
+    cosines mu (-1 .. 1, increasing), linear in between, normalised by the
+    library."""
+
+    def __init__(self, ctx, mu, p):
+        self.ctx = ctx
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        p = np.ascontiguousarray(p, dtype=np.float64)
+        h = C.c_void_p()
+        _check(_lib.load().nc_phase_create(ctx.handle, mu.ctypes.data, p.ctypes.data, len(mu), C.byref(h)), ctx.handle)
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.load().nc_phase_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sample(self, u: torch.Tensor) -> torch.Tensor:
+        """u (n,) float32 on the device -> (n, 2): sampled cosine, phase function there."""
+        u = u.contiguous()
+        out = torch.empty((u.numel(), 2), dtype=torch.float32, device=u.device)
+        _check(_lib.load().nc_phase_sample(self.ctx.handle, self.handle, _ptr(u), u.numel(), _ptr(out)),
+               self.ctx.handle)
+        return out
+
+
+# device copies of the tables that Optics.phase_table names, per context
+_PHASE_CACHE = {}
+
+
+def _phase_handle(o: Optics, ctx):
+    tab = getattr(o, "phase_table", None)
+    if tab is None:
+        return None
+    if isinstance(tab, PhaseTable):
+        return tab.handle
+    mu, p = tab
+    key = (id(ctx), id(mu), id(p))
+    hit = _PHASE_CACHE.get(key)
+    if hit is None or hit[1] is not mu or hit[2] is not p:
+        hit = (PhaseTable(ctx, mu, p), mu, p)
+        _PHASE_CACHE[key] = hit
+    return hit[0].handle
+
+
+def _optics(o: Optics, ctx=None):
+    ph = _phase_handle(o, ctx) if ctx is not None else None
+    if getattr(o, "phase_table", None) is not None and ph is None:
+        raise ValueError("a phase table needs the context")
     return _lib.Optics(o.ssa, o.g, o.ground_albedo, o.sun_zenith_deg, o.sun_azimuth_deg, o.sun_irradiance,
-                       o.majorant_scale, o.max_scatter, o.max_segments, o.sun_half_angle_deg)
+                       o.majorant_scale, o.max_scatter, o.max_segments, o.sun_half_angle_deg, ph)
 
 
 def _camera(c: Camera):
@@ -167,7 +224,7 @@ def transmittance(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, ra
     n = rays.shape[0]
     s = torch.zeros(n, dtype=torch.float64, device=rays.device)
     s2 = torch.zeros_like(s)
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     sm = _sampling(sampling)
     _check(_lib.load().nc_transmittance(ctx.handle, grid.handle, _ptr(kc), C.byref(o), _ptr(rays.contiguous()), n,
                                         C.byref(sm), _ptr(s), _ptr(s2), _ptr(counters)), ctx.handle)
@@ -182,7 +239,7 @@ def render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, camera: C
         out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
     if out_sumsq is None:
         out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     c = _camera(camera)
     sm = _sampling(sampling)
     _check(_lib.load().nc_render(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
@@ -200,7 +257,7 @@ def render_guided(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, ca
         out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
     if out_sumsq is None:
         out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     c = _camera(camera)
     sm = _sampling(sampling)
     _check(_lib.load().nc_render_guided(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
@@ -218,7 +275,7 @@ def render_progressive(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optic
     out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
     plan = _lib.Progressive(float(target_rel_err), int(first_spp), int(max_spp), int(block), 0)
     rep = _lib.ProgressReport()
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     c = _camera(camera)
     sm = _sampling(sampling)
     _check(_lib.load().nc_render_progressive(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
@@ -247,7 +304,7 @@ def collect_vertices(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics,
     path_L = torch.empty(max(camera.width * camera.height * sampling.spp, 1), dtype=torch.float32, device=dev)
     out_sum = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
     out_sumsq = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=dev)
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     c = _camera(camera)
     sm = _sampling(sampling)
     _check(_lib.load().nc_collect_vertices(ctx.handle, grid.handle, _ptr(kc), C.byref(o), C.byref(c), C.byref(sm),
@@ -272,7 +329,7 @@ def flux(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px: tuple, 
     nx, ny = px
     tally = torch.zeros((9, ny, nx), dtype=torch.float64, device=kc.device)
     glob = torch.zeros(4, dtype=torch.float64, device=kc.device)
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     sm = _sampling(sampling)
     _check(_lib.load().nc_flux(ctx.handle, grid.handle, _ptr(kc), C.byref(o), float(extinction_scale), nx, ny,
                                int(n_photons), C.byref(sm), _ptr(tally), _ptr(glob), _ptr(counters)), ctx.handle)
@@ -286,7 +343,7 @@ def flux_adjoint(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, px:
     assert tuple(grad.shape) == (ny, nx)
     out = torch.zeros(3, dtype=torch.float64, device=kc.device)
     g64 = grad.to(dtype=torch.float64).contiguous()
-    o = _optics(optics)
+    o = _optics(optics, ctx)
     sm = _sampling(sampling)
     _check(_lib.load().nc_flux_adjoint(ctx.handle, grid.handle, _ptr(kc), C.byref(o), float(extinction_scale), nx, ny,
                                        int(n_photons), C.byref(sm), _ptr(g64), _ptr(out)), ctx.handle)
@@ -331,7 +388,7 @@ def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, samplin
     after the other, and each image's first element."""
     n = len(jobs)
     cams = (_lib.Camera * n)(*[_camera(c) for c, _ in jobs])
-    opts = (_lib.Optics * n)(*[_optics(o) for _, o in jobs])
+    opts = (_lib.Optics * n)(*[_optics(o, ctx) for _, o in jobs])
     offs, total = [], 0
     for c, _ in jobs:
         offs.append(total)
@@ -356,7 +413,7 @@ def autotune_render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, 
     s = torch.zeros((camera.height, camera.width), dtype=torch.float64, device=kc.device)
     s2 = torch.zeros_like(s)
     best = C.c_double()
-    _check(_lib.load().nc_autotune_render(ctx.handle, grid.handle, _ptr(kc), C.byref(_optics(optics)),
+    _check(_lib.load().nc_autotune_render(ctx.handle, grid.handle, _ptr(kc), C.byref(_optics(optics, ctx)),
                                           C.byref(_camera(camera)), C.byref(_sampling(sampling)), _ptr(s), _ptr(s2),
                                           C.byref(best)), ctx.handle)
     return ctx.get_launch(), best.value

@@ -65,6 +65,8 @@ nc_status check_optics(nc_ctx *ctx, const nc_optics *o)
     if (o->max_segments < 1) return fail(ctx, NC_ERR_INVALID_ARG, "max_segments must be >= 1");
     if (!(o->sun_half_angle_deg >= 0.0 && o->sun_half_angle_deg < 90.0))
         return fail(ctx, NC_ERR_RANGE, "sun half angle must be in [0,90) degrees");
+    if (o->phase && o->phase->device != ctx->device)
+        return fail(ctx, NC_ERR_INVALID_ARG, "phase table lives on another device");
     return NC_OK;
 }
 
@@ -89,6 +91,8 @@ nc::OptView make_opt(const nc_optics *o, double k_gas)
     v.ssa = (float)o->ssa;
     v.g = (float)o->g;
     v.hg = nc::make_hg(o->g);
+    v.tab = nc::PhaseView{nullptr, nullptr, nullptr, 0};
+    if (o->phase) v.tab = nc::PhaseView{o->phase->d_mu, o->phase->d_p, o->phase->d_cdf, o->phase->n};
     const double a = o->sun_half_angle_deg * M_PI / 180.0;
     v.cone = a > 0.0 ? 1 : 0;
     v.cone_cos = (float)std::cos(a);
@@ -562,6 +566,77 @@ nc_status nc_guide_sample(nc_ctx *ctx, const nc_guide *guide, const float *d_in,
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "guide sample");
 }
 
+nc_status nc_phase_create(nc_ctx *ctx, const double *h_mu, const double *h_p, int32_t n, nc_phase **out)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!out || !h_mu || !h_p) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (n < 2 || n > (1 << 20)) return fail(ctx, NC_ERR_INVALID_ARG, "the table needs 2 .. 2^20 nodes");
+    if (h_mu[0] != -1.0 || h_mu[n - 1] != 1.0) return fail(ctx, NC_ERR_RANGE, "the cosines must run from -1 to 1");
+    double area = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (!std::isfinite(h_p[i]) || !(h_p[i] >= 0.0)) return fail(ctx, NC_ERR_RANGE, "phase values must be finite, >= 0");
+        if (i > 0 && !(h_mu[i] > h_mu[i - 1])) return fail(ctx, NC_ERR_RANGE, "the cosines must increase");
+        if (i > 0) area += 0.5 * (h_p[i] + h_p[i - 1]) * (h_mu[i] - h_mu[i - 1]);
+    }
+    if (!(area > 0.0) || !std::isfinite(area)) return fail(ctx, NC_ERR_RANGE, "the phase function integrates to 0");
+    // per steradian, and the CDF at the nodes (in double, then float)
+    const double c = 1.0 / (2.0 * M_PI * area);
+    std::vector<float> mu(n), p(n), cdf(n);
+    double acc = 0.0;
+    for (int i = 0; i < n; ++i) {
+        if (i > 0) acc += 2.0 * M_PI * c * 0.5 * (h_p[i] + h_p[i - 1]) * (h_mu[i] - h_mu[i - 1]);
+        mu[i] = (float)h_mu[i];
+        p[i] = (float)(c * h_p[i]);
+        cdf[i] = (float)acc;
+    }
+    cdf[n - 1] = 1.0f;
+    for (int i = 1; i < n; ++i)
+        if (!(mu[i] > mu[i - 1])) return fail(ctx, NC_ERR_RANGE, "cosines closer than float32 resolves");
+    DeviceGuard guard(ctx->device);
+    nc_phase *ph = new (std::nothrow) nc_phase();
+    if (!ph) return fail(ctx, NC_ERR_OOM, "host allocation failed");
+    ph->device = ctx->device;
+    ph->n = n;
+    hipError_t e = hipMalloc(&ph->d_mu, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMalloc(&ph->d_p, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMalloc(&ph->d_cdf, sizeof(float) * n);
+    if (e == hipSuccess) e = hipMemcpyAsync(ph->d_mu, mu.data(), sizeof(float) * n, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(ph->d_p, p.data(), sizeof(float) * n, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(ph->d_cdf, cdf.data(), sizeof(float) * n, hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);   // the host vectors go out of scope
+    if (e != hipSuccess) {
+        nc_phase_destroy(ph);
+        return hip_fail(ctx, e, "phase table");
+    }
+    *out = ph;
+    return NC_OK;
+}
+
+void nc_phase_destroy(nc_phase *ph)
+{
+    if (!ph) return;
+    DeviceGuard guard(ph->device);
+    if (ph->d_mu) (void)hipFree(ph->d_mu);
+    if (ph->d_p) (void)hipFree(ph->d_p);
+    if (ph->d_cdf) (void)hipFree(ph->d_cdf);
+    delete ph;
+}
+
+nc_status nc_phase_sample(nc_ctx *ctx, const nc_phase *ph, const float *d_u, int32_t n, float *d_out)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ph || !d_u || !d_out) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    if (ph->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "phase table lives on another device");
+    if (n < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative count");
+    if (n == 0) return NC_OK;
+    DeviceGuard guard(ctx->device);
+    const hipError_t e =
+        nc::launch_phase_sample(ctx, nc::PhaseView{ph->d_mu, ph->d_p, ph->d_cdf, ph->n}, d_u, n, d_out);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "phase sample");
+}
+
 nc_status nc_gather_rate(nc_ctx *ctx, const float *d_buf, uint64_t n_words, int32_t threads, int32_t loads,
                          float *d_out, double *loads_per_s)
 {
@@ -637,7 +712,7 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
         if ((st = check_optics(ctx, optics + j)) != NC_OK) return st;
         const nc_optics &a = optics[0], &b = optics[j];
         if (a.ssa != b.ssa || a.g != b.g || a.majorant_scale != b.majorant_scale || a.max_scatter != b.max_scatter ||
-            a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg)
+            a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg || a.phase != b.phase)
             return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
         nc::CamView cam;
         if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;
@@ -750,6 +825,7 @@ static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     if ((st = check_optics(ctx, optics)) != NC_OK) return st;
     if (optics->sun_half_angle_deg != 0.0)
         return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the directional sun only");
+    if (optics->phase) return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the HG phase function only");
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (!(scale > 0.0) || !std::isfinite(scale)) return fail(ctx, NC_ERR_RANGE, "extinction_scale must be > 0");
     if (px_nx < 1 || px_ny < 1 || (long long)px_nx * px_ny > (1ll << 28))

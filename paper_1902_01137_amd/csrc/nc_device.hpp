@@ -432,6 +432,58 @@ __device__ inline float hg_sample_mu(const HGc &h, float xi)
     return fminf(1.0f, fmaxf(-1.0f, mu));
 }
 
+// A tabulated phase function: values p at cosines mu (n nodes, -1 .. 1),
+// linear in between, normalised per steradian; cdf[i] = 2 pi times its
+// integral up to mu[i].
+struct PhaseView {
+    const float *mu, *p, *cdf;
+    int n;
+};
+
+// the node interval [mu[i], mu[i+1]] holding x of a sorted array (i in 0..n-2)
+__device__ inline int tab_interval(const float *a, int n, float x)
+{
+    int lo = 0, hi = n - 1;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (a[mid] <= x) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline float tab_phase(const PhaseView &t, float m)
+{
+    const int i = tab_interval(t.mu, t.n, m);
+    const float f = (m - t.mu[i]) * __builtin_amdgcn_rcpf(t.mu[i + 1] - t.mu[i]);
+    return t.p[i] + f * (t.p[i + 1] - t.p[i]);
+}
+
+// Inverse CDF: in the interval holding xi the CDF is 2 pi (p_i x + s x^2 / 2)
+// above cdf[i], x = m - mu[i], s the slope; x is the positive root, in the
+// form without cancellation.
+__device__ inline float tab_sample(const PhaseView &t, float xi)
+{
+    const int i = tab_interval(t.cdf, t.n, xi);
+    const float m0 = t.mu[i], dm = t.mu[i + 1] - m0, p0 = t.p[i];
+    const float s = (t.p[i + 1] - p0) * __builtin_amdgcn_rcpf(dm);
+    const float r = fmaxf(xi - t.cdf[i], 0.0f) * (1.0f / (2.0f * kPi));
+    const float den = p0 + sqrtf(fmaxf(p0 * p0 + 2.0f * s * r, 0.0f));
+    const float x = den > 0.0f ? 2.0f * r * __builtin_amdgcn_rcpf(den) : 0.0f;
+    return fminf(m0 + fminf(x, dm), 1.0f);
+}
+
+// The medium's phase function: the table when there is one, else HG.
+__device__ inline float phase_eval(const HGc &h, const PhaseView &t, float mu)
+{
+    return t.n ? tab_phase(t, mu) : hg_phase(h, mu);
+}
+
+__device__ inline float phase_sample_mu(const HGc &h, const PhaseView &t, float xi)
+{
+    return t.n ? tab_sample(t, xi) : hg_sample_mu(h, xi);
+}
+
 // Orthonormal basis around unit n (Duff et al., "Building an orthonormal
 // basis, revisited", JCGT 2017), then the direction at cosine mu, azimuth
 // 2 pi u about n.

@@ -20,6 +20,12 @@ struct nc_ctx {
     size_t lds_per_cu = 160 * 1024;
 };
 
+struct nc_phase {
+    int device = 0;
+    int n = 0;
+    float *d_mu = nullptr, *d_p = nullptr, *d_cdf = nullptr;   // nodes, values per steradian, CDF at the nodes
+};
+
 struct nc_grid {
     int device = 0;
     int n[3] = {0, 0, 0};
@@ -86,6 +92,7 @@ struct CamView {
 struct OptView {
     float ssa, g, rho, S, mscale;
     HGc hg;              // the phase function's constants
+    PhaseView tab;       // a tabulated phase function (tab.n == 0: HG)
     int cone;            // the sun is a disc (else directional)
     float cone_cos;      // cos of its angular radius
     float cone_gain;     // 2 / (1 + cos alpha): a local estimate's weight for a direction drawn in the cone
@@ -134,6 +141,7 @@ GridView grid_view(const nc_grid *g, const float *d_kc);
 Shape choose_shape(const nc_ctx *ctx, const nc_grid *g, int block_default, size_t reserve = 0, int waves_default = 0);
 
 hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsigned int *d_bad, int *d_zc);
+hipError_t launch_phase_sample(const nc_ctx *ctx, const PhaseView &t, const float *u, int n, float *out);
 hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int level, float *kmin, float *kmax, uint8_t *mg);
 hipError_t launch_leaf_levels(const nc_ctx *ctx, const nc_grid *g, uint8_t *out);
 hipError_t launch_trace_leaves(const nc_ctx *ctx, const nc_grid *g, const float *rays, int n, int maxv, int *leaf,

@@ -807,7 +807,8 @@ __device__ inline float lane_max32(float v)
     return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
-__device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, const HGc &g, int kq)
+__device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, const HGc &g,
+                                              const PhaseView &tab, int kq)
 {
     const float amax = lane_max32(lane_max16(fmaxf(z[0], z[5])));
     const float e0 = __expf(z[0] - amax), e1 = __expf(z[5] - amax);
@@ -839,7 +840,7 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     float v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
     turn_sc(v, t, sp, cp);
     float hgd[3] = {pd[0], pd[1], pd[2]};
-    turn_sc(hgd, hg_sample_mu(g, u1), sp, cp);
+    turn_sc(hgd, phase_sample_mu(g, tab, u1), sp, cp);
     GuidedStep o;
     // the chosen lobe's direction from lane group qs of the column
     const int rel = qs ^ kq;
@@ -863,7 +864,7 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     }
     qp = lane_sum32(lane_sum16(qp));   // the same sum in every lane of the column
     o.q = qp * __builtin_amdgcn_rcpf(psum);
-    o.p = hg_phase(g, pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2]);
+    o.p = phase_eval(g, tab, pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2]);
     o.w = o.p * __builtin_amdgcn_rcpf(c * o.q + (1.0f - c) * o.p);
     return o;
 }
@@ -938,7 +939,7 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
             wave_sync();
             float z[12];
             guide_tile_forward(wl, bl, tin, lane, z);
-            const GuidedStep st = guided_turn_tile(z, tf + col * 8, c, g, kq);
+            const GuidedStep st = guided_turn_tile(z, tf + col * 8, c, g, PhaseView{nullptr, nullptr, nullptr, 0}, kq);
             if (kq == 0 && valid) {
                 float *o = out + (size_t)r * 8;
                 o[0] = st.d[0];
@@ -953,6 +954,23 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
             wave_sync();
         }
     }
+}
+
+// The tabulated phase function's sampler and value on given uniforms.
+__global__ void phase_sample_kernel(PhaseView t, const float *__restrict__ u, int n, float *__restrict__ out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+        const float m = tab_sample(t, u[i]);
+        out[2 * i] = m;
+        out[2 * i + 1] = tab_phase(t, m);
+    }
+}
+
+hipError_t launch_phase_sample(const nc_ctx *ctx, const PhaseView &t, const float *u, int n, float *out)
+{
+    hipLaunchKernelGGL(phase_sample_kernel, dim3(std::max(1, std::min((n + 255) / 256, 4096))), dim3(256), 0,
+                       ctx->stream, t, u, n, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const float *in, const float *u, float c,
@@ -1190,7 +1208,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         gain = A.op.cone_gain;
                     }
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * hg_phase(A.op.hg, mu) * gain;
+                    w_nee = ssa * phase_eval(A.op.hg, A.op.tab, mu) * gain;
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
@@ -1265,7 +1283,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         if (ground_ev)
                             lambert(pd, u1, u2);
                         else
-                            turn(pd, hg_sample_mu(A.op.hg, u1), u2);
+                            turn(pd, phase_sample_mu(A.op.hg, A.op.tab, u1), u2);
                         phase = kPhRay;
                         if (kMode == kCollect && !ground_ev) {
                             // training record: vertex, incoming and outgoing directions, radiance so far
@@ -1346,7 +1364,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 wave_sync();
                 float z[12];
                 guide_tile_forward(wl, bl, tin, lane, z);
-                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.hg, kq);
+                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.hg, A.op.tab, kq);
                 // each owner takes its column's result
                 const int src = owner ? row : lane;
                 const float d0 = __shfl(st.d[0], src), d1 = __shfl(st.d[1], src), d2 = __shfl(st.d[2], src);

@@ -34,7 +34,7 @@ def test_abi_version():
 def test_struct_layouts_match_header():
     assert C.sizeof(_lib.FieldDesc) == 16 + 6 * 8
     assert C.sizeof(_lib.GridParams) == 24
-    assert C.sizeof(_lib.Optics) == 7 * 8 + 8 + 8
+    assert C.sizeof(_lib.Optics) == 7 * 8 + 8 + 8 + 8
     assert C.sizeof(_lib.Camera) == 16 + 12 * 8
     assert C.sizeof(_lib.Sampling) == 40
     assert C.sizeof(_lib.Launch) == 16
