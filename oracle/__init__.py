@@ -43,7 +43,8 @@ class OpticsC(C.Structure):
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double),
                 ("S", C.c_double), ("majorant_scale", C.c_double),
                 ("max_scatter", C.c_int32), ("max_segments", C.c_int32), ("sun_half_angle_deg", C.c_double),
-                ("tab_n", C.c_int32), ("tab_pad_", C.c_int32), ("tab_mu", C.c_void_p), ("tab_p", C.c_void_p)]
+                ("tab_n", C.c_int32), ("tab_pad_", C.c_int32), ("tab_mu", C.c_void_p), ("tab_p", C.c_void_p),
+                ("kd_n", C.c_int32), ("kd_pad_", C.c_int32), ("kd_w", C.c_void_p), ("kd_k", C.c_void_p)]
 
 
 class CameraC(C.Structure):
@@ -122,6 +123,14 @@ def make_optics(op) -> OpticsC:
         o.tab_mu = mu.ctypes.data
         o.tab_p = p.ctypes.data
         o._keep = (mu, p)
+    kd = getattr(op, "kdist", None)
+    if kd is not None:
+        w = np.ascontiguousarray(kd[0], dtype=np.float64)
+        kk = np.ascontiguousarray(kd[1], dtype=np.float64)
+        o.kd_n = len(w)
+        o.kd_w = w.ctypes.data
+        o.kd_k = kk.ctypes.data
+        o._keep_kd = (w, kk)
     return o
 
 

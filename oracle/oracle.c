@@ -113,6 +113,9 @@ typedef struct {
     int32_t tab_n, tab_pad_;     /* tabulated phase function (n >= 2 nodes) instead of HG; 0: HG */
     const double *tab_mu;        /* node cosines, -1 = mu_0 < ... < mu_{n-1} = 1 */
     const double *tab_p;         /* phase function at the nodes (any positive scale) */
+    int32_t kd_n, kd_pad_;       /* k-distribution: n quadrature points (0: the field's k_gas alone) */
+    const double *kd_w;          /* their weights (any positive scale) */
+    const double *kd_k;          /* their gas extinction, km^-1 */
 } orc_optics;
 
 typedef struct {
@@ -1028,6 +1031,22 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
     return L;
 }
 
+/* Spectral integration by a k-distribution (Section 4.1: a quadrature point
+ * of the band is sampled per path): point i with probability w_i / sum w,
+ * whose gas extinction replaces the field's for the whole path.  The
+ * estimate's expectation is sum_i w_i L(k_gas,i) / sum w. */
+static double kd_pick(const orc_optics *op, double u)
+{
+    double tot = 0.0, acc = 0.0;
+    int i;
+    for (i = 0; i < op->kd_n; ++i) tot += op->kd_w[i];
+    for (i = 0; i < op->kd_n - 1; ++i) {
+        acc += op->kd_w[i];
+        if (u * tot < acc) return op->kd_k[i];
+    }
+    return op->kd_k[op->kd_n - 1];
+}
+
 void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam, int32_t spp, uint64_t seed,
                 const int32_t *pixels, int32_t npix, double *sum, double *sumsq, uint64_t *counters)
 {
@@ -1040,7 +1059,9 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
         for (k = 0; k < spp; ++k) {
             orc_rng r;
             double o[3], d[3], L;
+            orc_field fk = *f;      /* the path's medium (its gas extinction under a k-distribution) */
             rng_init(&r, seed, ((uint64_t)p << 24) + (uint64_t)k);
+            if (op->kd_n > 0) fk.k_gas = kd_pick(op, rng_u01(&r));
             {
                 double u1 = rng_u01(&r), u2 = rng_u01(&r);
                 camera_ray(cam, px, py, u1, u2, o, d);
@@ -1048,17 +1069,17 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
             if (cam->type == 2) {
                 double w[3];
                 sun_sample(op, s, &r, w);
-                L = (s[2] > 0.0 && w[2] > 0.0) ? op->S * cone_gain(op) * (w[2] / s[2]) * sun_transmissivity(f, o, w)
+                L = (s[2] > 0.0 && w[2] > 0.0) ? op->S * cone_gain(op) * (w[2] / s[2]) * sun_transmissivity(&fk, o, w)
                                                : 0.0;
                 if (op->max_scatter != 0 && s[2] > 0.0) {
                     double v1 = rng_u01(&r), v2 = rng_u01(&r), rr = sqrt(v1), phi = 2.0 * ORC_PI * v2;
                     d[0] = rr * cos(phi);
                     d[1] = rr * sin(phi);
                     d[2] = sqrt(fmax(0.0, 1.0 - v1));
-                    L += ORC_PI / s[2] * radiance_path(f, op, s, o, d, 0, &r, counters);
+                    L += ORC_PI / s[2] * radiance_path(&fk, op, s, o, d, 0, &r, counters);
                 }
             } else {
-                L = radiance_path(f, op, s, o, d, 1, &r, counters);
+                L = radiance_path(&fk, op, s, o, d, 1, &r, counters);
             }
             if (counters) counters[2]++;
             acc += L;

@@ -70,6 +70,7 @@ class Optics:
     max_segments: int = 1_000_000  # per path, counted when hit
     sun_half_angle_deg: float = 0.0  # angular radius of the solar disc (0: directional sun)
     phase_table: object = None       # (mu, p): tabulated phase function instead of HG (cosines -1..1, values)
+    kdist: object = None             # (w, k_gas): k-distribution, a quadrature point drawn per path (<= 16 points)
 
 
 @dataclass
@@ -300,6 +301,16 @@ def phase_table_tthg(g1=0.92, g2=-0.35, w=0.96, n=181):
     def hg(g):
         return (1 - g * g) / (4 * np.pi * (1 + g * g - 2 * g * mu) ** 1.5)
     return mu, w * hg(g1) + (1 - w) * hg(g2)
+
+
+def kdist_synthetic(n=8, k_min=1e-3, k_max=1.0, seed=5):
+    """A synthetic k-distribution of one band: n quadrature points whose gas
+    extinction spans k_min .. k_max km^-1 geometrically, with Gauss-like
+    weights (more weight on the weak lines).  Returns (w, k_gas)."""
+    k = np.geomspace(k_min, k_max, n)
+    rng = np.random.default_rng(seed)
+    w = np.exp(-0.5 * np.linspace(0.0, 2.5, n) ** 2) * (1.0 + 0.1 * rng.random(n))
+    return w / w.sum(), k
 
 
 def sun_direction(zenith_deg, azimuth_deg):

@@ -423,3 +423,34 @@ def test_tabulated_hg_matches_hg_image(orc):
     assert res["ok"], res
     res = compare(ma, sa, mb, sb)
     assert res["ok"], res
+
+
+# ---------------------------------------------------------------- k-distribution
+
+def test_kdistribution_gas_slab_closed_form(orc):
+    """Gas-only slab over a Lambertian ground, 4 quadrature points: the radiance
+    is the weighted sum of the points' closed forms (sun and view paths both
+    attenuated by each point's gas)."""
+    H, rho, mu, th0 = 0.6, 0.4, 0.8, 30.0
+    desc, k = slab_field([0.0], H)
+    w = np.array([0.1, 0.4, 0.3, 0.2])
+    kg = np.array([0.05, 0.4, 1.3, 3.0])
+    op = Optics(ssa=0.5, g=0.85, ground_albedo=rho, sun_zenith_deg=th0, kdist=(w, kg))
+    cam = _slab_camera(mu, H)
+    spp = 40000
+    s, s2, _ = orc.render(desc, k, 0.0, op, cam, spp, seed=33)
+    mu0 = math.cos(math.radians(th0))
+    per = rho / math.pi * mu0 * np.exp(-kg * H / mu0) * np.exp(-kg * H / mu)
+    exact = float((w * per).sum())
+    mean = s / spp
+    se = np.sqrt(np.maximum(s2 / spp - mean ** 2, 0) / spp)
+    for m, e in zip(mean, se):
+        assert z_ok(m, e, exact), (m, e, exact)
+    # a single point replaces the field's gas extinction (here 0) by its own
+    op1 = Optics(ssa=0.5, g=0.85, ground_albedo=rho, sun_zenith_deg=th0, kdist=(np.array([2.0]), np.array([0.4])))
+    n1 = 20000
+    s1, _, _ = orc.render(desc, k, 0.0, op1, cam, n1, seed=34)
+    c1 = rho / math.pi * mu0 * math.exp(-0.4 * H / mu0)
+    p1 = math.exp(-0.4 * H / mu)
+    for m in s1 / n1:
+        assert z_ok(m, c1 * math.sqrt(p1 * (1 - p1) / n1), c1 * p1)
