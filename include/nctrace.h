@@ -105,7 +105,20 @@ typedef struct {
  * phase: a tabulated phase function (nc_phase_create) that replaces HG(g) in
  * the renderers (local estimates, scattering, the guided step's MIS weight
  * and its phase-function candidate); NULL = HG.  It must live on the
- * context's device; nc_flux and nc_flux_adjoint take HG only. */
+ * context's device; nc_flux and nc_flux_adjoint take HG only.
+ * kdist: a k-distribution (host struct, read at the call): the renderers draw
+ * one quadrature point per path (Section 4.1), whose gas extinction replaces
+ * the grid's k_gas along the whole path; the grid's majorant stays the
+ * grid's, so every point's k_gas must be <= the grid's k_gas (one grid shared
+ * by all points; NC_ERR_RANGE otherwise).  NULL = the grid's k_gas.  Not
+ * taken by nc_transmittance, nc_flux, nc_flux_adjoint (NC_ERR_UNSUPPORTED). */
+#define NC_KDIST_MAX 16
+typedef struct {
+    int32_t n;                     /* 1 .. NC_KDIST_MAX points */
+    int32_t pad_;
+    double w[NC_KDIST_MAX];        /* weights >= 0, normalised by the library */
+    double k_gas[NC_KDIST_MAX];    /* gas extinction per point, km^-1, >= 0 */
+} nc_kdist;
 typedef struct {
     double ssa, g, ground_albedo;
     double sun_zenith_deg, sun_azimuth_deg, sun_irradiance;
@@ -114,6 +127,7 @@ typedef struct {
     int32_t max_segments;
     double sun_half_angle_deg;
     const nc_phase *phase;
+    const nc_kdist *kdist;
 } nc_optics;
 
 /* Camera (Section 4.1, Table 3): type 0 pinhole with vertical field of view

@@ -34,11 +34,19 @@ class GridParams(C.Structure):
     _fields_ = [("tau_tilde", C.c_double), ("k_gas", C.c_double), ("criterion", C.c_int32), ("flat_level", C.c_int32)]
 
 
+KDIST_MAX = 16
+
+
+class KDist(C.Structure):
+    _fields_ = [("n", C.c_int32), ("pad_", C.c_int32), ("w", C.c_double * KDIST_MAX),
+                ("k_gas", C.c_double * KDIST_MAX)]
+
+
 class Optics(C.Structure):
     _fields_ = [("ssa", C.c_double), ("g", C.c_double), ("ground_albedo", C.c_double),
                 ("sun_zenith_deg", C.c_double), ("sun_azimuth_deg", C.c_double), ("sun_irradiance", C.c_double),
                 ("majorant_scale", C.c_double), ("max_scatter", C.c_int32), ("max_segments", C.c_int32),
-                ("sun_half_angle_deg", C.c_double), ("phase", C.c_void_p)]
+                ("sun_half_angle_deg", C.c_double), ("phase", C.c_void_p), ("kdist", C.c_void_p)]
 
 
 class Camera(C.Structure):

@@ -86,8 +86,21 @@ def _optics(o: Optics, ctx=None):
     ph = _phase_handle(o, ctx) if ctx is not None else None
     if getattr(o, "phase_table", None) is not None and ph is None:
         raise ValueError("a phase table needs the context")
-    return _lib.Optics(o.ssa, o.g, o.ground_albedo, o.sun_zenith_deg, o.sun_azimuth_deg, o.sun_irradiance,
-                       o.majorant_scale, o.max_scatter, o.max_segments, o.sun_half_angle_deg, ph)
+    r = _lib.Optics(o.ssa, o.g, o.ground_albedo, o.sun_zenith_deg, o.sun_azimuth_deg, o.sun_irradiance,
+                    o.majorant_scale, o.max_scatter, o.max_segments, o.sun_half_angle_deg, ph, None)
+    kd = getattr(o, "kdist", None)
+    if kd is not None:
+        w, k = (np.asarray(a, dtype=np.float64).ravel() for a in kd)
+        if len(w) != len(k) or not 1 <= len(w) <= _lib.KDIST_MAX:
+            raise ValueError("a k-distribution needs 1 .. %d (weight, k_gas) pairs" % _lib.KDIST_MAX)
+        rec = _lib.KDist()
+        rec.n = len(w)
+        for i in range(len(w)):
+            rec.w[i] = w[i]
+            rec.k_gas[i] = k[i]
+        r._kdist = rec                      # kept alive with the optics record
+        r.kdist = C.addressof(rec)
+    return r
 
 
 def _camera(c: Camera):
@@ -388,7 +401,8 @@ def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, samplin
     after the other, and each image's first element."""
     n = len(jobs)
     cams = (_lib.Camera * n)(*[_camera(c) for c, _ in jobs])
-    opts = (_lib.Optics * n)(*[_optics(o, ctx) for _, o in jobs])
+    recs = [_optics(o, ctx) for _, o in jobs]   # (they keep any k-distribution records alive through the call)
+    opts = (_lib.Optics * n)(*recs)
     offs, total = [], 0
     for c, _ in jobs:
         offs.append(total)

@@ -67,6 +67,27 @@ nc_status check_optics(nc_ctx *ctx, const nc_optics *o)
         return fail(ctx, NC_ERR_RANGE, "sun half angle must be in [0,90) degrees");
     if (o->phase && o->phase->device != ctx->device)
         return fail(ctx, NC_ERR_INVALID_ARG, "phase table lives on another device");
+    if (o->kdist) {
+        const nc_kdist &k = *o->kdist;
+        if (k.n < 1 || k.n > NC_KDIST_MAX) return fail(ctx, NC_ERR_INVALID_ARG, "k-distribution needs 1 .. 16 points");
+        double tot = 0.0;
+        for (int i = 0; i < k.n; ++i) {
+            if (!std::isfinite(k.w[i]) || !(k.w[i] >= 0.0) || !std::isfinite(k.k_gas[i]) || !(k.k_gas[i] >= 0.0))
+                return fail(ctx, NC_ERR_RANGE, "k-distribution weights and extinctions must be finite, >= 0");
+            tot += k.w[i];
+        }
+        if (!(tot > 0.0)) return fail(ctx, NC_ERR_RANGE, "k-distribution weights sum to 0");
+    }
+    return NC_OK;
+}
+
+// every k-distribution point within the shared grid's majorant
+nc_status check_kdist_grid(nc_ctx *ctx, const nc_optics *o, const nc_grid *g)
+{
+    if (!o->kdist) return NC_OK;
+    for (int i = 0; i < o->kdist->n; ++i)
+        if (o->kdist->k_gas[i] > g->params.k_gas)
+            return fail(ctx, NC_ERR_RANGE, "a k-distribution point's k_gas exceeds the grid's (its majorant)");
     return NC_OK;
 }
 
@@ -93,6 +114,18 @@ nc::OptView make_opt(const nc_optics *o, double k_gas)
     v.hg = nc::make_hg(o->g);
     v.tab = nc::PhaseView{nullptr, nullptr, nullptr, 0};
     if (o->phase) v.tab = nc::PhaseView{o->phase->d_mu, o->phase->d_p, o->phase->d_cdf, o->phase->n};
+    v.kd_n = 0;
+    for (int i = 0; i < NC_KDIST_MAX; ++i) v.kd_cdf[i] = v.kd_k[i] = 0.0f;
+    if (o->kdist) {
+        double tot = 0.0, acc = 0.0;
+        for (int i = 0; i < o->kdist->n; ++i) tot += o->kdist->w[i];
+        v.kd_n = o->kdist->n;
+        for (int i = 0; i < o->kdist->n; ++i) {
+            acc += o->kdist->w[i];
+            v.kd_cdf[i] = (float)(acc / tot);
+            v.kd_k[i] = (float)o->kdist->k_gas[i];
+        }
+    }
     const double a = o->sun_half_angle_deg * M_PI / 180.0;
     v.cone = a > 0.0 ? 1 : 0;
     v.cone_cos = (float)std::cos(a);
@@ -450,6 +483,7 @@ nc_status nc_transmittance(nc_ctx *ctx, const nc_grid *g, const float *d_kc, con
     nc_status st = check_grid(ctx, g);
     if (st != NC_OK) return st;
     if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    if (optics->kdist) return fail(ctx, NC_ERR_UNSUPPORTED, "the transmittance kernel takes the grid's gas extinction");
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (n < 0 || s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative size");
     if (n == 0 || s->spp == 0) return NC_OK;
@@ -469,6 +503,7 @@ static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, co
     nc_status st = check_grid(ctx, g);
     if (st != NC_OK) return st;
     if ((st = check_optics(ctx, optics)) != NC_OK) return st;
+    if ((st = check_kdist_grid(ctx, optics, g)) != NC_OK) return st;
     nc::CamView cam;
     if ((st = make_cam(ctx, camera, cam)) != NC_OK) return st;
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
@@ -710,9 +745,11 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
     std::vector<nc::JobView> jobs((size_t)n_jobs);
     for (int j = 0; j < n_jobs; ++j) {
         if ((st = check_optics(ctx, optics + j)) != NC_OK) return st;
+        if ((st = check_kdist_grid(ctx, optics + j, g)) != NC_OK) return st;
         const nc_optics &a = optics[0], &b = optics[j];
         if (a.ssa != b.ssa || a.g != b.g || a.majorant_scale != b.majorant_scale || a.max_scatter != b.max_scatter ||
-            a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg || a.phase != b.phase)
+            a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg || a.phase != b.phase ||
+            a.kdist != b.kdist)
             return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
         nc::CamView cam;
         if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;
@@ -826,6 +863,7 @@ static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     if (optics->sun_half_angle_deg != 0.0)
         return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the directional sun only");
     if (optics->phase) return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the HG phase function only");
+    if (optics->kdist) return fail(ctx, NC_ERR_UNSUPPORTED, "forward photons take the grid's gas extinction only");
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (!(scale > 0.0) || !std::isfinite(scale)) return fail(ctx, NC_ERR_RANGE, "extinction_scale must be > 0");
     if (px_nx < 1 || px_ny < 1 || (long long)px_nx * px_ny > (1ll << 28))

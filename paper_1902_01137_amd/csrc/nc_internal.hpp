@@ -93,6 +93,9 @@ struct OptView {
     float ssa, g, rho, S, mscale;
     HGc hg;              // the phase function's constants
     PhaseView tab;       // a tabulated phase function (tab.n == 0: HG)
+    int kd_n;            // k-distribution points (0: the grid's gas extinction for every path)
+    float kd_cdf[NC_KDIST_MAX];   // cumulative normalised weights
+    float kd_k[NC_KDIST_MAX];     // gas extinction per point
     int cone;            // the sun is a disc (else directional)
     float cone_cos;      // cos of its angular radius
     float cone_gain;     // 2 / (1 + cos alpha): a local estimate's weight for a direction drawn in the cone

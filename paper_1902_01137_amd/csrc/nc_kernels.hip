@@ -982,7 +982,7 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
     return hipGetLastError();
 }
 
-template <int kWavesPerEU, int kMode, int kSun>
+template <int kWavesPerEU, int kMode, int kSun, bool kKd>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
     extern __shared__ __align__(16) float2 s_nodes[];
@@ -1028,6 +1028,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     VoxelCache vc{g.L, -1, 0, 0, 0.0f, 0.0f};
     float beta = 1.0f;                   // path weight (guided mode)
     float kev = 0.0f;                    // extinction at the current event (guided and collection modes)
+    float kg = g.k_gas;                  // the path's gas extinction: a k-distribution point (kKd)
+    // (without a k-distribution every path has the grid's: no register for it)
+    auto path_kg = [&]() { return kKd ? kg : g.k_gas; };
     unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
     int chunk_left = 0;
     bool queue_done = false;
@@ -1072,7 +1075,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             if (active) {
                 const bool resid = shadow && kSun == 2;
                 if (resid) {
-                    t_sun *= __expf(-(g.kscale * r.kmin + g.k_gas) * (r.texit - r.t));
+                    t_sun *= __expf(-(g.kscale * r.kmin + path_kg()) * (r.texit - r.t));
                     if (t_sun < kSunRoulette) {     // Russian roulette on small estimates
                         rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
                                  A.key1);
@@ -1088,7 +1091,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     phase = kPhEvent;
                 } else {
                     leaf = true;
-                    if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + g.k_gas), 0.0f);
+                    if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
                     phase = voxel_phase(r, tau);
                     if (++segs >= A.op.max_segments) {
                         trunc = true;
@@ -1111,11 +1114,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 const float t0 = r.t;
                 r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
-                const float kmin = g.kscale * r.kmin + g.k_gas;
+                const float kmin = g.kscale * r.kmin + path_kg();
                 const float kctrl = kSun == 2 ? kmin : 0.0f;
                 float kx = kmin;                // a level-0 voxel is one cell: k is known
                 if (r.lev != 0) {
-                    kx = g.kscale * g.kc[collision_cell(g, r, r.t)] + g.k_gas;
+                    kx = g.kscale * g.kc[collision_cell(g, r, r.t)] + path_kg();
                     ++reads;
                     gathered = true;
                 }
@@ -1143,7 +1146,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 r.t = fminf(r.t + tau * __builtin_amdgcn_rcpf(r.khat), r.texit);
                 const float thr = rng.take() * r.khat;
-                if (shadow && thr < g.kscale * r.kmin + g.k_gas) {
+                if (shadow && thr < g.kscale * r.kmin + path_kg()) {
                     real = true;                // below the voxel's minimum: real without reading k
                 } else {
                     if (r.lev == 0) {
@@ -1153,7 +1156,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         ++reads;
                         gathered = true;
                     }
-                    real = thr < g.kscale * kc_hit + g.k_gas;
+                    real = thr < g.kscale * kc_hit + path_kg();
                 }
                 if (real) {
                     res = kReal;
@@ -1192,8 +1195,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         r.o[a] = r.o[a] + r.t * r.d[a];
                     }
                     const float kd = g.kscale * kc_hit;
-                    kev = kd + g.k_gas;
-                    const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + g.k_gas);
+                    kev = kd + path_kg();
+                    const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + path_kg());
                     float gain = 1.0f;
                     if (A.op.cone) {
                         // solar disc: the local estimate's direction drawn in its cone
@@ -1314,7 +1317,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 hit = start_ray_cached_r(g, ns, r, o, rd, vc, A.op.mscale, reads);
                 if (kSun != 0 && shadow) {
                     t_sun = 1.0f;
-                    if (kSun == 2) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + g.k_gas), 0.0f);
+                    if (kSun == 2) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
                 }
                 rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
                 tau = rng.take_exp1();
@@ -1470,7 +1473,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const volatile JobView &J = R.jobs[job];
                 const int W = J.cam.W;
                 const int py = pix / W, px = pix - py * W;
-                rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+                rng.need(kKd ? 3 : 2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
+                         A.key1);
+                if (kKd) {
+                    // spectral integration: the path's quadrature point (Section 4.1)
+                    // (unrolled over the table, so that its entries stay scalar kernel arguments)
+                    const float uk = rng.take();
+                    kg = A.op.kd_k[0];
+#pragma unroll
+                    for (int q = 1; q < NC_KDIST_MAX; ++q)
+                        if (q < A.op.kd_n && uk >= A.op.kd_cdf[q - 1]) kg = A.op.kd_k[q];
+                }
                 const float u1 = rng.take(), u2 = rng.take();
                 float o[3];
                 camera_ray_v(J.cam, px, py, u1, u2, o, pd);
@@ -1498,6 +1511,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     if (A.op.cone) {
                         // the direct beam along a direction drawn in the disc's cone
                         const float s0[3] = {sun[0], sun[1], sun[2]};
+                        rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
+                                 A.key1);
                         const float c1 = rng.take(), c2 = rng.take();
                         float w[3];
                         cone_dir(s0, A.op.cone_cos, c1, c2, w);
@@ -1564,8 +1579,8 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
     const size_t guide_bytes =
         mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
-    // the guided kernel holds 3 waves per SIMD (12 per CU) by its register count
-    Shape sh = choose_shape(ctx, g, 256, guide_bytes, mode == kGuided ? 12 : 0);
+    // the guided kernel and the k-distribution kernels hold 3 waves per SIMD (12 per CU) by their register counts
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (mode == kGuided || op.kd_n > 0) ? 12 : 0);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -1636,23 +1651,37 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     // kernel variant: mode, sun-ray estimator, register budget (waves per SIMD)
     const int est = s.flags & NC_SUN_ESTIMATOR_MASK;
     const void *fn = nullptr;
-    if (mode == kGuided) {
-        fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0>
-             : est == 1 ? (const void *)render_kernel<3, kGuided, 1>
-                        : (const void *)render_kernel<3, kGuided, 2>;
+    if (op.kd_n > 0) {
+        // a k-distribution: the kernels that carry a per-path gas extinction
+        if (mode == kGuided)
+            fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0, true>
+                 : est == 1 ? (const void *)render_kernel<3, kGuided, 1, true>
+                            : (const void *)render_kernel<3, kGuided, 2, true>;
+        else if (mode == kCollect)
+            fn = est == 0 ? (const void *)render_kernel<3, kCollect, 0, true>
+                 : est == 1 ? (const void *)render_kernel<3, kCollect, 1, true>
+                            : (const void *)render_kernel<3, kCollect, 2, true>;
+        else
+            fn = est == 0 ? (const void *)render_kernel<3, kPlain, 0, true>
+                 : est == 1 ? (const void *)render_kernel<3, kPlain, 1, true>
+                            : (const void *)render_kernel<3, kPlain, 2, true>;
+    } else if (mode == kGuided) {
+        fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0, false>
+             : est == 1 ? (const void *)render_kernel<3, kGuided, 1, false>
+                        : (const void *)render_kernel<3, kGuided, 2, false>;
     } else if (mode == kCollect) {
-        fn = est == 0 ? (const void *)render_kernel<4, kCollect, 0>
-             : est == 1 ? (const void *)render_kernel<4, kCollect, 1>
-                        : (const void *)render_kernel<4, kCollect, 2>;
+        fn = est == 0 ? (const void *)render_kernel<4, kCollect, 0, false>
+             : est == 1 ? (const void *)render_kernel<4, kCollect, 1, false>
+                        : (const void *)render_kernel<4, kCollect, 2, false>;
     } else if (est == 0) {
-        fn = wpe == 3   ? (const void *)render_kernel<3, kPlain, 0>
-             : wpe == 4 ? (const void *)render_kernel<4, kPlain, 0>
-             : wpe == 5 ? (const void *)render_kernel<5, kPlain, 0>
-                        : (const void *)render_kernel<6, kPlain, 0>;
+        fn = wpe == 3   ? (const void *)render_kernel<3, kPlain, 0, false>
+             : wpe == 4 ? (const void *)render_kernel<4, kPlain, 0, false>
+             : wpe == 5 ? (const void *)render_kernel<5, kPlain, 0, false>
+                        : (const void *)render_kernel<6, kPlain, 0, false>;
     } else if (est == 1) {
-        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 1> : (const void *)render_kernel<4, kPlain, 1>;
+        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 1, false> : (const void *)render_kernel<4, kPlain, 1, false>;
     } else {
-        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 2> : (const void *)render_kernel<4, kPlain, 2>;
+        fn = wpe == 3 ? (const void *)render_kernel<3, kPlain, 2, false> : (const void *)render_kernel<4, kPlain, 2, false>;
     }
     int resident = 0;
     const size_t lds = node_bytes + guide_bytes;

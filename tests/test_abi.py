@@ -34,7 +34,8 @@ def test_abi_version():
 def test_struct_layouts_match_header():
     assert C.sizeof(_lib.FieldDesc) == 16 + 6 * 8
     assert C.sizeof(_lib.GridParams) == 24
-    assert C.sizeof(_lib.Optics) == 7 * 8 + 8 + 8 + 8
+    assert C.sizeof(_lib.Optics) == 7 * 8 + 8 + 8 + 8 + 8
+    assert C.sizeof(_lib.KDist) == 8 + 2 * 16 * 8
     assert C.sizeof(_lib.Camera) == 16 + 12 * 8
     assert C.sizeof(_lib.Sampling) == 40
     assert C.sizeof(_lib.Launch) == 16
@@ -45,7 +46,7 @@ def test_struct_layouts_match_header():
 # ctypes mirror of each header struct
 _STRUCTS = {
     "nc_field_desc": "FieldDesc", "nc_grid_params": "GridParams", "nc_optics": "Optics", "nc_camera": "Camera",
-    "nc_sampling": "Sampling", "nc_launch": "Launch", "nc_progressive": "Progressive",
+    "nc_sampling": "Sampling", "nc_launch": "Launch", "nc_progressive": "Progressive", "nc_kdist": "KDist",
     "nc_progress_report": "ProgressReport",
 }
 

@@ -452,3 +452,58 @@ def test_disc_sun_argument_checks():
     with pytest.raises(_lib.NcError) as e:
         api.render(c, g, kd, op, sensor, Sampling(seed=1, spp=1))
     assert e.value.status == _lib.NC_ERR_RANGE
+
+
+# ---------------------------------------------------------------- k-distribution (spectral quadrature)
+
+def test_kdistribution_gas_slab_closed_form():
+    """Gas-only slab over a Lambertian ground, 4 quadrature points drawn per
+    path, one grid shared by all (built with the largest point's k_gas)."""
+    H, rho, mu, th0 = 0.6, 0.4, 0.8, 30.0
+    desc, k = inputs.slab_field([0.0], H)
+    w = np.array([0.1, 0.4, 0.3, 0.2])
+    kg = np.array([0.05, 0.4, 1.3, 3.0])
+    op = Optics(ssa=0.5, g=0.85, ground_albedo=rho, sun_zenith_deg=th0, kdist=(w, kg))
+    spp = 100000
+    s, s2 = _render(desc, k, 3.0, 1.0, op, _slab_camera(mu, H), spp, seed=93)
+    mu0 = math.cos(math.radians(th0))
+    exact = float((w * rho / math.pi * mu0 * np.exp(-kg * H / mu0) * np.exp(-kg * H / mu)).sum())
+    m, se = mean_se(s, s2, spp)
+    assert np.all(np.abs(m - exact) < 4.5 * se), (m, exact, se)
+
+
+def test_small_cloud_kdistribution_vs_oracle():
+    """The small cloud with an 8-point synthetic k-distribution of the gas
+    (0.001 .. 1 km^-1): GPU image (shared grid at the largest k_gas) against
+    the oracle's."""
+    sc = inputs.scene_small()
+    kd = inputs.kdist_synthetic()
+    op = Optics(**{**vars(sc.optics), "kdist": kd})
+    spp_g, spp_o = 256, 128
+    s, s2 = _render(sc.desc, sc.kc, float(kd[1].max()), sc.grid.tau_tilde, op, sc.camera, spp_g, seed=1021)
+    os_, os2, _ = oracle.render(sc.desc, sc.kc, 0.0, op, sc.camera, spp_o, inputs.SEED_ORACLE_BASE + 21)
+    gm, gse = mean_se(s, s2, spp_g)
+    om, ose = mean_se(os_, os2, spp_o)
+    res = compare(*block(gm, gse, (64, 64)), *block(om, ose, (64, 64)))
+    assert res["ok"], res
+    res_px = compare(gm, gse, om, ose)
+    assert res_px["ok"], res_px
+
+
+def test_kdistribution_argument_checks():
+    sc = inputs.scene_small()
+    c = ctx()
+    kd_ = device_field(sc.kc)
+    g = api.build_grid(c, kd_, sc.desc, GridParams(1.0, 0.5, 0))
+    ok = (np.array([0.5, 0.5]), np.array([0.1, 0.5]))
+    api.render(c, g, kd_, Optics(**{**vars(sc.optics), "kdist": ok}), sc.camera, Sampling(seed=1, spp=1))
+    for bad, status in (((np.array([0.5, 0.5]), np.array([0.1, 0.6])), _lib.NC_ERR_RANGE),    # above the grid's k_gas
+                        ((np.array([0.0, 0.0]), np.array([0.1, 0.2])), _lib.NC_ERR_RANGE),
+                        ((np.array([1.0, -1.0]), np.array([0.1, 0.2])), _lib.NC_ERR_RANGE)):
+        with pytest.raises(_lib.NcError) as e:
+            api.render(c, g, kd_, Optics(**{**vars(sc.optics), "kdist": bad}), sc.camera, Sampling(seed=1, spp=1))
+        assert e.value.status == status
+    op = Optics(**{**vars(sc.optics), "kdist": ok})
+    with pytest.raises(_lib.NcError) as e:
+        api.flux(c, g, kd_, op, (4, 4), 1000, Sampling(seed=1, spp=1))
+    assert e.value.status == _lib.NC_ERR_UNSUPPORTED
