@@ -80,13 +80,14 @@ def parse():
     p.add_argument("--no-tau-sweep", action="store_true", help="skip the merge-threshold sweep")
     p.add_argument("--autotune", action="store_true", help="autotune the launch knobs before timing")
     p.add_argument("--no-flux", action="store_true", help="skip the forward-photon / adjoint timing (cylinder cumulus)")
+    p.add_argument("--no-kdist", action="store_true", help="skip the k-distribution comparison (shared grid vs per point)")
     p.add_argument("--no-guide-kernels", action="store_true", help="skip the network training / inference timing")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
         a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
         a.no_progressive = a.no_ceiling = a.no_estimators = a.no_tau_sweep = True
-        a.no_flux = a.no_guide_kernels = True
+        a.no_flux = a.no_guide_kernels = a.no_kdist = True
     return a
 
 
@@ -234,6 +235,9 @@ def main():
     if not args.no_estimators:
         out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
         note("sun_estimators")
+    if args.workload == "cumulus" and not args.no_kdist:
+        out["kdist"] = kdist_run(ctx, sc, kc)
+        note("kdist")
     if not args.no_flux:
         out["flux"] = flux_run(ctx)
         note("flux")
@@ -320,6 +324,51 @@ def estimator_run(ctx, sc, kc, spp, build_ms):
         paths = cam.width * cam.height * spp
         res[name] = {"render_ms": ms, "paths_per_s": paths / (ms / 1e3), "rel_std_err": eps,
                      "time_to_1pct_s": (build_ms + ms) / 1e3 * (eps / 0.01) ** 2}
+    return res
+
+
+def kdist_run(ctx, sc, kc):
+    """Spectral integration over a synthetic 8-point k-distribution of the gas
+    (0.001 .. 1 km^-1) on the workload's view at 512^2, 32 samples per pixel:
+    one launch that draws a point per path under one grid built for the
+    largest k_gas, against one grid and one launch per point (w_i x spp
+    samples each, combined with the weights)."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    w, kgs = inputs.kdist_synthetic()
+    cam = inputs.Camera(**{**vars(sc.camera), "width": 512, "height": 512})
+    spp = 32
+    op = inputs.Optics(**{**vars(sc.optics), "kdist": (w, kgs)})
+    res = {"points": len(w), "k_gas": [float(x) for x in kgs], "weights": [float(x) for x in w]}
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = api.build_grid(ctx, kc, sc.desc, inputs.GridParams(sc.grid.tau_tilde, float(kgs.max()), sc.grid.criterion))
+    s, s2 = api.render(ctx, g, kc, op, cam, inputs.Sampling(seed=sc.sampling.seed + 91, spp=spp, flags=FLAGS))
+    torch.cuda.synchronize()
+    t_shared = time.perf_counter() - t0
+    eps = rel_err(s, s2, spp)
+    res["shared_grid"] = {"s": t_shared, "rel_std_err": eps, "time_to_1pct_s": t_shared * (eps / 0.01) ** 2}
+    del g
+    mean = torch.zeros((cam.height, cam.width), dtype=torch.float64, device="cuda")
+    var = torch.zeros_like(mean)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, (wi, ki) in enumerate(zip(w, kgs)):
+        n_i = max(2, int(round(wi * spp)))
+        # without a k-distribution a path takes its grid's gas extinction: this point's
+        gi = api.build_grid(ctx, kc, sc.desc, inputs.GridParams(sc.grid.tau_tilde, float(ki), sc.grid.criterion))
+        si, s2i = api.render(ctx, gi, kc, sc.optics, cam,
+                             inputs.Sampling(seed=sc.sampling.seed + 92 + i, spp=n_i, flags=FLAGS))
+        m_i = si / n_i
+        v_i = torch.clamp(s2i / n_i - m_i * m_i, min=0.0) * n_i / (n_i - 1) / n_i
+        mean += wi * m_i
+        var += wi * wi * v_i
+        del gi
+    torch.cuda.synchronize()
+    t_per = time.perf_counter() - t0
+    eps_p = float(torch.sqrt(var.mean()) / mean.mean())
+    res["grid_per_point"] = {"s": t_per, "rel_std_err": eps_p, "time_to_1pct_s": t_per * (eps_p / 0.01) ** 2}
     return res
 
 
