@@ -807,6 +807,7 @@ __device__ inline float lane_max32(float v)
     return fmaxf(__uint_as_float(r[0]), __uint_as_float(r[1]));
 }
 
+template <bool kTab>
 __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *slot, float c, const HGc &g,
                                               const PhaseView &tab, int kq)
 {
@@ -840,7 +841,7 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     float v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
     turn_sc(v, t, sp, cp);
     float hgd[3] = {pd[0], pd[1], pd[2]};
-    turn_sc(hgd, phase_sample_mu(g, tab, u1), sp, cp);
+    turn_sc(hgd, kTab ? phase_sample_mu(g, tab, u1) : hg_sample_mu(g, u1), sp, cp);
     GuidedStep o;
     // the chosen lobe's direction from lane group qs of the column
     const int rel = qs ^ kq;
@@ -864,7 +865,8 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     }
     qp = lane_sum32(lane_sum16(qp));   // the same sum in every lane of the column
     o.q = qp * __builtin_amdgcn_rcpf(psum);
-    o.p = phase_eval(g, tab, pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2]);
+    const float mu_o = pd[0] * o.d[0] + pd[1] * o.d[1] + pd[2] * o.d[2];
+    o.p = kTab ? phase_eval(g, tab, mu_o) : hg_phase(g, mu_o);
     o.w = o.p * __builtin_amdgcn_rcpf(c * o.q + (1.0f - c) * o.p);
     return o;
 }
@@ -939,7 +941,7 @@ __global__ __launch_bounds__(64) void guide_sample_kernel(GuideWeights W, const 
             wave_sync();
             float z[12];
             guide_tile_forward(wl, bl, tin, lane, z);
-            const GuidedStep st = guided_turn_tile(z, tf + col * 8, c, g, PhaseView{nullptr, nullptr, nullptr, 0}, kq);
+            const GuidedStep st = guided_turn_tile<false>(z, tf + col * 8, c, g, PhaseView{nullptr, nullptr, nullptr, 0}, kq);
             if (kq == 0 && valid) {
                 float *o = out + (size_t)r * 8;
                 o[0] = st.d[0];
@@ -982,7 +984,7 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
     return hipGetLastError();
 }
 
-template <int kWavesPerEU, int kMode, int kSun, bool kKd>
+template <int kWavesPerEU, int kMode, int kSun, bool kExt>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
     extern __shared__ __align__(16) float2 s_nodes[];
@@ -1028,9 +1030,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     VoxelCache vc{g.L, -1, 0, 0, 0.0f, 0.0f};
     float beta = 1.0f;                   // path weight (guided mode)
     float kev = 0.0f;                    // extinction at the current event (guided and collection modes)
-    float kg = g.k_gas;                  // the path's gas extinction: a k-distribution point (kKd)
-    // (without a k-distribution every path has the grid's: no register for it)
-    auto path_kg = [&]() { return kKd ? kg : g.k_gas; };
+    float kg = g.k_gas;                  // the path's gas extinction: a k-distribution point (kExt)
+    // kExt: the extended medium (a k-distribution, a tabulated phase function,
+    // the solar disc); the other variants have none of them in their code, so
+    // neither a register for a per-path gas extinction nor the table's search
+    auto path_kg = [&]() { return kExt ? kg : g.k_gas; };
     unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
     int chunk_left = 0;
     bool queue_done = false;
@@ -1198,7 +1202,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     kev = kd + path_kg();
                     const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + path_kg());
                     float gain = 1.0f;
-                    if (A.op.cone) {
+                    if (kExt && A.op.cone) {
                         // solar disc: the local estimate's direction drawn in its cone
                         const volatile JobView &J = R.jobs[job];
                         const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
@@ -1211,7 +1215,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         gain = A.op.cone_gain;
                     }
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * phase_eval(A.op.hg, A.op.tab, mu) * gain;
+                    w_nee = ssa * (kExt ? phase_eval(A.op.hg, A.op.tab, mu) : hg_phase(A.op.hg, mu)) * gain;
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
@@ -1233,7 +1237,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     r.o[2] = 0.0f;
                     const float rho = R.jobs[job].rho;
                     float gain = 1.0f;
-                    if (A.op.cone) {
+                    if (kExt && A.op.cone) {
                         const volatile JobView &J = R.jobs[job];
                         const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
                         const float c1 = rng.take(), c2 = rng.take();
@@ -1260,7 +1264,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 } else {
                     // escaped upward: a camera ray that met nothing may look into the solar disc
-                    if (A.op.cone && order == 0 && !ground_ev) {
+                    if (kExt && A.op.cone && order == 0 && !ground_ev) {
                         const volatile JobView &J = R.jobs[job];
                         if (r.d[0] * J.sun[0] + r.d[1] * J.sun[1] + r.d[2] * J.sun[2] >= A.op.cone_cos)
                             Lp += beta * A.op.cone_L;
@@ -1270,7 +1274,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 if (cont) {
                     shadow = false;
                     // (the disc's draw may have left too few numbers for the scattering)
-                    if (A.op.cone)
+                    if (kExt && A.op.cone)
                         rng.need(kMode == kGuided ? 4 : 3, (uint32_t)pix, A.sample_base + (uint32_t)s,
                                  A.stream_base + (uint32_t)job, A.key0, A.key1);
                     if (A.op.max_scatter >= 0 && order >= A.op.max_scatter) {
@@ -1286,7 +1290,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         if (ground_ev)
                             lambert(pd, u1, u2);
                         else
-                            turn(pd, phase_sample_mu(A.op.hg, A.op.tab, u1), u2);
+                            turn(pd, kExt ? phase_sample_mu(A.op.hg, A.op.tab, u1) : hg_sample_mu(A.op.hg, u1), u2);
                         phase = kPhRay;
                         if (kMode == kCollect && !ground_ev) {
                             // training record: vertex, incoming and outgoing directions, radiance so far
@@ -1367,7 +1371,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 wave_sync();
                 float z[12];
                 guide_tile_forward(wl, bl, tin, lane, z);
-                const GuidedStep st = guided_turn_tile(z, tf + col * 8, A.guide_frac, A.op.hg, A.op.tab, kq);
+                const GuidedStep st = guided_turn_tile<kExt>(z, tf + col * 8, A.guide_frac, A.op.hg, A.op.tab, kq);
                 // each owner takes its column's result
                 const int src = owner ? row : lane;
                 const float d0 = __shfl(st.d[0], src), d1 = __shfl(st.d[1], src), d2 = __shfl(st.d[2], src);
@@ -1473,9 +1477,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const volatile JobView &J = R.jobs[job];
                 const int W = J.cam.W;
                 const int py = pix / W, px = pix - py * W;
-                rng.need(kKd ? 3 : 2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
+                rng.need(kExt && A.op.kd_n ? 3 : 2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
                          A.key1);
-                if (kKd) {
+                if (kExt && A.op.kd_n) {
                     // spectral integration: the path's quadrature point (Section 4.1)
                     // (unrolled over the table, so that its entries stay scalar kernel arguments)
                     const float uk = rng.take();
@@ -1508,7 +1512,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     // happens, a cosine-distributed upward path of weight pi / mu_sun
                     beta = kPi / sun[2];
                     float gain = 1.0f;
-                    if (A.op.cone) {
+                    if (kExt && A.op.cone) {
                         // the direct beam along a direction drawn in the disc's cone
                         const float s0[3] = {sun[0], sun[1], sun[2]};
                         rng.need(2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
@@ -1579,8 +1583,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
     const size_t guide_bytes =
         mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
-    // the guided kernel and the k-distribution kernels hold 3 waves per SIMD (12 per CU) by their register counts
-    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (mode == kGuided || op.kd_n > 0) ? 12 : 0);
+    // the guided kernel and the extended-medium kernels hold 3 waves per SIMD (12 per CU) by their register counts
+    const bool ext = op.kd_n > 0 || op.tab.n > 0 || op.cone;
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (mode == kGuided || ext) ? 12 : 0);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -1651,8 +1656,8 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     // kernel variant: mode, sun-ray estimator, register budget (waves per SIMD)
     const int est = s.flags & NC_SUN_ESTIMATOR_MASK;
     const void *fn = nullptr;
-    if (op.kd_n > 0) {
-        // a k-distribution: the kernels that carry a per-path gas extinction
+    if (op.kd_n > 0 || op.tab.n > 0 || op.cone) {
+        // the extended medium (k-distribution, phase table, solar disc): its own kernel variants
         if (mode == kGuided)
             fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0, true>
                  : est == 1 ? (const void *)render_kernel<3, kGuided, 1, true>
