@@ -462,8 +462,9 @@ nc_status nc_philox4x32_10(nc_ctx *ctx, const uint32_t *d_ctr, const uint32_t *d
  * under optics[j] into d_sum/d_sumsq starting at element out_offsets[j]
  * (host array; image j occupies cams[j].height * cams[j].width elements).
  * The medium's parameters (ssa, g, majorant_scale, max_scatter,
- * max_segments) must be equal across jobs; the sun (zenith, azimuth,
- * irradiance) and the ground albedo may differ.  Queue items of all jobs are
+ * max_segments, the sun's half angle, the phase table, the k-distribution's
+ * points) must be equal across jobs; the sun's direction and irradiance and
+ * the ground albedo may differ.  Queue items of all jobs are
  * drawn from one work queue, so views of uneven size balance across the
  * GPU.  Random streams: job j uses stream sampling->stream + j. */
 nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs, const nc_camera *cams,

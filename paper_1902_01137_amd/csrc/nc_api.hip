@@ -81,6 +81,16 @@ nc_status check_optics(nc_ctx *ctx, const nc_optics *o)
     return NC_OK;
 }
 
+// two k-distributions with the same points (or both absent)
+bool same_kdist(const nc_kdist *a, const nc_kdist *b)
+{
+    if (!a || !b) return a == b;
+    if (a->n != b->n) return false;
+    for (int i = 0; i < a->n; ++i)
+        if (a->w[i] != b->w[i] || a->k_gas[i] != b->k_gas[i]) return false;
+    return true;
+}
+
 // every k-distribution point within the shared grid's majorant
 nc_status check_kdist_grid(nc_ctx *ctx, const nc_optics *o, const nc_grid *g)
 {
@@ -749,7 +759,7 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
         const nc_optics &a = optics[0], &b = optics[j];
         if (a.ssa != b.ssa || a.g != b.g || a.majorant_scale != b.majorant_scale || a.max_scatter != b.max_scatter ||
             a.max_segments != b.max_segments || a.sun_half_angle_deg != b.sun_half_angle_deg || a.phase != b.phase ||
-            a.kdist != b.kdist)
+            !same_kdist(a.kdist, b.kdist))
             return fail(ctx, NC_ERR_INVALID_ARG, "the medium's optics must be the same for every job");
         nc::CamView cam;
         if ((st = make_cam(ctx, cams + j, cam)) != NC_OK) return st;

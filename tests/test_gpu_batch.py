@@ -54,6 +54,29 @@ def test_batch_equals_single_renders():
         torch.testing.assert_close(s2[offs[j]:offs[j] + n], r2.ravel(), rtol=1e-12, atol=1e-12)
 
 
+def test_batch_with_extended_medium_equals_single_renders():
+    """A solar disc, a tabulated phase function and a k-distribution shared
+    by all jobs (the extended-medium kernels): still image by image the
+    single renders."""
+    sc = inputs.scene_small()
+    c = ctx()
+    kd = device_field(sc.kc)
+    kdist = (np.array([0.3, 0.5, 0.2]), np.array([0.0, 0.02, 0.05]))
+    g = api.build_grid(c, kd, sc.desc, inputs.GridParams(sc.grid.tau_tilde, 0.05, sc.grid.criterion))
+    tab = api.PhaseTable(c, *inputs.phase_table_tthg(n=61))
+    ext = {"sun_half_angle_deg": 2.0, "phase_table": tab, "kdist": kdist}
+    jobs = [(cam, Optics(**{**vars(op), **ext})) for cam, op in _jobs(sc)]
+    smp = Sampling(seed=37, spp=6, stream=9)
+    s, s2, offs = api.render_batch(c, g, kd, jobs, smp)
+    torch.cuda.synchronize()
+    for j, (cam, op) in enumerate(jobs):
+        r, r2 = api.render(c, g, kd, op, cam, Sampling(seed=37, spp=6, stream=9 + j))
+        n = cam.width * cam.height
+        torch.testing.assert_close(s[offs[j]:offs[j] + n], r.ravel(), rtol=1e-12, atol=1e-12)
+        torch.testing.assert_close(s2[offs[j]:offs[j] + n], r2.ravel(), rtol=1e-12, atol=1e-12)
+    assert float(s.sum()) > 0.0
+
+
 def test_batch_rejects_mixed_media():
     sc, c, kd, g = _scene()
     jobs = _jobs(sc)[:2]
