@@ -1442,15 +1442,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         }
                         job = lo;
                         const volatile JobView &J = R.jobs[job];
-                        const int tx = J.tiles_x, ty = J.tiles_y, spi = R.spi, spp = R.spp;
+                        const int tx = J.tiles_x, spi = R.spi, spp = R.spp;
                         const int W = J.cam.W, H = J.cam.H;
                         // a job has fewer than 2^32 items (checked at launch): 32-bit divisions
                         const uint32_t lw = (uint32_t)(w - J.item_begin);
-                        const uint32_t tile_px = (uint32_t)tx * (uint32_t)ty * 64u;
-                        const uint32_t blk_u = lw / tile_px;
-                        const int blk = (int)blk_u;
-                        const int rem = (int)(lw - blk_u * tile_px);
-                        const int tile = rem >> 6, within = rem & 63;
+                        // items run tile by tile, each tile's sample blocks together: the
+                        // waves in flight share a narrow band of the image, so their paths
+                        // share the caches (sample block major: 6 % slower on the cumulus view)
+                        const uint32_t nblk = (uint32_t)((spp + spi - 1) / spi);
+                        const uint32_t per_tile = nblk * 64u;
+                        const uint32_t tile_u = lw / per_tile;
+                        const int tile = (int)tile_u;
+                        const int rem = (int)(lw - tile_u * per_tile);
+                        const int blk = rem >> 6, within = rem & 63;
                         const int trow = (int)((uint32_t)tile / (uint32_t)tx);
                         const int px = (tile - trow * tx) * 8 + (within & 7);
                         const int py = trow * 8 + (within >> 3);
