@@ -78,9 +78,10 @@ struct nc_guide {
 
 namespace nc {
 
-constexpr int kScratchWords = 256;   // [0] queue head, [1] validation flag, [2] cloudy layer, [8..] launch parameters
+constexpr int kScratchWords = 384;   // [1] validation flag, [2] cloudy layer, [8..] launch parameters
 constexpr int kScratchRare = 8;
 constexpr int kScratchErr = 240;     // [240..242] image error accumulators (float64)
+constexpr int kScratchQueues = 256;  // [256 + 16 q] head of work queue q (q < 8), one per 128-byte line
 
 // Camera, optics and launch records as the kernels see them (FP32).
 struct CamView {

@@ -515,8 +515,9 @@ struct RenderArgs {
     int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
     float gpos[3];              // network position input: (x - lo) * gpos - 1 spans [-1, 1] over the box
     nc_counters *counters;
-    unsigned long long *queue;
+    unsigned long long *queue;  // 8 queue heads, 16 words apart
     unsigned long long items;
+    unsigned long long q_span;  // items per queue (a multiple of kChunk)
     int lds_first, lds_nodes;
 };
 
@@ -1038,6 +1039,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     unsigned long long chunk_base = 0;   // wave-uniform: the wave's chunk of queue items
     int chunk_left = 0;
     bool queue_done = false;
+    int q_seen = 0;                      // wave-uniform: queues found drained (its XCD's first)
     int guide_wait = 0;                  // wave-uniform: trips that lanes have waited for the network
 
     for (;;) {
@@ -1421,8 +1423,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 unsigned long long nb = A.items;
                 if (take_new > 0 && !queue_done) {
                     const int leader = __ffsll((unsigned long long)need) - 1;
-                    if (lane == leader) nb = atomicAdd(A.queue, (unsigned long long)kChunk);
+                    if (lane == leader) {
+                        // workgroups are dealt to the 8 XCDs in turn (blockIdx mod 8);
+                        // queue q holds the q-th eighth of the items, so each XCD's L2
+                        // serves its own band of the image; a drained queue sends the
+                        // wave on to the next one
+                        for (;;) {
+                            const int q = (int)((blockIdx.x + (unsigned)q_seen) & 7u);
+                            const unsigned long long lo = (unsigned long long)q * A.q_span;
+                            const unsigned long long hi = lo + A.q_span < A.items ? lo + A.q_span : A.items;
+                            const unsigned long long b = lo + atomicAdd(A.queue + 16 * q, (unsigned long long)kChunk);
+                            if (b < hi) { nb = b; break; }
+                            if (++q_seen == 8) { nb = A.items; break; }
+                        }
+                    }
                     nb = __shfl(nb, leader);
+                    q_seen = __shfl(q_seen, leader);
                     if (nb >= A.items) queue_done = true;
                 }
                 if (need_item) {
@@ -1632,7 +1648,8 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.stream_base = s.stream;
     A.items = items;
     A.counters = counters;
-    A.queue = ctx->d_scratch;
+    A.queue = ctx->d_scratch + kScratchQueues;
+    A.q_span = ((items + 8 * kChunk - 1) / (8 * kChunk)) * kChunk;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
     const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
@@ -1652,7 +1669,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     if (e == hipSuccess)
         e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, ctx->d_scratch, 1);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(2), dim3(64), 0, ctx->stream, ctx->d_scratch + kScratchQueues, 128);
     if (collect) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, collect->count, 1);
     // register budget: waves per SIMD the kernel is compiled for (3..6)
     // (default 4: the plain kernel fits 128 registers without spilling)
