@@ -64,7 +64,7 @@ def parse():
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
     p.add_argument("--collect-spp", type=int, default=64, help="plain samples per pixel whose vertices train the guide")
     p.add_argument("--train-steps", type=int, default=40000)
-    p.add_argument("--batch-train-steps", type=int, default=10000, help="Adam steps of each per-sun network of the batch")
+    p.add_argument("--batch-train-steps", type=int, default=20000, help="Adam steps of each per-sun network of the batch")
     p.add_argument("--train-batch", type=int, default=65536)
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
@@ -666,9 +666,11 @@ def batch_block_err(s, s2, offs, jobs, spp, b=8):
 
 def batch_guided_run(ctx, sc, kc, spp, args):
     """The 48 views x 4 suns with guidance: one network per sun (its inputs do
-    not see the sun), trained on vertices of that sun's largest view; one
-    guided launch per sun.  Error on 8x8-pixel block means against the plain
-    batch at the same spp."""
+    not see the sun), trained on vertices of 8 of that sun's views spread
+    around the ring (every 6th, 5 spp each: the guided paths start from all
+    around the cloud, and a network fed from one view alone generalised
+    badly to the others); one guided launch per sun.  Error on 8x8-pixel
+    block means against the plain batch at the same spp."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -679,10 +681,14 @@ def batch_guided_run(ctx, sc, kc, spp, args):
     guides = {}
     for sz in suns:
         op = inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})
-        cam = max((c for c, z in views if z == sz), key=lambda c: c.width * c.height)
-        rec, n, _, _ = api.collect_vertices(ctx, g, kc, op, cam,
-                                            inputs.Sampling(seed=sc.sampling.seed + 301, spp=16, flags=FLAGS),
-                                            cam.width * cam.height * 16 * 16)
+        recs = []
+        for cam in [c for c, z in views if z == sz][::6]:
+            r, n, _, _ = api.collect_vertices(ctx, g, kc, op, cam,
+                                              inputs.Sampling(seed=sc.sampling.seed + 301, spp=5, flags=FLAGS),
+                                              cam.width * cam.height * 5 * 16)
+            recs.append(r)
+        rec = torch.cat(recs)
+        del recs
         gd = api.Guide(ctx, seed=1)
         gen = torch.Generator(device="cuda")
         gen.manual_seed(1)
