@@ -71,7 +71,7 @@ def parse():
     p.add_argument("--guide-max-order", type=int, default=0, help="last guided scattering order (0: all)")
     p.add_argument("--no-variants", action="store_true", help="skip the grid variants (flat supercells, tau 0, global)")
     p.add_argument("--no-refinement", action="store_true", help="skip the refinement sweep (fields 128^2x40..1024^2x320)")
-    p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1% block error")
+    p.add_argument("--no-progressive", action="store_true", help="skip the progressive runs to 1%% block error")
     p.add_argument("--max-spp", type=int, default=16384, help="cap of the progressive runs")
     p.add_argument("--no-ceiling", action="store_true", help="skip the random-read ceiling measurement")
     p.add_argument("--sun", choices=["delta", "ratio", "residual"], default="residual",
@@ -241,6 +241,8 @@ def main():
     if not args.no_flux:
         out["flux"] = flux_run(ctx)
         note("flux")
+        out["transmittance"] = transmittance_run(ctx, sc, kc)
+        note("transmittance")
     if not args.no_guide_kernels:
         out["guide_kernels"] = guide_kernel_run(ctx, args)
         note("guide_kernels")
@@ -399,6 +401,36 @@ def flux_run(ctx):
             "photons_per_s": N / (t1 - t0), "mean_T": float(T.mean()),
             "dmeanT_ds": float(out[0]) * f / 1e4, "dmeanT_dg": float(out[1]) * f / 1e4,
             "dmeanT_dalpha": float(out[2]) * f / 1e4}
+
+
+def transmittance_run(ctx, sc, kc):
+    """Direct transmissivity (nc_transmittance) of 2^22 rays from uniform
+    points of the workload's box towards its sun, 16 paths each, for the
+    three estimators."""
+    import torch
+
+    from paper_1902_01137_amd import _lib, api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    n, spp = 1 << 22, 16
+    gen = np.random.default_rng(5)
+    (xa, xb), (ya, yb), (za, zb) = sc.desc.box
+    o = np.stack([gen.uniform(xa, xb, n), gen.uniform(ya, yb, n), gen.uniform(za, zb, n)], axis=1)
+    d = np.broadcast_to(np.asarray(inputs.sun_direction(sc.optics.sun_zenith_deg, sc.optics.sun_azimuth_deg)), (n, 3))
+    rays = torch.from_numpy(np.concatenate([o, d], axis=1).astype(np.float32)).cuda()
+    res = {"rays": n, "spp": spp}
+    for name, fl in (("delta", _lib.NC_SUN_DELTA), ("ratio", _lib.NC_SUN_RATIO), ("residual", _lib.NC_SUN_RESIDUAL)):
+        api.transmittance(ctx, g, kc, sc.optics, rays[:4096], inputs.Sampling(seed=1, spp=spp, flags=fl))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, s2 = api.transmittance(ctx, g, kc, sc.optics, rays, inputs.Sampling(seed=sc.sampling.seed + 91, spp=spp,
+                                                                                flags=fl))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        m = s / spp
+        var = (s2 / spp - m * m).clamp(min=0) * spp / (spp - 1) / spp
+        res[name] = {"ms": dt * 1e3, "paths_per_s": n * spp / dt, "mean_T": float(m.mean()),
+                     "rel_std_err": float(var.mean().sqrt() / m.mean())}
+    return res
 
 
 def guide_kernel_run(ctx, args):
