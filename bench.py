@@ -63,7 +63,7 @@ def parse():
     p.add_argument("--batch-spp", type=int, default=4)
     p.add_argument("--no-guided", action="store_true", help="skip the guided leg (collect, train, guided render)")
     p.add_argument("--collect-spp", type=int, default=64, help="plain samples per pixel whose vertices train the guide")
-    p.add_argument("--train-steps", type=int, default=40000)
+    p.add_argument("--train-steps", type=int, default=80000, help="Adam steps of the single-view network")
     p.add_argument("--batch-train-steps", type=int, default=20000, help="Adam steps of each per-sun network of the batch")
     p.add_argument("--train-batch", type=int, default=65536)
     p.add_argument("--lr", type=float, default=3e-3)
