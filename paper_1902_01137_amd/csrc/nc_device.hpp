@@ -45,6 +45,17 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
     return c;
 }
 
+// The same with a key that is uniform over the wave (a kernel argument): the
+// empty asm makes the key a fresh scalar at every call, so the round keys are
+// formed by scalar adds inside the rounds instead of being hoisted out of
+// the tracing loop as 18 loop invariants that take scalar registers from the
+// loop (and are spilled).  Never call it with a key that differs across lanes.
+__device__ inline U4 philox4x32_10_uk(U4 c, uint32_t k0, uint32_t k1)
+{
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    return philox4x32_10(c, k0, k1);
+}
+
 // A path's random stream: counter = (a, b, draw, stream), key = seed.  Each
 // Philox call yields four uniforms, consumed in order.
 struct Rng {
@@ -67,7 +78,7 @@ struct Rng {
     __device__ float u01()
     {
         if (left == 0) {
-            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            U4 r = philox4x32_10_uk(U4{a, b, draw, stream}, k0, k1);
             ++draw;
             q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
             left = 4;
@@ -87,7 +98,7 @@ struct Rng {
     __device__ void need(int k)
     {
         if (left < k) {
-            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            U4 r = philox4x32_10_uk(U4{a, b, draw, stream}, k0, k1);
             ++draw;
             q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
             left = 4;
@@ -119,7 +130,7 @@ struct RngBuf {
     __device__ void need(int k, uint32_t a, uint32_t b, uint32_t stream, uint32_t k0, uint32_t k1)
     {
         if (left < k) {
-            U4 r = philox4x32_10(U4{a, b, draw, stream}, k0, k1);
+            U4 r = philox4x32_10_uk(U4{a, b, draw, stream}, k0, k1);
             ++draw;
             q0 = r.x; q1 = r.y; q2 = r.z; q3 = r.w;
             left = 4;
@@ -258,12 +269,15 @@ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, i
     (void)hint;
     float kmin, kmax;
     int l = 0;
-    const size_t cell = ((size_t)r.c[2] * g.n[1] + r.c[1]) * g.n[0] + r.c[0];
+    // cell indices are >= 0; the row index fits 32 bits (n1, n2 <= 2^15)
+    const uint32_t row = (uint32_t)r.c[2] * (uint32_t)g.n[1] + (uint32_t)r.c[1];
+    const uint64_t cell = (uint64_t)row * (uint32_t)g.n[0] + (uint32_t)r.c[0];
     const float kcell = g.kc[cell];
     ++node_reads;
     if (g.L >= 1) {
         const int d0 = level_dim(g.n[0], 1), d1 = level_dim(g.n[1], 1);
-        const uint32_t m = g.mask[((size_t)(r.c[2] >> 1) * d1 + (r.c[1] >> 1)) * d0 + (r.c[0] >> 1)];
+        const uint32_t mrow = (uint32_t)(r.c[2] >> 1) * (uint32_t)d1 + (uint32_t)(r.c[1] >> 1);
+        const uint32_t m = g.mask[(uint64_t)mrow * (uint32_t)d0 + (uint32_t)(r.c[0] >> 1)];
         ++node_reads;
         l = m ? 31 - __clz(m) : 0;
     }
@@ -384,7 +398,8 @@ __device__ inline size_t collision_cell(const GridView &g, const Ray &r, float t
             cc[a] = j < base ? base : (j > top ? top : j);
         }
     }
-    return ((size_t)cc[2] * g.n[1] + cc[1]) * g.n[0] + cc[0];
+    const uint32_t row = (uint32_t)cc[2] * (uint32_t)g.n[1] + (uint32_t)cc[1];
+    return (size_t)((uint64_t)row * (uint32_t)g.n[0] + (uint32_t)cc[0]);
 }
 
 // ---------------------------------------------------------------------------
