@@ -22,6 +22,8 @@ sys.path.insert(0, ROOT)
 METRIC = "paths/s + time to 1% rel. std err radiance, plain vs guided, 1 MI355X"
 HBM_PEAK_GBS = 8000.0
 GRANULE = 64  # bytes moved by one random 4- or 8-byte read from HBM
+MI355X_SIMDS = 256 * 4       # compute units x SIMDs per compute unit
+MI355X_CLOCK_HZ = 2.4e9      # peak engine clock
 PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
 
 
@@ -36,14 +38,30 @@ def kernel_sources_digest():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per render launch from the committed rocprofv3 counter runs, or None if stale."""
+def _profile_record():
+    """The committed rocprofv3 record of the render kernel, or None if missing or measured on other sources."""
     path = os.path.join(ROOT, "profiles", "render_traffic.json")
     if not os.path.exists(path):
         return None
     with open(path) as fh:
         rec = json.load(fh)
-    return rec["bytes_per_launch"] if rec.get("sources_sha256") == kernel_sources_digest() else None
+    return rec if rec.get("sources_sha256") == kernel_sources_digest() else None
+
+
+def measured_traffic():
+    """HBM bytes per render launch from the committed rocprofv3 counter runs, or None if stale."""
+    rec = _profile_record()
+    return rec["bytes_per_launch"] if rec else None
+
+
+def measured_valu_issue(render_ms):
+    """Share of the SIMDs' cycles spent issuing VALU instructions during one render launch:
+    SQ_ACTIVE_INST_VALU of the committed counter run (units of 4 cycles, summed over waves)
+    x 4 over SIMDs x clock x this run's kernel time; None if the record is stale or lacks it."""
+    rec = _profile_record()
+    if not rec or "sq_active_inst_valu" not in rec:
+        return None
+    return rec["sq_active_inst_valu"] * 4.0 / (MI355X_SIMDS * MI355X_CLOCK_HZ * render_ms / 1e3)
 
 
 def parse():
@@ -218,7 +236,9 @@ def main():
                                    "step time x (err / 0.01)^2, plus the guide's collection and training time",
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None},
+                     "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None,
+                     "valu_issue_frac": measured_valu_issue(render_ms)
+                     if args.workload == "cumulus" and spp == 64 else None},
     }
     gd = None
     if not args.no_guided:
