@@ -76,7 +76,7 @@ def lib():
         L.orc_optical_depth.argtypes = [C.POINTER(Field), _P, C.c_double]
         L.orc_optical_depth.restype = C.c_double
         L.orc_transmittance.argtypes = [C.POINTER(Field), _P, C.c_int, C.c_double, _P, C.c_int32, C.c_int32,
-                                        C.c_uint64, _P, _P, _P]
+                                        C.c_uint64, _P, _P, _P, _P]
         L.orc_hg_phase.argtypes = [C.c_double, C.c_double]
         L.orc_hg_phase.restype = C.c_double
         L.orc_hg_sample_mu.argtypes = [C.c_double, C.c_double]
@@ -88,6 +88,8 @@ def lib():
         L.orc_camera_ray.argtypes = [C.POINTER(CameraC), C.c_int, C.c_int, C.c_double, C.c_double, _P]
         L.orc_render.argtypes = [C.POINTER(Field), C.POINTER(OpticsC), C.POINTER(CameraC), C.c_int32, C.c_uint64,
                                  _P, C.c_int32, _P, _P, _P]
+        L.orc_render_tracked.argtypes = [C.POINTER(Field), _P, C.POINTER(OpticsC), C.POINTER(CameraC), C.c_int32,
+                                         C.c_uint64, _P, C.c_int32, _P, _P, _P, _P]
         L.orc_hg_dlng.argtypes = [C.c_double, C.c_double]
         L.orc_hg_dlng.restype = C.c_double
         L.orc_flux.argtypes = [C.POINTER(Field), _P, C.POINTER(OpticsC), C.c_int32, C.c_int32, C.c_int32,
@@ -217,8 +219,8 @@ class OracleGrid:
             raise ValueError("leaf sequence longer than maxv")
         return leaf[:n].copy(), t[:n].copy(), bool(deg[0])
 
-    def transmittance(self, rays, nsamples, seed, mode=2, majorant_scale=1.0):
-        return transmittance(self.field, rays, nsamples, seed, mode, majorant_scale, grid=self)
+    def transmittance(self, rays, nsamples, seed, mode=2, majorant_scale=1.0, with_sq=False):
+        return transmittance(self.field, rays, nsamples, seed, mode, majorant_scale, grid=self, with_sq=with_sq)
 
 
 # ---------------------------------------------------------------------------
@@ -230,17 +232,19 @@ def optical_depth(field: Field, ray, t1=np.inf):
     return lib().orc_optical_depth(C.byref(field), _ptr(r), float(t1))
 
 
-def transmittance(field: Field, rays, nsamples, seed, mode, majorant_scale=1.0, grid=None):
-    """Per-ray (mean, se, counters[tentative, null, leaf visits])."""
+def transmittance(field: Field, rays, nsamples, seed, mode, majorant_scale=1.0, grid=None, with_sq=False):
+    """Per-ray (mean, se, counters[tentative, null, leaf visits]) and, with
+    with_sq, the sums of the counters' per-path squares."""
     rays = np.ascontiguousarray(rays, dtype=np.float64).reshape(-1, 6)
     n = rays.shape[0]
     mean = np.zeros(n)
     se = np.zeros(n)
     cnt = np.zeros(3, np.uint64)
+    sq = np.zeros(3)
     lib().orc_transmittance(C.byref(field), grid.handle if grid is not None else None, int(mode),
                             float(majorant_scale), _ptr(rays), n, int(nsamples), int(seed),
-                            _ptr(mean), _ptr(se), _ptr(cnt))
-    return mean, se, cnt
+                            _ptr(mean), _ptr(se), _ptr(cnt), _ptr(sq))
+    return (mean, se, cnt, sq) if with_sq else (mean, se, cnt)
 
 
 def hg_phase(g, mu):
@@ -274,6 +278,27 @@ def render(desc, kc, k_gas, optics, cam, spp, seed, pixels=None):
     lib().orc_render(C.byref(f), C.byref(op), C.byref(c), int(spp), int(seed), _ptr(pixels), len(pixels),
                      _ptr(s), _ptr(s2), _ptr(cnt))
     return s, s2, cnt
+
+
+def render_tracked(desc, kc, k_gas, optics, cam, spp, seed, grid, pixels=None):
+    """Backward radiance with every ray null-collision tracked in `grid`'s
+    majorant (an OracleGrid over the same kc and k_gas; the majorant scale is
+    optics.majorant_scale) and delta-tracked sun rays: (sum, sumsq, stats)
+    with stats[0:3] the sums over paths of the path's tentative collisions,
+    nulls and leaves entered, stats[3:6] the sums of their squares."""
+    f = make_field(desc, kc, k_gas)
+    op = make_optics(optics)
+    c = make_camera(cam)
+    if pixels is None:
+        pixels = np.arange(cam.width * cam.height, dtype=np.int32)
+    pixels = np.ascontiguousarray(pixels, dtype=np.int32)
+    s = np.zeros(len(pixels))
+    s2 = np.zeros(len(pixels))
+    cnt = np.zeros(3, np.uint64)
+    st = np.zeros(6)
+    lib().orc_render_tracked(C.byref(f), grid.handle, C.byref(op), C.byref(c), int(spp), int(seed), _ptr(pixels),
+                             len(pixels), _ptr(s), _ptr(s2), _ptr(cnt), _ptr(st))
+    return s, s2, st
 
 
 def hg_dlng(g, mu):

@@ -625,8 +625,9 @@ static int regular_free_path(const orc_field *f, const double o[3], const double
  *           m (kmax_c(leaf) + k_g) in each leaf (Fig. 2c), with the free path
  *           carried from leaf to leaf;
  *   mode 0: no sampling: the exact exp(-tau).
- * counters (mode 2): [0] tentative collisions, [1] null collisions,
- * [2] leaf visits, summed over all samples.
+ * counters (modes 1 and 2, may be NULL): [0] tentative collisions, [1] null
+ * collisions, [2] leaf visits, summed over all samples; counters_sq (may be
+ * NULL): the sums of their per-sample squares (for standard errors).
  * ======================================================================== */
 static double field_max_kc(const orc_field *f)
 {
@@ -674,14 +675,17 @@ static int delta_global(const orc_field *f, double khat, const double o[3], cons
 /* Delta tracking in the grid's piecewise-constant majorant, written cell by
  * cell: inside one leaf the majorant is constant, so consuming the leaf one
  * cell at a time with the remaining optical thickness carried over is the
- * same walk as consuming it at once. */
-static int delta_hier(const orc_field *f, const orc_grid *g, double m, const double o[3], const double d[3],
-                      orc_rng *r, uint64_t *cnt)
+ * same walk as consuming it at once.  Returns 1 at the first real collision
+ * (its parameter and the droplet extinction there in *tc, *kd) and 0 when
+ * the ray leaves B.  cnt (may be NULL): [0] tentative collisions, [1] nulls,
+ * [2] leaves entered. */
+static int delta_hier_walk(const orc_field *f, const orc_grid *g, double m, const double o[3], const double d[3],
+                           orc_rng *r, uint64_t *cnt, double *tc, double *kd)
 {
     walker w;
     double tau_s;
     int prev[4] = {-1, -1, -1, -1};
-    if (!walker_init(&w, f, o, d, 0.0)) return 1;
+    if (!walker_init(&w, f, o, d, 0.0)) return 0;
     tau_s = -log(1.0 - rng_u01(r));
     for (;;) {
         int axis, lev, id[3];
@@ -697,20 +701,31 @@ static int delta_hier(const orc_field *f, const orc_grid *g, double m, const dou
             w.t += tau_s / khat;
             k = walker_k(&w);
             if (cnt) cnt[0]++;
-            if (rng_u01(r) * khat < k) return 0;
+            if (rng_u01(r) * khat < k) {
+                if (tc) *tc = w.t;
+                if (kd) *kd = cell_kd(f, w.idx[0], w.idx[1], w.idx[2]);
+                return 1;
+            }
             if (cnt) cnt[1]++;
             tau_s = -log(1.0 - rng_u01(r));
         }
         if (te > w.t) tau_s -= khat * (te - w.t);
-        if (!walker_advance(&w, te, axis)) return 1;
+        if (!walker_advance(&w, te, axis)) return 0;
     }
+}
+
+/* The 0/1 transmissivity estimate of delta tracking: 1 iff no real collision. */
+static int delta_hier(const orc_field *f, const orc_grid *g, double m, const double o[3], const double d[3],
+                      orc_rng *r, uint64_t *cnt)
+{
+    return !delta_hier_walk(f, g, m, o, d, r, cnt, NULL, NULL);
 }
 
 void orc_transmittance(const orc_field *f, const orc_grid *g, int mode, double majorant_scale,
                        const double *rays, int32_t n, int32_t nsamples, uint64_t seed,
-                       double *mean, double *se, uint64_t *counters)
+                       double *mean, double *se, uint64_t *counters, double *counters_sq)
 {
-    int i, s;
+    int i, s, k;
     double kglob = majorant_scale * (field_max_kc(f) + f->k_gas);
     for (i = 0; i < n; ++i) {
         const double *o = rays + 6 * i, *d = rays + 6 * i + 3;
@@ -723,11 +738,16 @@ void orc_transmittance(const orc_field *f, const orc_grid *g, int mode, double m
             double sum = 0.0;
             for (s = 0; s < nsamples; ++s) {
                 orc_rng r;
+                uint64_t pc[3] = {0, 0, 0};
                 int t;
                 rng_init(&r, seed, ((uint64_t)i << 24) + (uint64_t)s);
-                if (mode == 1) t = delta_global(f, kglob, o, d, &r, counters);
-                else t = delta_hier(f, g, majorant_scale, o, d, &r, counters);
+                if (mode == 1) t = delta_global(f, kglob, o, d, &r, pc);
+                else t = delta_hier(f, g, majorant_scale, o, d, &r, pc);
                 sum += t;
+                for (k = 0; k < 3; ++k) {
+                    if (counters) counters[k] += pc[k];
+                    if (counters_sq) counters_sq[k] += (double)pc[k] * (double)pc[k];
+                }
             }
             mean[i] = sum / nsamples;
             /* the estimator is Bernoulli: its variance is p(1-p) */
@@ -969,17 +989,46 @@ static double sun_transmissivity(const orc_field *f, const double x[3], const do
     return tau > 200.0 ? 0.0 : exp(-tau);
 }
 
+/* How a path's rays meet the medium.  g == NULL: path tracking (exact free
+ * paths) and the exact sun transmissivity, as above.  g != NULL: the
+ * null-collision algorithm of Section 2.3 in the grid's piecewise-constant
+ * majorant m (kmax_c + k_g) for the free paths and for the sun rays (a sun
+ * ray then reports 0 or 1), with the path's tentative collisions, nulls and
+ * leaves entered counted in cnt. */
+typedef struct {
+    const orc_grid *g;
+    double m;
+    uint64_t cnt[3];
+} orc_tracker;
+
+/* Sun contribution `weight` times the transmissivity towards the sun along w;
+ * no sun ray is traced for a zero weight. */
+static double local_estimate(const orc_field *f, orc_tracker *tk, const double x[3], const double w[3], double weight,
+                             orc_rng *r)
+{
+    if (!(weight > 0.0)) return 0.0;
+    if (tk->g) return delta_hier(f, tk->g, tk->m, x, w, r, tk->cnt) ? weight : 0.0;
+    return weight * sun_transmissivity(f, x, w);
+}
+
 static double radiance_path(const orc_field *f, const orc_optics *op, const double s[3], double o_in[3],
-                            double d_in[3], int primary, orc_rng *r, uint64_t *cnt)
+                            double d_in[3], int primary, orc_rng *r, uint64_t *cnt, orc_tracker *tk)
 {
     double o[3], d[3], L = 0.0, gain = cone_gain(op);
     int order = 0, a, segs = 0;
     for (a = 0; a < 3; ++a) { o[a] = o_in[a]; d[a] = d_in[a]; }
     for (;;) {
         double tc, kc;
-        double tau_s = -log(1.0 - rng_u01(r));
-        if (++segs > op->max_segments) break;
-        if (regular_free_path(f, o, d, 0.0, tau_s, &tc, &kc)) {
+        int hit;
+        if (tk->g) {
+            if (++segs > op->max_segments) break;
+            hit = delta_hier_walk(f, tk->g, tk->m, o, d, r, tk->cnt, &tc, &kc);
+        } else {
+            double tau_s = -log(1.0 - rng_u01(r));
+            if (++segs > op->max_segments) break;
+            hit = regular_free_path(f, o, d, 0.0, tau_s, &tc, &kc);
+        }
+        if (hit) {
             double x[3], k = kc + f->k_gas, ssa = op->ssa * kc / k, mu_sun, nd[3];
             for (a = 0; a < 3; ++a) x[a] = o[a] + tc * d[a];
             if (cnt) cnt[0]++;
@@ -989,7 +1038,7 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
                 double w[3];
                 sun_sample(op, s, r, w);
                 mu_sun = d[0] * w[0] + d[1] * w[1] + d[2] * w[2];
-                L += ssa * phase_eval(op, mu_sun) * op->S * gain * sun_transmissivity(f, x, w);
+                L += local_estimate(f, tk, x, w, ssa * phase_eval(op, mu_sun) * op->S * gain, r);
             }
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
             if (rng_u01(r) >= ssa) break;
@@ -1009,8 +1058,7 @@ static double radiance_path(const orc_field *f, const orc_optics *op, const doub
             {
                 double w[3];
                 sun_sample(op, s, r, w);
-                if (w[2] > 0.0)
-                    L += (op->rho / ORC_PI) * op->S * gain * w[2] * sun_transmissivity(f, x, w);
+                if (w[2] > 0.0) L += local_estimate(f, tk, x, w, (op->rho / ORC_PI) * op->S * gain * w[2], r);
             }
             if (op->max_scatter >= 0 && order >= op->max_scatter) break;
             if (rng_u01(r) >= op->rho) break;
@@ -1047,11 +1095,12 @@ static double kd_pick(const orc_optics *op, double u)
     return op->kd_k[op->kd_n - 1];
 }
 
-void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam, int32_t spp, uint64_t seed,
-                const int32_t *pixels, int32_t npix, double *sum, double *sumsq, uint64_t *counters)
+static void render_pixels(const orc_field *f, const orc_optics *op, const orc_camera *cam, int32_t spp,
+                          uint64_t seed, const int32_t *pixels, int32_t npix, double *sum, double *sumsq,
+                          uint64_t *counters, const orc_grid *g, double *path_stats)
 {
     double s[3];
-    int i, k;
+    int i, k, c;
     sun_dir(op, s);
     for (i = 0; i < npix; ++i) {
         int p = pixels[i], px = p % cam->width, py = p / cam->width;
@@ -1060,6 +1109,7 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
             orc_rng r;
             double o[3], d[3], L;
             orc_field fk = *f;      /* the path's medium (its gas extinction under a k-distribution) */
+            orc_tracker tk = {g, op->majorant_scale, {0, 0, 0}};
             rng_init(&r, seed, ((uint64_t)p << 24) + (uint64_t)k);
             if (op->kd_n > 0) fk.k_gas = kd_pick(op, rng_u01(&r));
             {
@@ -1069,25 +1119,50 @@ void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam,
             if (cam->type == 2) {
                 double w[3];
                 sun_sample(op, s, &r, w);
-                L = (s[2] > 0.0 && w[2] > 0.0) ? op->S * cone_gain(op) * (w[2] / s[2]) * sun_transmissivity(&fk, o, w)
-                                               : 0.0;
+                L = (s[2] > 0.0 && w[2] > 0.0)
+                        ? local_estimate(&fk, &tk, o, w, op->S * cone_gain(op) * (w[2] / s[2]), &r)
+                        : 0.0;
                 if (op->max_scatter != 0 && s[2] > 0.0) {
                     double v1 = rng_u01(&r), v2 = rng_u01(&r), rr = sqrt(v1), phi = 2.0 * ORC_PI * v2;
                     d[0] = rr * cos(phi);
                     d[1] = rr * sin(phi);
                     d[2] = sqrt(fmax(0.0, 1.0 - v1));
-                    L += ORC_PI / s[2] * radiance_path(&fk, op, s, o, d, 0, &r, counters);
+                    L += ORC_PI / s[2] * radiance_path(&fk, op, s, o, d, 0, &r, counters, &tk);
                 }
             } else {
-                L = radiance_path(&fk, op, s, o, d, 1, &r, counters);
+                L = radiance_path(&fk, op, s, o, d, 1, &r, counters, &tk);
             }
             if (counters) counters[2]++;
+            if (path_stats)
+                for (c = 0; c < 3; ++c) {
+                    path_stats[c] += (double)tk.cnt[c];
+                    path_stats[3 + c] += (double)tk.cnt[c] * (double)tk.cnt[c];
+                }
             acc += L;
             acc2 += L * L;
         }
         sum[i] = acc;
         sumsq[i] = acc2;
     }
+}
+
+void orc_render(const orc_field *f, const orc_optics *op, const orc_camera *cam, int32_t spp, uint64_t seed,
+                const int32_t *pixels, int32_t npix, double *sum, double *sumsq, uint64_t *counters)
+{
+    render_pixels(f, op, cam, spp, seed, pixels, npix, sum, sumsq, counters, NULL, NULL);
+}
+
+/* The same estimate with every ray tracked by the null-collision algorithm
+ * in the grid's majorant op->majorant_scale (kmax_c + k_g) (O4b: free paths
+ * and delta-tracked sun rays, leaf by leaf), for the expected event counts of
+ * the GPU renderer with delta-tracked sun rays.  path_stats[6]: sums over
+ * paths of the path's tentative collisions, null collisions and leaves
+ * entered (all its rays), then the sums of their squares. */
+void orc_render_tracked(const orc_field *f, const orc_grid *g, const orc_optics *op, const orc_camera *cam,
+                        int32_t spp, uint64_t seed, const int32_t *pixels, int32_t npix, double *sum, double *sumsq,
+                        uint64_t *counters, double *path_stats)
+{
+    render_pixels(f, op, cam, spp, seed, pixels, npix, sum, sumsq, counters, g, path_stats);
 }
 
 /* ========================================================================

@@ -21,12 +21,13 @@ def block(mean, se, shape, b=8):
     return m.mean(axis=(1, 3)).ravel(), np.sqrt((e ** 2).sum(axis=(1, 3))).ravel() / (b * b)
 
 
-def compare(ma, sa, mb, sb, zmax_global=4.0, p_min=1e-4):
+def compare(ma, sa, mb, sb, zmax_global=3.0, p_min=1e-3):
     """Two-sample z-tests with independent errors.
 
     Passes if the number of |z| > 3 elements is consistent with
     Binomial(n, 0.0027) (p-value >= p_min) and the z of the overall mean is
-    below zmax_global.  Returns a dict of diagnostics and the verdict."""
+    below zmax_global (the acceptance rule of the parity tests: 3 combined
+    standard errors, p >= 1e-3).  Returns a dict of diagnostics and the verdict."""
     ma, sa, mb, sb = (np.asarray(x, dtype=np.float64).ravel() for x in (ma, sa, mb, sb))
     den = np.sqrt(sa ** 2 + sb ** 2)
     ok = den > 0
@@ -42,3 +43,18 @@ def compare(ma, sa, mb, sb, zmax_global=4.0, p_min=1e-4):
                bad_zero_se=int(exact_eq.sum()))
     res["ok"] = (p >= p_min) and abs(zg) < zmax_global and res["bad_zero_se"] == 0
     return res
+
+
+def vs_exact(m, se, exact, zmax_global=3.0, p_min=1e-3):
+    """compare() of estimates against exact values (zero standard error)."""
+    m = np.asarray(m, dtype=np.float64).ravel()
+    ex = np.broadcast_to(np.asarray(exact, dtype=np.float64).ravel() if np.ndim(exact) else exact, m.shape)
+    se = np.broadcast_to(np.asarray(se, dtype=np.float64).ravel() if np.ndim(se) else se, m.shape)
+    return compare(m, np.array(se, dtype=np.float64), np.array(ex, dtype=np.float64), np.zeros_like(m), zmax_global,
+                   p_min)
+
+
+def z_scalar(a, sa, b, sb=0.0):
+    """z of one difference with independent errors."""
+    den = math.sqrt(sa * sa + sb * sb)
+    return (a - b) / den if den > 0 else (0.0 if a == b else math.inf)

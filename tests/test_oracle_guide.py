@@ -141,7 +141,7 @@ def test_mis_weight_is_unbiased():
     q = G.vmf_pdf(mu[None, :], np.array([kappa]), d)
     est = G.mis_weight(p, q, c) * f(d)
     se = math.sqrt(est.var() / n + f(hg_sample(n)).var() / n)
-    assert abs(est.mean() - ref) < 4 * se
+    assert abs(est.mean() - ref) < 3 * se
 
 
 def test_adam_first_step_is_signed_lr():
