@@ -169,6 +169,12 @@ typedef struct {
 #define NC_SUN_RATIO 1
 #define NC_SUN_RESIDUAL 2
 #define NC_SUN_ESTIMATOR_MASK 3
+/* nc_flux and nc_flux_adjoint (bit 2 of nc_sampling.flags): apply the
+ * estimator's normalisation px_nx * px_ny / n_photons (ground flux over the
+ * flux through the top face, per unit area) inside the kernels, so that the
+ * tallies are the transmissivity map and its derivatives and the adjoint
+ * output is dL/ds, dL/dg, dL/dalpha (see nc_flux). */
+#define NC_FLUX_NORMALISE 4
 
 /* Sampling: seed keys the random streams; sample s of pixel p of job j uses
  * the Philox counter (p, sample_offset + s, draw, stream + j), so a run with
@@ -315,7 +321,10 @@ nc_status nc_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const n
  * transmissivity of pixel p is T_p = tally[0][p] * px_nx*px_ny / n_photons
  * (ground flux over the flux through the top, per unit area), and
  * dT_p/ds, dT_p/dg, dT_p/dalpha are tally[3][p], tally[5][p], tally[7][p]
- * times the same factor.
+ * times the same factor.  With NC_FLUX_NORMALISE in sampling->flags each
+ * arrival adds f = px_nx*px_ny / n_photons times the values above (f^2 times
+ * the squares), so that tally[0] = T_p, tally[2] = its direct part, and
+ * tally[3], tally[5], tally[7] = dT_p/ds, dT_p/dg, dT_p/dalpha.
  * d_global[4] (float64, added): photons escaping upward, absorbed by the
  * ground inside / outside the footprint, absorbed in the volume; they sum to
  * n_photons. */
@@ -328,7 +337,9 @@ nc_status nc_flux(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_
  * times the path's scores is accumulated: d_out[0] += sum grad[p] sigma_s,
  * d_out[1] += sum grad[p] sigma_g, d_out[2] += sum grad[p] sigma_a
  * (float64).  Multiplied by px_nx*px_ny / n_photons this is dL/ds, dL/dg
- * and dL/dalpha for L = sum_p grad[p] T_p.
+ * and dL/dalpha for L = sum_p grad[p] T_p; with NC_FLUX_NORMALISE in
+ * sampling->flags the kernel applies that factor (d_out receives dL/ds,
+ * dL/dg, dL/dalpha).
  * d_grad is float64 [px_ny][px_nx]. */
 nc_status nc_flux_adjoint(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                           double extinction_scale, int32_t px_nx, int32_t px_ny, uint64_t n_photons,

@@ -71,6 +71,7 @@ COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visit
                                               for b in PHASES] + ["sched_pad%d" % i for i in range(6)]
 N_COUNTER_WORDS = 34
 NC_SUN_DELTA, NC_SUN_RATIO, NC_SUN_RESIDUAL = 0, 1, 2
+NC_FLUX_NORMALISE = 4
 GUIDE_PARAMS = 11944
 GUIDE_RECORD = 12
 

@@ -367,25 +367,26 @@ class TransmissionFn(torch.autograd.Function):
     """Ground transmissivity map T(s, g, alpha) with gradients through the adjoint kernel.
 
     s scales the droplet extinction, g is the HG asymmetry, alpha = 1 - ssa the
-    droplets' absorptivity.  forward: photons traced by nc_flux; T_p =
-    arrivals_p * n_pixels / n_photons.  backward: nc_flux_adjoint replays the
-    same photons weighting each arrival by grad_T[p], giving dL/ds, dL/dg and
-    dL/dalpha for the same samples."""
+    droplets' absorptivity.  forward: photons traced by nc_flux with
+    NC_FLUX_NORMALISE, whose first tally is T_p.  backward: nc_flux_adjoint
+    (same flag) replays the same photons weighting each arrival by
+    grad_T[p] and returns dL/ds, dL/dg and dL/dalpha for the same samples.
+    This class only moves tensors: the kernels compute every number."""
 
     @staticmethod
     def forward(fctx, scale, g, alpha, lib_ctx, grid, kc, optics, px, n_photons, sampling):
         import dataclasses
         op = dataclasses.replace(optics, g=float(g), ssa=1.0 - float(alpha))
-        tally, _ = flux(lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale))
-        f = px[0] * px[1] / float(n_photons)
-        fctx.args = (lib_ctx, grid, kc, op, px, n_photons, sampling, float(scale), f)
+        smp = dataclasses.replace(sampling, flags=sampling.flags | _lib.NC_FLUX_NORMALISE)
+        tally, _ = flux(lib_ctx, grid, kc, op, px, n_photons, smp, float(scale))
+        fctx.args = (lib_ctx, grid, kc, op, px, n_photons, smp, float(scale))
         fctx.dev = scale.device if torch.is_tensor(scale) else kc.device
-        return tally[0] * f
+        return tally[0]
 
     @staticmethod
     def backward(fctx, grad_T):
-        lib_ctx, grid, kc, op, px, n_photons, sampling, s, f = fctx.args
-        out = flux_adjoint(lib_ctx, grid, kc, op, px, n_photons, sampling, grad_T, s) * f
+        lib_ctx, grid, kc, op, px, n_photons, smp, s = fctx.args
+        out = flux_adjoint(lib_ctx, grid, kc, op, px, n_photons, smp, grad_T, s)
         ds = out[0].to(fctx.dev)
         dg = out[1].to(fctx.dev)
         da = out[2].to(fctx.dev)

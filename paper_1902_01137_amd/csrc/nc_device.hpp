@@ -168,8 +168,11 @@ struct GridView {
 
 __host__ __device__ inline int level_dim(int n, int l) { return (n + (1 << l) - 1) >> l; }
 
-__device__ inline bool node_merged(float2 v) { return (__float_as_uint(v.x) >> 31) != 0; }
-__device__ inline float node_kmin(float2 v) { return __uint_as_float(__float_as_uint(v.x) & 0x7fffffffu); }
+__host__ __device__ inline bool node_merged(float2 v) { return (__builtin_bit_cast(uint32_t, v.x) >> 31) != 0; }
+__host__ __device__ inline float node_kmin(float2 v)
+{
+    return __builtin_bit_cast(float, __builtin_bit_cast(uint32_t, v.x) & 0x7fffffffu);
+}
 
 // Node access with the top levels (l >= lds_first) staged in LDS.
 struct NodeSrc {
@@ -181,7 +184,7 @@ struct NodeSrc {
     int n0, n1;
 };
 
-__device__ inline float2 fetch_node(const NodeSrc &s, int l, int c0, int c1, int c2, uint32_t &gcount)
+__host__ __device__ inline float2 fetch_node(const NodeSrc &s, int l, int c0, int c1, int c2, uint32_t &gcount)
 {
     const int d0 = level_dim(s.n0, l), d1 = level_dim(s.n1, l);
     const int idx = s.off[l] + ((c2 >> l) * d1 + (c1 >> l)) * d0 + (c0 >> l);
@@ -202,6 +205,11 @@ __device__ inline float2 fetch_node(const NodeSrc &s, int l, int c0, int c1, int
 // exit axes always move forward and no axis steps back across a voxel face,
 // so the walk visits each voxel at most once and ends after at most
 // nx + ny + nz voxels.
+//
+// The crossing functions are compiled for the host as well (a bit-exact
+// FP32 twin for testing the walk on every ray): they use only IEEE
+// operations that round the same on both sides (no approximate reciprocal;
+// the library is built without FP contraction).
 // ---------------------------------------------------------------------------
 struct Ray {
     float o[3], d[3], inv[3];
@@ -214,13 +222,13 @@ struct Ray {
     int xmask;           // axes whose voxel face is met at texit (bit a)
 };
 
-__device__ inline float face_t(const GridView &g, const Ray &r, int a, int j)
+__host__ __device__ inline float face_t(const GridView &g, const Ray &r, int a, int j)
 {
     return ((float)j * g.h[a] + g.lo[a] - r.o[a]) * r.inv[a];
 }
 
 // Clip o + t d (t >= tmin) to the box; false if it misses.
-__device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], const float d[3], float tmin)
+__host__ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], const float d[3], float tmin)
 {
     float tin = tmin, tout = INFINITY;
 #pragma unroll
@@ -232,7 +240,7 @@ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], co
             const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
             if (o[a] < b0 || o[a] > b1) return false;
         } else {
-            r.inv[a] = __builtin_amdgcn_rcpf(d[a]);
+            r.inv[a] = 1.0f / d[a];   // correctly rounded (the host twin divides alike)
             float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
             if (t0 > t1) { float s = t0; t0 = t1; t1 = s; }
             tin = fmaxf(tin, t0);
@@ -256,17 +264,16 @@ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], co
     return true;
 }
 
-__device__ inline void leaf_exit(const GridView &g, Ray &r);
+__host__ __device__ inline void leaf_exit(const GridView &g, Ray &r);
 
 // Voxel of the current cell: its coarsest merged ancestor (the cell itself
 // when no ancestor is merged).  The ancestry mask of the cell's level-1 node
 // gives the level in one read (highest set bit); the cell's own value is
 // read at the same time, so a level-0 voxel costs one round trip to memory
 // and a coarser one at most two (none when its level is staged in LDS).
-__device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, int hint, float mscale,
-                                 uint32_t &node_reads)
+__host__ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
+                                          uint32_t &node_reads)
 {
-    (void)hint;
     float kmin, kmax;
     int l = 0;
     // cell indices are >= 0; the row index fits 32 bits (n1, n2 <= 2^15)
@@ -279,7 +286,7 @@ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, i
         const uint32_t mrow = (uint32_t)(r.c[2] >> 1) * (uint32_t)d1 + (uint32_t)(r.c[1] >> 1);
         const uint32_t m = g.mask[(uint64_t)mrow * (uint32_t)d0 + (uint32_t)(r.c[0] >> 1)];
         ++node_reads;
-        l = m ? 31 - __clz(m) : 0;
+        l = m ? 31 - __builtin_clz(m) : 0;
     }
     if (l == 0) {
         kmin = kmax = kcell;
@@ -294,51 +301,8 @@ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, i
     leaf_exit(g, r);
 }
 
-// Reference walk over the levels (kept for the crossing checks): starts at
-// level `hint` and moves up or down; the merged flag is monotone along the
-// ancestry, so the first unmerged parent above a merged node (or the first
-// merged node below an unmerged one) decides.
-__device__ inline void find_leaf_walk(const GridView &g, const NodeSrc &ns, Ray &r, int hint, float mscale,
-                                      uint32_t &node_reads)
-{
-    int l = hint < 0 ? 0 : (hint > g.L ? g.L : hint);
-    float2 nd = make_float2(0.0f, 0.0f);
-    bool found = false;
-    if (l == 0 && g.L >= 1) l = 1;
-    if (l >= 1) {
-        nd = fetch_node(ns, l, r.c[0], r.c[1], r.c[2], node_reads);
-        if (node_merged(nd)) {
-            while (l < g.L) {
-                float2 p = fetch_node(ns, l + 1, r.c[0], r.c[1], r.c[2], node_reads);
-                if (!node_merged(p)) break;
-                nd = p;
-                ++l;
-            }
-            found = true;
-        } else {
-            for (--l; l >= 1; --l) {
-                nd = fetch_node(ns, l, r.c[0], r.c[1], r.c[2], node_reads);
-                if (node_merged(nd)) { found = true; break; }
-            }
-        }
-    }
-    float kmin, kmax;
-    if (found) {
-        kmin = node_kmin(nd);
-        kmax = nd.y;
-    } else {
-        l = 0;
-        kmin = kmax = g.kc[((size_t)r.c[2] * g.n[1] + r.c[1]) * g.n[0] + r.c[0]];
-        ++node_reads;
-    }
-    r.lev = l;
-    r.khat = mscale * (g.kscale * kmax + g.k_gas);
-    r.kmin = kmin;
-    leaf_exit(g, r);
-}
-
 // Exit parameter of the current voxel (its faces clipped to the field).
-__device__ inline void leaf_exit(const GridView &g, Ray &r)
+__host__ __device__ inline void leaf_exit(const GridView &g, Ray &r)
 {
     const int l = r.lev;
     float te = r.tend;
@@ -360,7 +324,8 @@ __device__ inline void leaf_exit(const GridView &g, Ray &r)
 }
 
 // Move to the voxel after the current one; false when the ray leaves the box.
-__device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale, uint32_t &node_reads)
+__host__ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
+                                          uint32_t &node_reads)
 {
     r.t = r.texit;
     if (!(r.t < r.tend)) return false;
@@ -377,7 +342,7 @@ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, f
             r.c[a] = j < vlo ? vlo : (j > vhi ? vhi : j);   // still inside the voxel's slab
         }
     }
-    find_leaf(g, ns, r, r.lev, mscale, node_reads);
+    find_leaf(g, ns, r, mscale, node_reads);
     return true;
 }
 
@@ -629,10 +594,10 @@ __device__ inline int track_step(const GridView &g, const NodeSrc &ns, Ray &r, f
 
 // Start a ray; a ray that misses the box is set up to exit on its first step.
 __device__ inline void start_ray(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3], const float d[3],
-                                 int hint, float mscale, Counters &cnt)
+                                 float mscale, Counters &cnt)
 {
     if (ray_setup(g, r, o, d, 0.0f)) {
-        find_leaf(g, ns, r, hint, mscale, cnt.node_reads);
+        find_leaf(g, ns, r, mscale, cnt.node_reads);
         ++cnt.leaf_visits;
     } else {
 #pragma unroll
@@ -643,7 +608,7 @@ __device__ inline void start_ray(const GridView &g, const NodeSrc &ns, Ray &r, c
         r.t = r.tend = r.texit = 0.0f;
         r.khat = 0.0f;
         r.kmin = 0.0f;
-        r.lev = hint;
+        r.lev = g.L;
     }
 }
 
@@ -670,7 +635,7 @@ __device__ inline void start_ray_cached(const GridView &g, const NodeSrc &ns, Ra
             r.kmin = vc.kmin;
             leaf_exit(g, r);
         } else {
-            find_leaf(g, ns, r, vc.lev, mscale, cnt.node_reads);
+            find_leaf(g, ns, r, mscale, cnt.node_reads);
         }
         ++cnt.leaf_visits;
     } else {
@@ -696,7 +661,7 @@ __device__ inline bool start_ray_cached_r(const GridView &g, const NodeSrc &ns, 
             r.kmin = vc.kmin;
             leaf_exit(g, r);
         } else {
-            find_leaf(g, ns, r, vc.lev, mscale, reads);
+            find_leaf(g, ns, r, mscale, reads);
         }
         return true;
     }

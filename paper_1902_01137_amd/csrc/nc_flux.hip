@@ -42,6 +42,7 @@ struct FluxArgs {
     double *glob;           // [4] (forward) or NULL
     const double *grad;     // [px_ny][px_nx] (adjoint) or NULL
     double *out;            // [3] (adjoint) or NULL
+    double norm;            // factor of every arrival: 1, or px_nx px_ny / n_photons (normalised output)
     nc_counters *counters;
     int lds_first, lds_nodes;
 };
@@ -111,7 +112,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
         bool scattered = false;
         int segs = 0;
         Ray r;
-        start_ray(g, ns, r, o, d, g.L, A.op.mscale, cnt);
+        start_ray(g, ns, r, o, d, A.op.mscale, cnt);
         float tau = rng.exp1();
         for (;;) {
             float kc_hit = 0.0f;
@@ -152,20 +153,21 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                     const int j = min((int)(fy * (float)A.px_ny), A.px_ny - 1);
                     const size_t q = (size_t)j * A.px_nx + i;
                     if (kAdjoint) {
-                        const double w = A.grad[q];
+                        const double w = A.grad[q] * A.norm;
                         adj_s += w * (double)sig_s;
                         adj_g += w * (double)sig_g;
                         adj_a += w * (double)sig_a;
                     } else {
-                        unsafeAtomicAdd(A.tally + q, 1.0);
-                        unsafeAtomicAdd(A.tally + np + q, 1.0);
-                        if (!scattered) unsafeAtomicAdd(A.tally + 2 * np + q, 1.0);
-                        unsafeAtomicAdd(A.tally + 3 * np + q, (double)sig_s);
-                        unsafeAtomicAdd(A.tally + 4 * np + q, (double)sig_s * (double)sig_s);
-                        unsafeAtomicAdd(A.tally + 5 * np + q, (double)sig_g);
-                        unsafeAtomicAdd(A.tally + 6 * np + q, (double)sig_g * (double)sig_g);
-                        unsafeAtomicAdd(A.tally + 7 * np + q, (double)sig_a);
-                        unsafeAtomicAdd(A.tally + 8 * np + q, (double)sig_a * (double)sig_a);
+                        const double f = A.norm, f2 = f * f;
+                        unsafeAtomicAdd(A.tally + q, f);
+                        unsafeAtomicAdd(A.tally + np + q, f2);
+                        if (!scattered) unsafeAtomicAdd(A.tally + 2 * np + q, f);
+                        unsafeAtomicAdd(A.tally + 3 * np + q, f * (double)sig_s);
+                        unsafeAtomicAdd(A.tally + 4 * np + q, f2 * (double)sig_s * (double)sig_s);
+                        unsafeAtomicAdd(A.tally + 5 * np + q, f * (double)sig_g);
+                        unsafeAtomicAdd(A.tally + 6 * np + q, f2 * (double)sig_g * (double)sig_g);
+                        unsafeAtomicAdd(A.tally + 7 * np + q, f * (double)sig_a);
+                        unsafeAtomicAdd(A.tally + 8 * np + q, f2 * (double)sig_a * (double)sig_a);
                     }
                 }
                 if (rng.u01() >= A.op.rho) {
@@ -175,7 +177,7 @@ __global__ __launch_bounds__(256) void flux_kernel(FluxArgs A)
                 float nd[3];
                 const float u1 = rng.u01(), u2 = rng.u01();
                 lambert(nd, u1, u2);
-                start_ray(g, ns, r, x, nd, g.L, A.op.mscale, cnt);
+                start_ray(g, ns, r, x, nd, A.op.mscale, cnt);
                 tau = rng.exp1();
                 scattered = true;
             } else {
@@ -233,6 +235,7 @@ hipError_t launch_flux(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     A.glob = glob;
     A.grad = grad;
     A.out = out;
+    A.norm = (s.flags & NC_FLUX_NORMALISE) ? (double)px_nx * (double)px_ny / (double)n_photons : 1.0;
     A.counters = counters;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;

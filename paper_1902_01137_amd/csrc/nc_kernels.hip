@@ -272,7 +272,7 @@ __global__ void trace_leaves_kernel(GridView g, const float *__restrict__ rays, 
     float d[3] = {rays[6 * i + 3], rays[6 * i + 4], rays[6 * i + 5]};
     int k = 0;
     if (ray_setup(g, r, o, d, 0.0f)) {
-        find_leaf(g, ns, r, g.L, 1.0f, reads);
+        find_leaf(g, ns, r, 1.0f, reads);
         for (;;) {
             if (r.texit > r.t) {
                 if (k < maxv) {
@@ -382,12 +382,11 @@ __global__ __launch_bounds__(256) void transmittance_kernel(TransArgs A)
         const float o[3] = {A.rays[6 * i], A.rays[6 * i + 1], A.rays[6 * i + 2]};
         const float d[3] = {A.rays[6 * i + 3], A.rays[6 * i + 4], A.rays[6 * i + 5]};
         double acc = 0.0, acc2 = 0.0;
-        int hint = A.g.L;
         for (int s = s0; s < s1; ++s) {
             Rng rng;
             rng.init((uint32_t)i, (uint32_t)(A.sample_offset + s), 1u, A.seed);
             Ray r;
-            start_ray(A.g, ns, r, o, d, hint, A.mscale, cnt);
+            start_ray(A.g, ns, r, o, d, A.mscale, cnt);
             float T;
             if (A.est == 0) {
                 float tau = rng.exp1();

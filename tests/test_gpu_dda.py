@@ -1,5 +1,8 @@
-"""Ordered crossing of the grid on the GPU (FP32) against the oracle (FP64):
-the voxel sequence of every non-degenerate ray must match exactly."""
+"""Ordered crossing of the grid on the GPU (FP32): against its host twin (the
+same crossing code compiled for the host) bit for bit on every ray,
+degenerate rays included; against the oracle (FP64) on every ray the oracle
+does not flag as degenerate (ties of face crossings within eps, origins on
+faces); every ray's voxels cover its chord once."""
 import numpy as np
 import pytest
 import torch
@@ -8,6 +11,8 @@ import oracle
 from gpu_common import ctx, device_field
 from paper_1902_01137_amd import api, inputs
 from paper_1902_01137_amd.inputs import FieldDesc, GridParams
+from test_twin_dda import covers_chord
+from twin import dda_twin
 
 pytestmark = pytest.mark.gpu
 
@@ -25,6 +30,14 @@ def _check(desc, k, tau, rays, maxv=2048, kg=0.0):
     og = oracle.OracleGrid(desc, k, tau_tilde=tau, k_gas=kg)
     leaf, t, cnt = api.trace_leaves(c, g, torch.from_numpy(rays).cuda(), maxv)
     leaf, t, cnt = leaf.cpu().numpy(), t.cpu().numpy(), cnt.cpu().numpy()
+    # the twin walks the GPU's own grid (its exported levels)
+    levels = [tuple(x.cpu().numpy() for x in g.level(l)) for l in range(1, g.L + 1)]
+    tl, tt, tc = dda_twin.trace(desc, k, levels, rays, maxv)
+    assert np.array_equal(cnt, tc)
+    for i in range(len(rays)):
+        n = min(cnt[i], maxv)
+        assert np.array_equal(leaf[i, :n], tl[i, :n]) and np.array_equal(t[i, :n], tt[i, :n]), i
+        assert covers_chord(desc, rays[i], leaf[i], t[i], n), i
     eps = _eps(desc)
     deg = 0
     for i, r in enumerate(rays):
@@ -44,7 +57,7 @@ def test_blob_random_rays(tau):
     desc, k = inputs.lognormal_blob()
     rays = inputs.random_rays(desc, 3000, seed=31)
     deg = _check(desc, k, tau, rays)
-    assert deg < 0.05 * len(rays)
+    assert deg <= 0.03 * len(rays), deg
 
 
 def test_ragged_grid_rays():
@@ -53,14 +66,14 @@ def test_ragged_grid_rays():
     desc = FieldDesc(37, 21, 13, -1.3, 2.2, 0.4, 0.07, 0.11, 0.05)
     rays = inputs.random_rays(desc, 3000, seed=32)
     deg = _check(desc, k, 0.7, rays, kg=0.01)
-    assert deg < 0.05 * len(rays)
+    assert deg <= 0.03 * len(rays), deg
 
 
 def test_cumulus_rays():
     desc, k = inputs.cumulus_field(fine=(80, 256, 256), pool=2)
     rays = inputs.random_rays(desc, 1500, seed=33)
     deg = _check(desc, k, 1.0, rays, maxv=4096, kg=0.05)
-    assert deg < 0.05 * len(rays)
+    assert deg <= 0.03 * len(rays), deg
 
 
 def test_count_saturates():
