@@ -482,6 +482,24 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, i
                           const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *sampling,
                           double *d_sum, double *d_sumsq, nc_counters *d_counters);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * nc_render_batch without any device allocation.  Its job table, launch
+ * record and work-queue heads live in a fixed array inside the library
+ * (NC_NOALLOC_MAX_JOBS job records, about 124 KB), one copy per GPU, held
+ * until the process ends; its address on a device is resolved when the
+ * first context is created there.  n_jobs above NC_NOALLOC_MAX_JOBS is
+ * NC_ERR_INVALID_ARG.  Every call on a GPU uses that GPU's one array and
+ * rewrites all of it that the launch reads (the queue heads are cleared by
+ * a kernel), so a call never depends on an earlier one, but calls that
+ * overlap in time on one GPU (any context, any stream) race and must not be
+ * made.  Otherwise as nc_render_batch: same arguments, same images. */
+#define NC_NOALLOC_MAX_JOBS 1024
+nc_status nc_render_batch_noalloc(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs,
+                                  const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                                  const nc_sampling *sampling, double *d_sum, double *d_sumsq,
+                                  nc_counters *d_counters);
+
 /* nc_render_batch with guided scattering (nc_render_guided) in every job.
  * The network's inputs do not include the sun, so a guide is trained for one
  * sun: pass the jobs that share it (one launch per sun). */

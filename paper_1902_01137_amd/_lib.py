@@ -73,6 +73,7 @@ N_COUNTER_WORDS = 34
 NC_SUN_DELTA, NC_SUN_RATIO, NC_SUN_RESIDUAL = 0, 1, 2
 NC_FLUX_NORMALISE = 4
 GUIDE_PARAMS = 11944
+NOALLOC_MAX_JOBS = 1024
 GUIDE_RECORD = 12
 
 class Progressive(C.Structure):
@@ -116,6 +117,7 @@ _SIGS = [
                                         C.c_uint64, _P, _P, _P, _P, _P]),
     ("nc_render_batch_guided", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P, _P]),
     ("nc_render_batch", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
+    ("nc_render_batch_noalloc", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_autotune_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
                                        C.POINTER(C.c_double)]),
     ("nc_philox4x32_10", C.c_int32, [_P, _P, _P, _P, C.c_int32]),

@@ -253,6 +253,13 @@ hipError_t ensure_jobs(nc_ctx *ctx, size_t n)
     return e;
 }
 
+// The context's buffers for a render launch (the job table must hold the jobs).
+nc::RenderScratch ctx_render_scratch(const nc_ctx *ctx)
+{
+    return nc::RenderScratch{(nc::JobView *)ctx->d_jobs, ctx->d_scratch + nc::kScratchRare,
+                             ctx->d_scratch + nc::kScratchQueues};
+}
+
 struct DeviceGuard {
     int prev = -1;
     explicit DeviceGuard(int dev)
@@ -296,6 +303,13 @@ nc_status nc_ctx_create(int32_t device, void *hip_stream, nc_ctx **out)
     if (e != hipSuccess) {
         delete ctx;
         return hip_fail(nullptr, e, "hipMalloc(scratch)");
+    }
+    // the no-allocation entry point's scratch: its address on this device, once
+    e = nc::noalloc_init_device(device);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx->d_scratch);
+        delete ctx;
+        return hip_fail(nullptr, e, "no-allocation scratch address");
     }
     *out = ctx;
     return NC_OK;
@@ -533,7 +547,7 @@ static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, co
     hipError_t e = ensure_jobs(ctx, 1);
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), &job, 1, *s, d_sum, d_sumsq,
-                              d_counters, (nc::JobView *)ctx->d_jobs, guide, collect);
+                              d_counters, ctx_render_scratch(ctx), guide, collect);
     if (e == hipSuccess && collect) e = nc::launch_collect_finish(ctx, *collect);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
 }
@@ -738,12 +752,14 @@ nc_status nc_collect_vertices(nc_ctx *ctx, const nc_grid *g, const float *d_kc, 
 static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
                                      const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
                                      const nc_sampling *s, const nc_guide *guide, double *d_sum, double *d_sumsq,
-                                     nc_counters *d_counters)
+                                     nc_counters *d_counters, bool noalloc = false)
 {
     if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
     nc_status st = check_grid(ctx, g);
     if (st != NC_OK) return st;
     if (n_jobs < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative job count");
+    if (noalloc && n_jobs > nc::kNoallocMaxJobs)
+        return fail(ctx, NC_ERR_INVALID_ARG, "nc_render_batch_noalloc takes at most NC_NOALLOC_MAX_JOBS jobs");
     if (!s) return fail(ctx, NC_ERR_INVALID_ARG, "sampling is NULL");
     if (s->spp < 0) return fail(ctx, NC_ERR_INVALID_ARG, "negative spp");
     if (n_jobs == 0 || s->spp == 0) return NC_OK;
@@ -771,10 +787,18 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
     if (guide && !(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
         return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
     DeviceGuard guard(ctx->device);
-    hipError_t e = ensure_jobs(ctx, (size_t)n_jobs);
+    nc::RenderScratch scr;
+    hipError_t e = hipSuccess;
+    if (noalloc) {
+        scr = nc::noalloc_render_scratch(ctx->device);
+        if (!scr.jobs) return fail(ctx, NC_ERR_DEVICE, "no-allocation scratch not set up on this device");
+    } else {
+        e = ensure_jobs(ctx, (size_t)n_jobs);
+        scr = ctx_render_scratch(ctx);
+    }
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), jobs.data(), n_jobs, *s, d_sum,
-                              d_sumsq, d_counters, (nc::JobView *)ctx->d_jobs, guide, nullptr);
+                              d_sumsq, d_counters, scr, guide, nullptr);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render batch");
 }
 
@@ -784,6 +808,14 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int3
 {
     return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, nullptr, d_sum, d_sumsq,
                                d_counters);
+}
+
+nc_status nc_render_batch_noalloc(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
+                                  const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                                  const nc_sampling *s, double *d_sum, double *d_sumsq, nc_counters *d_counters)
+{
+    return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, nullptr, d_sum, d_sumsq,
+                               d_counters, true);
 }
 
 nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,

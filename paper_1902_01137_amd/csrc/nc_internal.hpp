@@ -162,10 +162,28 @@ hipError_t guide_forward(const nc_ctx *ctx, const nc_guide *gd, const float *X, 
 hipError_t guide_train_step(const nc_ctx *ctx, nc_guide *gd, const float *rec, int n, int rec_stride, float lr,
                             double *d_loss, bool apply);
 hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t *key, uint32_t *out, int n);
+// Device memory a render launch writes before it starts: the job table, the
+// launch record (the renderer's rarely used parameters, at most kRareBytes)
+// and the 8 work-queue heads (128 words, 16 apart, zeroed by a kernel at each
+// launch).  Either the context's buffers or the no-allocation scratch.
+constexpr size_t kRareBytes = 256;
+struct RenderScratch {
+    JobView *jobs;
+    unsigned long long *rare;
+    unsigned long long *queue;
+};
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, JobView *jobs_dev, const nc_guide *guide = nullptr,
+                         nc_counters *counters, const RenderScratch &scr, const nc_guide *guide = nullptr,
                          const CollectView *collect = nullptr);
+// The no-allocation scratch (nc_noalloc.hip): a file-scope device array of
+// kNoallocMaxJobs job records plus a launch record and queue heads, one copy
+// per GPU.  noalloc_init_device resolves its address on the current device
+// (once per device, at context creation); noalloc_render_scratch returns the
+// views into it (jobs == nullptr if the device was never initialised).
+constexpr int kNoallocMaxJobs = NC_NOALLOC_MAX_JOBS;
+hipError_t noalloc_init_device(int device);
+RenderScratch noalloc_render_scratch(int device);
 hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv);
 hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const float *in, const float *u, float c,
                                float g, int n, float *out);

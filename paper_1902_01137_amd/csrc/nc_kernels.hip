@@ -1596,7 +1596,8 @@ hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv)
 
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs_host, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, JobView *jobs_dev, const nc_guide *guide, const CollectView *collect)
+                         nc_counters *counters, const RenderScratch &scr, const nc_guide *guide,
+                         const CollectView *collect)
 {
     const int mode = guide ? kGuided : collect ? kCollect : kPlain;
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
@@ -1624,7 +1625,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     }
     rare.sum = sum;
     rare.sumsq = sumsq;
-    rare.jobs = jobs_dev;
+    rare.jobs = scr.jobs;
     rare.n_jobs = n_jobs;
     rare.stream_base = s.stream;
     const unsigned long long blocks = (unsigned long long)((s.spp + rare.spi - 1) / rare.spi);
@@ -1640,14 +1641,14 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     RenderArgs A;
     A.g = grid_view(g, d_kc);
     A.op = op;
-    A.rare = reinterpret_cast<const RenderRare *>(ctx->d_scratch + kScratchRare);
+    A.rare = reinterpret_cast<const RenderRare *>(scr.rare);
     A.key0 = (uint32_t)s.seed;
     A.key1 = (uint32_t)(s.seed >> 32);
     A.sample_base = (uint32_t)s.sample_offset;
     A.stream_base = s.stream;
     A.items = items;
     A.counters = counters;
-    A.queue = ctx->d_scratch + kScratchQueues;
+    A.queue = scr.queue;
     A.q_span = ((items + 8 * kChunk - 1) / (8 * kChunk)) * kChunk;
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
@@ -1661,14 +1662,14 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.col = CollectView{};
     if (guide) A.gw = guide_weights(guide);
     if (collect) A.col = *collect;
-    static_assert(sizeof(RenderRare) <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
+    static_assert(sizeof(RenderRare) <= kRareBytes &&
+                      kRareBytes <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
-    hipError_t e = hipMemcpyAsync(jobs_dev, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
+    hipError_t e = hipMemcpyAsync(scr.jobs, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
                                   ctx->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(ctx->d_scratch + kScratchRare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(scr.rare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(2), dim3(64), 0, ctx->stream, ctx->d_scratch + kScratchQueues, 128);
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(2), dim3(64), 0, ctx->stream, scr.queue, 128);
     if (collect) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, collect->count, 1);
     // register budget: waves per SIMD the kernel is compiled for (3..6)
     // (default 4: the plain kernel fits 128 registers without spilling)
