@@ -100,12 +100,17 @@ def parse():
     p.add_argument("--no-flux", action="store_true", help="skip the forward-photon / adjoint timing (cylinder cumulus)")
     p.add_argument("--no-kdist", action="store_true", help="skip the k-distribution comparison (shared grid vs per point)")
     p.add_argument("--no-guide-kernels", action="store_true", help="skip the network training / inference timing")
+    p.add_argument("--no-time-to-eps", action="store_true", help="skip the measured runs to 3%% per-pixel error")
+    p.add_argument("--eps", type=float, default=0.03, help="target of the measured time-to-error runs")
+    p.add_argument("--spread-renders", type=int, default=4,
+                   help="independent renders whose spread checks the reported standard error")
+    p.add_argument("--cpu-workers", type=int, default=0, help="oracle processes of the all-core baseline (0: host)")
     p.add_argument("--main-only", action="store_true", help="only the timed steps (for profiling runs)")
     a = p.parse_args()
     if a.main_only:
         a.no_cpu_baseline = a.no_batch = a.no_guided = a.no_variants = a.no_refinement = True
         a.no_progressive = a.no_ceiling = a.no_estimators = a.no_tau_sweep = True
-        a.no_flux = a.no_guide_kernels = a.no_kdist = True
+        a.no_flux = a.no_guide_kernels = a.no_kdist = a.no_time_to_eps = True
     return a
 
 
@@ -202,8 +207,6 @@ def main():
     t_1pct = ms_step / 1e3 * (eps / 0.01) ** 2
 
     paths_s = paths_per_step / (ms_step / 1e3)
-    gathers_per_launch = c["gathers"] + c["node_reads"]
-    achieved = gathers_per_launch * GRANULE / (render_ms / 1e3) / 1e9
     out = {
         "metric": METRIC,
         "value": paths_s,
@@ -225,32 +228,26 @@ def main():
         "segments_per_s": c["segments"] / (render_ms / 1e3),
         "tentative_per_s": c["tentative"] / (render_ms / 1e3),
         "per_path": {k: c[k] / max(c["paths"], 1) for k in ("segments", "tentative", "nulls", "reals",
-                                                            "leaf_visits", "gathers", "node_reads", "nee_rays")},
+                                                            "leaf_visits", "deep_visits", "gathers", "node_reads",
+                                                            "nee_rays")},
         "truncated": c["truncated"],
         "sched": {"trips": {k: c["trips_" + k] for k in PHASES},
                   "lanes_per_trip": {k: round(c["lanes_" + k] / max(c["trips_" + k], 1), 2) for k in PHASES},
                   "ticks_per_trip": {k: round(c["ticks_" + k] / max(c["trips_" + k], 1), 1) for k in PHASES}},
         "rel_std_err": eps,
-        "time_to_1pct_s": {"plain": t_1pct, "guided": None},
-        "time_to_1pct_definition": "RMS over pixels of the per-pixel standard error, relative to the mean radiance; "
-                                   "step time x (err / 0.01)^2, plus the guide's collection and training time",
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": measured_traffic() if args.workload == "cumulus" and spp == 64 else None,
-                     "valu_issue_frac": measured_valu_issue(render_ms)
-                     if args.workload == "cumulus" and spp == 64 else None},
     }
+    roof = roofline(c, render_ms, spp == 64 and args.workload == "cumulus")
     gd = None
+    tail = {}
     if not args.no_guided:
-        out["guided"], gd = guided_run(ctx, sc, kc, spp, args, build_ms=ms_step - render_ms)
-        out["time_to_1pct_s"]["guided"] = out["guided"]["time_to_1pct_s"]
+        tail["guided"], gd = guided_run(ctx, sc, kc, spp, args, build_ms=ms_step - render_ms,
+                                        plain={"step_ms": ms_step, "render_ms": render_ms})
         note("guided")
     if not args.no_ceiling:
         out["gather_ceiling"] = gather_ceiling(ctx)
-        out["roofline"]["frac_of_measured_gather_rate"] = achieved / out["gather_ceiling"]["GB_per_s_at_64B"]
         note("gather_ceiling")
     if not args.no_progressive:
-        out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args)
+        out["progressive_block8"] = progressive_run(ctx, sc, kc, gd, args, tail.get("guided"))
         note("progressive")
     if not args.no_estimators:
         out["sun_estimators"] = estimator_run(ctx, sc, kc, spp, build_ms=ms_step - render_ms)
@@ -282,26 +279,73 @@ def main():
         if not args.no_guided:
             out["batch_guided"] = batch_guided_run(ctx, sc, kc, args.batch_spp, args)
             note("batch_guided")
+        ctx.set_launch(args.block, args.waves_per_cu, args.spi, args.lds_levels)   # the single-view shape again
+    if not args.no_time_to_eps:
+        tail["time_to_eps"] = time_to_eps_run(ctx, sc, kc, gd, args, tail.get("guided"))
+        note("time_to_eps")
+    # the headline numbers last (a stored tail of the line keeps them)
+    t1_plain = t_1pct
+    t1_guided = tail["guided"]["time_to_1pct_s"] if "guided" in tail else None
+    tail["time_to_1pct_s"] = {"plain": t1_plain, "guided": t1_guided,
+                              "definition": "extrapolated from one step: RMS over pixels of the per-pixel standard "
+                                            "error relative to the mean radiance, step time x (err / 0.01)^2; "
+                                            "guided: error from the spread of independent renders, plus the "
+                                            "guide's collection and training time; measured runs to 3 %: "
+                                            "time_to_eps"}
+    tail["roofline"] = roof
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds)
+        tail["cpu_baseline"] = cpu_baseline(sc, spp, args.cpu_seconds, args.cpu_workers)
         note("cpu_baseline")
+    out.update(tail)
     print(json.dumps(out))
 
 
+def roofline(c, render_ms, with_record):
+    """Gather-bound HBM roofline of the render kernel.  The method's reads
+    per launch are the field gathers at tentative collisions plus the
+    voxels entered below the LDS-staged grid levels (a node, or for a
+    single-cell voxel the cell, read from memory); each random read moves
+    one 64-byte HBM access granule.  The kernel's own extra reads (the
+    ancestry mask and the cell value it reads at every voxel lookup) are
+    reported beside it, and the measured HBM traffic from the committed
+    counter record when it matches these sources."""
+    t = render_ms / 1e3
+    method = c["gathers"] + c["deep_visits"]
+    achieved = method * GRANULE / t / 1e9
+    impl = c["gathers"] + c["node_reads"]
+    traffic = measured_traffic() if with_record else None
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic,
+            "definition": "(field gathers + voxels entered below the LDS-staged levels) x 64 B / render time",
+            "method_reads_per_path": method / max(c["paths"], 1),
+            "implementation_reads_per_path": impl / max(c["paths"], 1),
+            "implementation_request_GBps_at_64B": impl * GRANULE / t / 1e9,
+            "method_bytes_GBps": (4 * c["gathers"] + 8 * c["deep_visits"] + 16 * c["paths"]) / t / 1e9,
+            "measured_hbm_GBps": traffic / t / 1e9 if traffic else None,
+            "valu_issue_frac": measured_valu_issue(render_ms) if with_record else None}
+
+
 def gather_ceiling(ctx):
-    """Measured random 4-byte read rate over a 2 GiB buffer (larger than the 256 MB last-level cache)."""
+    """Measured random 4-byte read rates (context for the roofline, not its
+    peak): over 2 GiB (beyond the 256 MB last-level cache: HBM) and over
+    128 MiB (held by the last-level cache)."""
     import torch
 
     from paper_1902_01137_amd import api
-    buf = torch.rand(1 << 29, device="cuda")
-    rate = api.gather_rate(ctx, buf, threads=1 << 20, loads=64)
-    del buf
-    torch.cuda.empty_cache()
-    return {"loads_per_s": rate, "GB_per_s_at_64B": rate * GRANULE / 1e9, "buffer_bytes": 1 << 31}
+    out = {}
+    for name, words in (("hbm_2GiB", 1 << 29), ("mall_128MiB", 1 << 25)):
+        buf = torch.rand(words, device="cuda")
+        rate = api.gather_rate(ctx, buf, threads=1 << 20, loads=64)
+        del buf
+        torch.cuda.empty_cache()
+        out[name] = {"loads_per_s": rate, "GB_per_s_at_64B": rate * GRANULE / 1e9, "buffer_bytes": words * 4}
+    return out
 
 
-def progressive_run(ctx, sc, kc, gd, args):
-    """Rounds of samples until the 8x8-block relative standard error is 1 % (plain, then guided)."""
+def progressive_run(ctx, sc, kc, gd, args, guided_info=None):
+    """Rounds of samples until the 8x8-block relative standard error is 1 %
+    (plain, then guided; the guided total adds the guide's collection and
+    training)."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -315,6 +359,38 @@ def progressive_run(ctx, sc, kc, gd, args):
         _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, 0.01, first_spp=16,
                                            max_spp=args.max_spp, block=8, guide=guide)
         torch.cuda.synchronize()
+        if name == "guided" and guided_info:
+            rep["setup_s"] = guided_info["collect_s"] + guided_info["train_s"]
+            rep["total_s"] = rep["seconds"] + rep["setup_s"]
+        else:
+            rep["total_s"] = rep["seconds"]
+        out[name] = rep
+    return out
+
+
+def time_to_eps_run(ctx, sc, kc, gd, args, guided_info=None):
+    """Measured time to a per-pixel relative standard error of args.eps on the
+    full image (RMS over pixels of the standard error relative to the mean):
+    progressive rounds of plain, then guided, rendering; the guided total
+    adds the guide's collection and training."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+    out = {"eps": args.eps, "definition": "per pixel, full resolution; progressive rounds from 64 spp"}
+    for name, guide in (("plain", None), ("guided", gd)):
+        if name == "guided" and guide is None:
+            continue
+        smp = inputs.Sampling(seed=sc.sampling.seed + 37, spp=0, flags=FLAGS, guide_frac=args.guide_frac,
+                              guide_max_order=args.guide_max_order)
+        _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, args.eps, first_spp=64,
+                                           max_spp=1 << 17, block=1, guide=guide)
+        torch.cuda.synchronize()
+        rep["total_s"] = rep["seconds"]
+        if name == "guided" and guided_info:
+            rep["setup_s"] = guided_info["collect_s"] + guided_info["train_s"]
+            rep["total_s"] += rep["setup_s"]
+        rep["to_1pct_extrapolated_s"] = rep["seconds"] * (rep["rel_err"] / 0.01) ** 2 + rep.get("setup_s", 0.0)
         out[name] = rep
     return out
 
@@ -622,11 +698,46 @@ def rel_err(s, s2, spp):
     return float(np.sqrt(np.mean(var / spp)) / np.mean(sm))
 
 
-def guided_run(ctx, sc, kc, spp, args, build_ms):
+def spread_err(runs):
+    """Relative standard error of one render from the spread of K independent
+    renders (RMS over pixels of the per-pixel standard deviation of the
+    renders' means, relative to the mean), and the one the renders report
+    (RMS of their per-pixel standard errors)."""
+    M = np.array([m for m, _ in runs])
+    E2 = np.array([e ** 2 for _, e in runs])
+    mean = M.mean()
+    return float(np.sqrt(M.var(axis=0, ddof=1).mean()) / mean), float(np.sqrt(E2.mean()) / mean)
+
+
+def render_runs(ctx, g, kc, sc, cam, spp, seeds, guide=None, args=None):
+    """Per-pixel (mean, standard error) of independent renders."""
+    import torch
+
+    from paper_1902_01137_amd import api, inputs
+    runs = []
+    for sd in seeds:
+        smp = inputs.Sampling(seed=sd, spp=spp, flags=FLAGS, guide_frac=args.guide_frac if args else 0.5,
+                              guide_max_order=args.guide_max_order if args else 0)
+        if guide is None:
+            s, s2 = api.render(ctx, g, kc, sc.optics, cam, smp)
+        else:
+            s, s2 = api.render_guided(ctx, g, kc, sc.optics, cam, smp, guide)
+        sm = s.cpu().numpy().ravel() / spp
+        var = np.maximum(s2.cpu().numpy().ravel() / spp - sm ** 2, 0) * spp / (spp - 1)
+        runs.append((sm, np.sqrt(var / spp)))
+        del s, s2
+    torch.cuda.synchronize()
+    return runs
+
+
+def guided_run(ctx, sc, kc, spp, args, build_ms, plain):
     """The guided leg: record the scattering vertices of a short plain render,
     fit the guide to them (Adam on random minibatches), then render the same
-    view guided at the same spp.  Time to 1% = collection + training + one
-    guided step (grid build + render) scaled by (err / 0.01)^2."""
+    view guided at the same spp.  The error of a guided step is measured from
+    the spread of independent renders (checked against the standard error
+    they report), and the plain step's likewise.  Time to 1 % = collection +
+    training + one guided step (grid build + render) scaled by
+    (err / 0.01)^2 (an extrapolation; the measured runs are time_to_eps)."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -660,11 +771,14 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     e0.record()
-    s, s2 = api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)
+    api.render_guided(ctx, g, kc, sc.optics, cam, smp, gd)
     e1.record()
     torch.cuda.synchronize()
     render_ms = e0.elapsed_time(e1)
-    eps = rel_err(s, s2, spp)
+    K = max(2, args.spread_renders)
+    g_spread, g_rep = spread_err(render_runs(ctx, g, kc, sc, cam, spp, [sc.sampling.seed + 210 + k for k in range(K)],
+                                             gd, args))
+    p_spread, p_rep = spread_err(render_runs(ctx, g, kc, sc, cam, spp, [sc.sampling.seed + 230 + k for k in range(K)]))
     step_ms = build_ms + render_ms
     collect_s, train_s = t1 - t0, t2 - t1
     paths = cam.width * cam.height * spp
@@ -672,12 +786,19 @@ def guided_run(ctx, sc, kc, spp, args, build_ms):
             "train_batch": args.train_batch, "train_s": train_s,
             "loss": [round((x[0] / x[1]).item(), 4) for x in losses], "guide_frac": args.guide_frac,
             "guide_max_order": args.guide_max_order,
-            "render_ms": render_ms, "paths_per_s": paths / (step_ms / 1e3), "rel_std_err": eps,
-            "time_to_1pct_s": collect_s + train_s + step_ms / 1e3 * (eps / 0.01) ** 2}, gd
+            "render_ms": render_ms, "paths_per_s": paths / (step_ms / 1e3),
+            "spread_renders": K,
+            "rel_std_err_spread": g_spread, "rel_std_err_reported": g_rep,
+            "plain_rel_std_err_spread": p_spread, "plain_rel_std_err_reported": p_rep,
+            "variance_ratio_guided_plain": (g_spread / p_spread) ** 2,
+            "time_to_1pct_s": collect_s + train_s + step_ms / 1e3 * (g_spread / 0.01) ** 2,
+            "plain_time_to_1pct_s_spread": plain["step_ms"] / 1e3 * (p_spread / 0.01) ** 2}, gd
 
 
 def batch_run(ctx, sc, kc, spp):
-    """48 views (256^2 .. 1024^2) x 4 sun zeniths of the same field in one persistent launch."""
+    """48 views (256^2 .. 1024^2) x 4 sun zeniths of the same field in one
+    persistent launch, on the launch shape the autotuner picks for it (tuned
+    at 1 spp; the context keeps the shape for the guided batch that follows)."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -685,18 +806,31 @@ def batch_run(ctx, sc, kc, spp):
     views = inputs.batch_views()
     jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": sz})) for cam, sz in views]
     px = sum(c.width * c.height for c, _ in jobs)
-    smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp, flags=FLAGS)
-    api.render_batch(ctx, g, kc, jobs, smp)                       # warm-up
-    torch.cuda.synchronize()
+    default_launch = ctx.get_launch()
     t0 = time.perf_counter()
-    s, s2, offs = api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp,
-                                                                     flags=FLAGS))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    eps = batch_block_err(s, s2, offs, jobs, spp)
-    return {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "ms": dt * 1e3,
-            "paths_per_s": px * spp / dt, "rel_std_err_block8": eps,
-            "time_to_1pct_block8_s": dt * (eps / 0.01) ** 2}
+    tuned, tuned_ms = api.autotune_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 16, spp=1,
+                                                                           flags=FLAGS))
+    tune_s = time.perf_counter() - t0
+    res = {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "tuned_launch": tuned,
+           "tuned_1spp_ms": tuned_ms, "tune_s": tune_s, "default_launch": default_launch}
+    for name in ("default", "tuned"):
+        ctx.set_launch(**(default_launch if name == "default" else tuned))
+        smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp, flags=FLAGS)
+        api.render_batch(ctx, g, kc, jobs, smp)                       # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, s2, offs = api.render_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 18, spp=spp,
+                                                                         flags=FLAGS))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        if name == "tuned":
+            eps = batch_block_err(s, s2, offs, jobs, spp)
+            res.update({"ms": dt * 1e3, "paths_per_s": px * spp / dt, "rel_std_err_block8": eps,
+                        "time_to_1pct_block8_s": dt * (eps / 0.01) ** 2})
+        else:
+            res["default_ms"] = dt * 1e3
+        del s, s2
+    return res
 
 
 def batch_block_err(s, s2, offs, jobs, spp, b=8):
@@ -721,8 +855,9 @@ def batch_guided_run(ctx, sc, kc, spp, args):
     not see the sun), trained on vertices of 8 of that sun's views spread
     around the ring (every 6th, 5 spp each: the guided paths start from all
     around the cloud, and a network fed from one view alone generalised
-    badly to the others); one guided launch per sun.  Error on 8x8-pixel
-    block means against the plain batch at the same spp."""
+    badly to the others); all 192 jobs in one persistent launch, each
+    workgroup holding one sun's network.  Error on 8x8-pixel block means
+    against the plain batch at the same spp, on the context's launch shape."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -751,51 +886,109 @@ def batch_guided_run(ctx, sc, kc, spp, args):
         del rec
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
-    out = {"train_s": train_s}
+    jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": z})) for cam, z in views]
+    per_job = [guides[z] for _, z in views]
+    out = {"train_s": train_s, "launches": 1, "launch": ctx.get_launch()}
     for name in ("plain", "guided"):
-        t_total, errs, means = 0.0, [], []
-        S_all = []
-        for sz in suns:
-            jobs = [(cam, inputs.Optics(**{**vars(sc.optics), "sun_zenith_deg": z})) for cam, z in views if z == sz]
-            smp = inputs.Sampling(seed=sc.sampling.seed + 311, spp=spp, flags=FLAGS, guide_frac=args.guide_frac,
-                                  guide_max_order=args.guide_max_order)
-            gd = guides[sz] if name == "guided" else None
-            api.render_batch(ctx, g, kc, jobs, smp, guide=gd)                # warm-up
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            s, s2, offs = api.render_batch(ctx, g, kc, jobs, smp, guide=gd)
-            torch.cuda.synchronize()
-            t_total += time.perf_counter() - t1
-            S_all.append((s, s2, offs, jobs))
-        eps = batch_block_err(torch.cat([x[0] for x in S_all]), torch.cat([x[1] for x in S_all]),
-                              [o + sum(x[0].numel() for x in S_all[:k]) for k, x in enumerate(S_all) for o in x[2]],
-                              [j for x in S_all for j in x[3]], spp)
-        out[name] = {"ms": t_total * 1e3, "rel_std_err_block8": eps,
-                     "time_to_1pct_block8_s": t_total * (eps / 0.01) ** 2 + (train_s if name == "guided" else 0.0)}
+        smp = inputs.Sampling(seed=sc.sampling.seed + 311, spp=spp, flags=FLAGS, guide_frac=args.guide_frac,
+                              guide_max_order=args.guide_max_order)
+        gd = per_job if name == "guided" else None
+        api.render_batch(ctx, g, kc, jobs, smp, guide=gd)                # warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s, s2, offs = api.render_batch(ctx, g, kc, jobs, smp, guide=gd)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t1
+        eps = batch_block_err(s, s2, offs, jobs, spp)
+        out[name] = {"ms": dt * 1e3, "rel_std_err_block8": eps,
+                     "time_to_1pct_block8_s": dt * (eps / 0.01) ** 2 + (train_s if name == "guided" else 0.0)}
+        del s, s2
     return out
 
 
-def cpu_baseline(sc, spp, budget_s):
-    """The oracle on a bounded sample of the same workload: pixels spread over
-    the image (a strided subset), all spp samples each, one host core."""
+def _cpu_info():
+    """CPU model, clock and the cores this process may use (from lscpu and the affinity mask)."""
+    import subprocess
+    info = {"model": None, "mhz": None, "max_mhz": None}
+    try:
+        txt = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+        for line in txt.splitlines():
+            k, _, v = line.partition(":")
+            v = v.strip()
+            if k.strip() == "Model name":
+                info["model"] = v
+            elif k.strip() == "CPU MHz":
+                info["mhz"] = float(v)
+            elif k.strip() == "CPU max MHz":
+                info["max_mhz"] = float(v)
+    except (OSError, ValueError, subprocess.SubprocessError):
+        pass
+    try:
+        info["usable_cpus"] = len(os.sched_getaffinity(0))
+    except AttributeError:
+        info["usable_cpus"] = os.cpu_count()
+    return info
+
+
+def _oracle_pixels(job):
+    """One oracle worker: render chunks of its pixel list (all spp) until the
+    time budget is spent; the field comes from a memory-mapped file."""
     import oracle
-    from paper_1902_01137_amd import inputs
-    cam = sc.camera
-    npix = cam.width * cam.height
-    rng = np.random.default_rng(0)
-    order = rng.permutation(npix).astype(np.int32)
-    done, paths, t_used = 0, 0, 0.0
-    chunk = 16
-    while t_used < budget_s and done < npix:
-        px = order[done:done + chunk]
+    desc, path, k_gas, optics, cam, spp, seed, pixels, budget_s = job
+    kc = np.load(path, mmap_mode="r")
+    done, paths, used = 0, 0, 0.0
+    chunk = 8
+    while used < budget_s and done < len(pixels):
+        px = np.ascontiguousarray(pixels[done:done + chunk])
         t0 = time.perf_counter()
-        oracle.render(sc.desc, sc.kc, sc.grid.k_gas, sc.optics, cam, spp, inputs.SEED_ORACLE_BASE + 2, pixels=px)
-        t_used += time.perf_counter() - t0
+        oracle.render(desc, kc, k_gas, optics, cam, spp, seed, pixels=px)
+        used += time.perf_counter() - t0
         done += len(px)
         paths += len(px) * spp
-        chunk = min(chunk * 2, 1024)
-    return {"value": paths / t_used, "unit": "paths/s", "cores": 1, "kind": "oracle",
-            "sample": "%d random pixels x %d spp of the same image (%d paths, %.1f s)" % (done, spp, paths, t_used)}
+        chunk = min(chunk * 2, 256)
+    return paths, used, done
+
+
+def cpu_baseline(sc, spp, budget_s, workers=0):
+    """The oracle on a bounded sample of the same workload (pixels drawn at
+    random over the image, all spp samples each): one host core, then every
+    usable core (independent processes on disjoint pixels, up to 16: the host
+    share of one GPU), with the CPU model and clock."""
+    import multiprocessing as mp
+    import tempfile
+
+    info = _cpu_info()
+    P = workers if workers > 0 else max(1, min(16, info["usable_cpus"] or 1))
+    cam = sc.camera
+    npix = cam.width * cam.height
+    order = np.random.default_rng(0).permutation(npix).astype(np.int32)
+    tmp = tempfile.mkdtemp(prefix="nc_bench_")
+    path = os.path.join(tmp, "kc.npy")
+    np.save(path, sc.kc)
+    seed = 2002
+    try:
+        one = _oracle_pixels((sc.desc, path, sc.grid.k_gas, sc.optics, cam, spp, seed, order[:4096], budget_s))
+        rest = order[4096:]
+        jobs = [(sc.desc, path, sc.grid.k_gas, sc.optics, cam, spp, seed, rest[i::P], budget_s) for i in range(P)]
+        t0 = time.perf_counter()
+        with mp.get_context("spawn").Pool(P) as pool:
+            res = pool.map(_oracle_pixels, jobs)
+        wall = time.perf_counter() - t0
+    finally:
+        try:
+            os.remove(path)
+            os.rmdir(tmp)
+        except OSError:
+            pass
+    paths_all = sum(r[0] for r in res)
+    busy = max(r[1] for r in res)
+    return {"value": paths_all / busy, "unit": "paths/s", "cores": P, "kind": "oracle",
+            "sample": "random pixels x %d spp of the same image: 1 core %d paths in %.1f s; %d processes on "
+                      "disjoint pixels %d paths in %.1f s of rendering (%.1f s wall with start-up)"
+                      % (spp, one[0], one[1], P, paths_all, busy, wall),
+            "single_core_paths_per_s": one[0] / one[1],
+            "cpu_model": info["model"], "cpu_mhz": info["mhz"], "cpu_max_mhz": info["max_mhz"],
+            "usable_cpus": info["usable_cpus"]}
 
 
 if __name__ == "__main__":

@@ -209,7 +209,9 @@ typedef struct {
     uint64_t sched[24];      /* renderer scheduling, per phase (voxel crossing, collision, event, ray
                                 start, sample, guide network): [0..5] wave trips, [6..11] active lanes
                                 summed over the trips, [12..17] wave wall-clock ticks spent in the
-                                phase, [18..23] unused */
+                                phase; [18] voxels entered whose level is not staged in LDS (the
+                                method's grid reads from memory: leaf_visits less those served
+                                from LDS); [19..23] unused */
 } nc_counters;
 
 /* A tabulated phase function (Section 4.1 takes the droplets' phase function
@@ -500,13 +502,20 @@ nc_status nc_render_batch_noalloc(nc_ctx *ctx, const nc_grid *grid, const float 
                                   const nc_sampling *sampling, double *d_sum, double *d_sumsq,
                                   nc_counters *d_counters);
 
-/* nc_render_batch with guided scattering (nc_render_guided) in every job.
- * The network's inputs do not include the sun, so a guide is trained for one
- * sun: pass the jobs that share it (one launch per sun). */
+/* nc_render_batch with guided scattering (nc_render_guided) in every job,
+ * job j guided by guides[j] (host array of n_jobs handles).  The network's
+ * inputs do not include the sun, so a guide is trained for one sun and the
+ * jobs of each sun take theirs, all in one persistent launch.  Jobs that
+ * share a guide must be consecutive, in at most NC_BATCH_MAX_GUIDES runs
+ * (NC_ERR_INVALID_ARG otherwise).  Each run's queue items form their own
+ * work queues; a workgroup holds one run's network in LDS and takes work from
+ * its queues, and once they are drained and its waves are idle it loads the
+ * network of a run that still has work. */
+#define NC_BATCH_MAX_GUIDES 8
 nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs,
                                  const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
-                                 const nc_sampling *sampling, const nc_guide *guide, double *d_sum, double *d_sumsq,
-                                 nc_counters *d_counters);
+                                 const nc_sampling *sampling, const nc_guide *const *guides, double *d_sum,
+                                 double *d_sumsq, nc_counters *d_counters);
 
 /* Launch-shape knobs of the path-tracing kernels (0 = library default). */
 typedef struct {
@@ -527,6 +536,13 @@ nc_status nc_get_launch(const nc_ctx *ctx, nc_launch *launch);
 nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, const nc_optics *optics,
                              const nc_camera *camera, const nc_sampling *sampling, double *d_sum, double *d_sumsq,
                              double *best_ms);
+
+/* The same autotuner on a batched launch (nc_render_batch with these jobs):
+ * d_sum/d_sumsq are scratch buffers of the batch's outputs (overwritten).
+ * The chosen shape stays in the context for the following launches. */
+nc_status nc_autotune_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, int32_t n_jobs,
+                            const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
+                            const nc_sampling *sampling, double *d_sum, double *d_sumsq, double *best_ms);
 
 #ifdef __cplusplus
 }

@@ -68,7 +68,7 @@ class Launch(C.Structure):
 PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
 COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visits", "gathers", "node_reads",
                  "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
-                                              for b in PHASES] + ["sched_pad%d" % i for i in range(6)]
+                                              for b in PHASES] + ["deep_visits"] + ["sched_pad%d" % i for i in range(5)]
 N_COUNTER_WORDS = 34
 NC_SUN_DELTA, NC_SUN_RATIO, NC_SUN_RESIDUAL = 0, 1, 2
 NC_FLUX_NORMALISE = 4
@@ -120,6 +120,8 @@ _SIGS = [
     ("nc_render_batch_noalloc", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_autotune_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P,
                                        C.POINTER(C.c_double)]),
+    ("nc_autotune_batch", C.c_int32, [_P, _P, _P, C.c_int32, _P, _P, _P, C.POINTER(Sampling), _P, _P,
+                                      C.POINTER(C.c_double)]),
     ("nc_philox4x32_10", C.c_int32, [_P, _P, _P, _P, C.c_int32]),
     ("nc_guide_create", C.c_int32, [_P, C.c_uint64, C.POINTER(_P)]),
     ("nc_guide_destroy", None, [_P]),

@@ -394,9 +394,10 @@ class TransmissionFn(torch.autograd.Function):
 
 
 def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, sampling: Sampling,
-                 counters: torch.Tensor | None = None, guide: "Guide | None" = None):
+                 counters: torch.Tensor | None = None, guide=None):
     """Render many (camera, optics) jobs in one persistent launch (nc_render_batch,
-    or nc_render_batch_guided when a guide is given).
+    or nc_render_batch_guided when guides are given: one Guide for every job,
+    or a list with one per job, jobs sharing a guide consecutive).
 
     Returns (sum, sumsq, offsets): flat float64 buffers holding the images one
     after the other, and each image's first element."""
@@ -417,9 +418,14 @@ def render_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, samplin
                                            C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm), _ptr(s),
                                            _ptr(s2), _ptr(counters)), ctx.handle)
     else:
+        per_job = list(guide) if isinstance(guide, (list, tuple)) else [guide] * n
+        if len(per_job) != n:
+            raise ValueError("one guide per job")
+        handles = (C.c_void_p * n)(*[gd.handle for gd in per_job])
         _check(_lib.load().nc_render_batch_guided(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
                                                   C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p), C.byref(sm),
-                                                  guide.handle, _ptr(s), _ptr(s2), _ptr(counters)), ctx.handle)
+                                                  C.cast(handles, C.c_void_p), _ptr(s), _ptr(s2), _ptr(counters)),
+               ctx.handle)
     return s, s2, offs
 
 
@@ -431,6 +437,26 @@ def autotune_render(ctx: Context, grid: Grid, kc: torch.Tensor, optics: Optics, 
     _check(_lib.load().nc_autotune_render(ctx.handle, grid.handle, _ptr(kc), C.byref(_optics(optics, ctx)),
                                           C.byref(_camera(camera)), C.byref(_sampling(sampling)), _ptr(s), _ptr(s2),
                                           C.byref(best)), ctx.handle)
+    return ctx.get_launch(), best.value
+
+
+def autotune_batch(ctx: Context, grid: Grid, kc: torch.Tensor, jobs: list, sampling: Sampling):
+    """Pick the fastest launch shape for this batch (nc_autotune_batch); returns (launch dict, best ms)."""
+    n = len(jobs)
+    cams = (_lib.Camera * n)(*[_camera(c) for c, _ in jobs])
+    recs = [_optics(o, ctx) for _, o in jobs]
+    opts = (_lib.Optics * n)(*recs)
+    offs, total = [], 0
+    for c, _ in jobs:
+        offs.append(total)
+        total += c.width * c.height
+    off_arr = (C.c_uint64 * n)(*offs)
+    s = torch.zeros(max(total, 1), dtype=torch.float64, device=kc.device)
+    s2 = torch.zeros_like(s)
+    best = C.c_double()
+    _check(_lib.load().nc_autotune_batch(ctx.handle, grid.handle, _ptr(kc), n, C.cast(cams, C.c_void_p),
+                                         C.cast(opts, C.c_void_p), C.cast(off_arr, C.c_void_p),
+                                         C.byref(_sampling(sampling)), _ptr(s), _ptr(s2), C.byref(best)), ctx.handle)
     return ctx.get_launch(), best.value
 
 

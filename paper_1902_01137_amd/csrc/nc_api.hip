@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -257,7 +258,7 @@ hipError_t ensure_jobs(nc_ctx *ctx, size_t n)
 nc::RenderScratch ctx_render_scratch(const nc_ctx *ctx)
 {
     return nc::RenderScratch{(nc::JobView *)ctx->d_jobs, ctx->d_scratch + nc::kScratchRare,
-                             ctx->d_scratch + nc::kScratchQueues};
+                             ctx->d_scratch + nc::kScratchQueues, nc::kMaxQueueSets};
 }
 
 struct DeviceGuard {
@@ -547,7 +548,7 @@ static nc_status render_one(nc_ctx *ctx, const nc_grid *g, const float *d_kc, co
     hipError_t e = ensure_jobs(ctx, 1);
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), &job, 1, *s, d_sum, d_sumsq,
-                              d_counters, ctx_render_scratch(ctx), guide, collect);
+                              d_counters, ctx_render_scratch(ctx), guide ? &guide : nullptr, collect);
     if (e == hipSuccess && collect) e = nc::launch_collect_finish(ctx, *collect);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render");
 }
@@ -751,8 +752,8 @@ nc_status nc_collect_vertices(nc_ctx *ctx, const nc_grid *g, const float *d_kc, 
 
 static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
                                      const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
-                                     const nc_sampling *s, const nc_guide *guide, double *d_sum, double *d_sumsq,
-                                     nc_counters *d_counters, bool noalloc = false)
+                                     const nc_sampling *s, const nc_guide *const *guides, double *d_sum,
+                                     double *d_sumsq, nc_counters *d_counters, bool noalloc = false)
 {
     if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
     nc_status st = check_grid(ctx, g);
@@ -783,9 +784,19 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
             return fail(ctx, NC_ERR_RANGE, "an irradiance sensor needs the sun above the horizon");
         jobs[j] = make_job(cam, optics + j, out_offsets[j]);
     }
-    if (guide && guide->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
-    if (guide && !(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
-        return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
+    if (guides) {
+        int runs = 0;
+        for (int j = 0; j < n_jobs; ++j) {
+            if (!guides[j]) return fail(ctx, NC_ERR_INVALID_ARG, "a job's guide is NULL");
+            if (guides[j]->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "guide lives on another device");
+            if (j == 0 || guides[j] != guides[j - 1]) ++runs;
+        }
+        if (runs > NC_BATCH_MAX_GUIDES)
+            return fail(ctx, NC_ERR_INVALID_ARG,
+                        "jobs sharing a guide must be consecutive, in at most NC_BATCH_MAX_GUIDES runs");
+        if (!(s->guide_frac >= 0.0f && s->guide_frac <= 1.0f))
+            return fail(ctx, NC_ERR_INVALID_ARG, "guide_frac must lie in [0, 1]");
+    }
     DeviceGuard guard(ctx->device);
     nc::RenderScratch scr;
     hipError_t e = hipSuccess;
@@ -798,7 +809,7 @@ static nc_status render_batch_common(nc_ctx *ctx, const nc_grid *g, const float 
     }
     if (e == hipSuccess)
         e = nc::launch_render(ctx, g, d_kc, make_opt(optics, g->params.k_gas), jobs.data(), n_jobs, *s, d_sum,
-                              d_sumsq, d_counters, scr, guide, nullptr);
+                              d_sumsq, d_counters, scr, guides, nullptr);
     return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "render batch");
 }
 
@@ -820,11 +831,11 @@ nc_status nc_render_batch_noalloc(nc_ctx *ctx, const nc_grid *g, const float *d_
 
 nc_status nc_render_batch_guided(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs,
                                  const nc_camera *cams, const nc_optics *optics, const uint64_t *out_offsets,
-                                 const nc_sampling *s, const nc_guide *guide, double *d_sum, double *d_sumsq,
-                                 nc_counters *d_counters)
+                                 const nc_sampling *s, const nc_guide *const *guides, double *d_sum,
+                                 double *d_sumsq, nc_counters *d_counters)
 {
-    if (!guide) return fail(ctx, NC_ERR_INVALID_ARG, "guide is NULL");
-    return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, guide, d_sum, d_sumsq,
+    if (!guides && n_jobs > 0) return fail(ctx, NC_ERR_INVALID_ARG, "guides is NULL");
+    return render_batch_common(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, guides, d_sum, d_sumsq,
                                d_counters);
 }
 
@@ -835,13 +846,14 @@ nc_status nc_get_launch(const nc_ctx *ctx, nc_launch *launch)
     return NC_OK;
 }
 
-nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
-                             const nc_camera *camera, const nc_sampling *s, double *d_sum, double *d_sumsq,
-                             double *best_ms)
+// Coordinate descent over the launch knobs (samples per queue item, workgroup
+// size, resident waves per CU, i.e. the register budget, LDS-staged levels),
+// starting from the library defaults; each candidate runs `render` twice on
+// the context's stream (a warm-up, then a run timed with HIP events) after
+// `clear` has zeroed its outputs.  Leaves the fastest knobs in the context.
+static nc_status autotune(nc_ctx *ctx, const std::function<nc_status()> &clear,
+                          const std::function<nc_status()> &render, double *best_ms)
 {
-    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
-    if (!s || s->spp < 1) return fail(ctx, NC_ERR_INVALID_ARG, "autotuning needs spp >= 1");
-    // coordinate descent over the knobs, starting from the library defaults
     const int spis[] = {1, 2, 4, 8, 16};
     const int blocks[] = {64, 128, 256};
     const int waves[] = {12, 16};
@@ -852,19 +864,16 @@ nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     hipError_t he = hipEventCreate(&e0);
     if (he == hipSuccess) he = hipEventCreate(&e1);
     if (he != hipSuccess) return hip_fail(ctx, he, "hipEventCreate");
-    const size_t npix = (size_t)std::max(1, camera ? camera->width : 1) * std::max(1, camera ? camera->height : 1);
     auto time_one = [&](const nc_launch &ln, float &ms) -> nc_status {
         ctx->launch = ln;
-        hipError_t e = hipMemsetAsync(d_sum, 0, npix * sizeof(double), ctx->stream);
-        if (e == hipSuccess) e = hipMemsetAsync(d_sumsq, 0, npix * sizeof(double), ctx->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "autotune clear");
-        nc_status r = nc_render(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, nullptr);   // warm-up
+        nc_status r = clear();
+        if (r == NC_OK) r = render();   // warm-up
         if (r != NC_OK) return r;
         (void)hipEventRecord(e0, ctx->stream);
-        r = nc_render(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, nullptr);
+        r = render();
         if (r != NC_OK) return r;
         (void)hipEventRecord(e1, ctx->stream);
-        e = hipEventSynchronize(e1);
+        hipError_t e = hipEventSynchronize(e1);
         if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
         return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "autotune timing");
     };
@@ -893,6 +902,51 @@ nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, c
     if (st != NC_OK) return st;
     if (best_ms) *best_ms = best;
     return NC_OK;
+}
+
+static nc_status clear_f64(nc_ctx *ctx, double *p, size_t n)
+{
+    const hipError_t e = hipMemsetAsync(p, 0, n * sizeof(double), ctx->stream);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "autotune clear");
+}
+
+nc_status nc_autotune_render(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,
+                             const nc_camera *camera, const nc_sampling *s, double *d_sum, double *d_sumsq,
+                             double *best_ms)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!s || s->spp < 1) return fail(ctx, NC_ERR_INVALID_ARG, "autotuning needs spp >= 1");
+    if (!camera || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    const size_t npix = (size_t)std::max(1, camera->width) * std::max(1, camera->height);
+    return autotune(
+        ctx,
+        [&]() {
+            nc_status r = clear_f64(ctx, d_sum, npix);
+            return r == NC_OK ? clear_f64(ctx, d_sumsq, npix) : r;
+        },
+        [&]() { return nc_render(ctx, g, d_kc, optics, camera, s, d_sum, d_sumsq, nullptr); }, best_ms);
+}
+
+nc_status nc_autotune_batch(nc_ctx *ctx, const nc_grid *g, const float *d_kc, int32_t n_jobs, const nc_camera *cams,
+                            const nc_optics *optics, const uint64_t *out_offsets, const nc_sampling *s, double *d_sum,
+                            double *d_sumsq, double *best_ms)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!s || s->spp < 1) return fail(ctx, NC_ERR_INVALID_ARG, "autotuning needs spp >= 1");
+    if (n_jobs < 1 || !cams || !out_offsets || !d_sum || !d_sumsq) return fail(ctx, NC_ERR_INVALID_ARG, "NULL argument");
+    size_t total = 0;
+    for (int j = 0; j < n_jobs; ++j)
+        total = std::max<size_t>(total, out_offsets[j] + (size_t)std::max(0, cams[j].width) * std::max(0, cams[j].height));
+    return autotune(
+        ctx,
+        [&]() {
+            nc_status r = clear_f64(ctx, d_sum, total);
+            return r == NC_OK ? clear_f64(ctx, d_sumsq, total) : r;
+        },
+        [&]() {
+            return nc_render_batch(ctx, g, d_kc, n_jobs, cams, optics, out_offsets, s, d_sum, d_sumsq, nullptr);
+        },
+        best_ms);
 }
 
 static nc_status flux_common(nc_ctx *ctx, const nc_grid *g, const float *d_kc, const nc_optics *optics,

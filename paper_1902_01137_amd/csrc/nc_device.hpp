@@ -52,6 +52,8 @@ __host__ __device__ inline U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 // loop (and are spilled).  Never call it with a key that differs across lanes.
 __device__ inline U4 philox4x32_10_uk(U4 c, uint32_t k0, uint32_t k1)
 {
+    k0 = __builtin_amdgcn_readfirstlane(k0);   // uniform by contract: scalar registers
+    k1 = __builtin_amdgcn_readfirstlane(k1);
     asm volatile("" : "+s"(k0), "+s"(k1));
     return philox4x32_10(c, k0, k1);
 }

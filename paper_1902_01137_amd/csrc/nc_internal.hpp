@@ -78,10 +78,13 @@ struct nc_guide {
 
 namespace nc {
 
-constexpr int kScratchWords = 384;   // [1] validation flag, [2] cloudy layer, [8..] launch parameters
+constexpr int kMaxQueueSets = NC_BATCH_MAX_GUIDES;   // work-queue sets of one launch (one per guide)
+constexpr int kScratchWords = 256 + 128 * kMaxQueueSets;   // [1] validation flag, [2] cloudy layer, [8..] launch
+                                                           // parameters, [256..] queue heads
 constexpr int kScratchRare = 8;
 constexpr int kScratchErr = 240;     // [240..242] image error accumulators (float64)
-constexpr int kScratchQueues = 256;  // [256 + 16 q] head of work queue q (q < 8), one per 128-byte line
+constexpr int kScratchQueues = 256;  // [256 + 16 (8 set + q)] head of work queue q (q < 8) of a queue set,
+                                     // one per 128-byte line
 
 // Camera, optics and launch records as the kernels see them (FP32).
 struct CamView {
@@ -166,15 +169,16 @@ hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t 
 // launch record (the renderer's rarely used parameters, at most kRareBytes)
 // and the 8 work-queue heads (128 words, 16 apart, zeroed by a kernel at each
 // launch).  Either the context's buffers or the no-allocation scratch.
-constexpr size_t kRareBytes = 256;
+constexpr size_t kRareBytes = 1024;
 struct RenderScratch {
     JobView *jobs;
     unsigned long long *rare;
-    unsigned long long *queue;
+    unsigned long long *queue;   // 128 words per queue set
+    int max_sets;                // queue sets it holds
 };
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, const RenderScratch &scr, const nc_guide *guide = nullptr,
+                         nc_counters *counters, const RenderScratch &scr, const nc_guide *const *guides = nullptr,
                          const CollectView *collect = nullptr);
 // The no-allocation scratch (nc_noalloc.hip): a file-scope device array of
 // kNoallocMaxJobs job records plus a launch record and queue heads, one copy

@@ -497,6 +497,12 @@ struct RenderRare {
     int n_jobs;
     int spp, spi;
     uint32_t stream_base;
+    // guided mode: the queue sets (items of set k: [set_begin[k], set_begin[k + 1]),
+    // 8 per-XCD queues of set_span[k] items) and each set's network
+    unsigned long long set_begin[kMaxQueueSets + 1];
+    unsigned long long set_span[kMaxQueueSets];
+    int set_group[kMaxQueueSets];   // a workgroup starts on the last set k with set_group[k] <= blockIdx / 8
+    GuideWeights gw[kMaxQueueSets];
 };
 
 struct RenderArgs {
@@ -506,7 +512,7 @@ struct RenderArgs {
     uint32_t sample_base;       // sample_offset (fits 32 bits)
     uint32_t stream_base;
     const RenderRare *rare;
-    GuideWeights gw;            // guided mode: the network
+    GuideWeights gw;            // guided mode: the first queue set's network
     float guide_frac;           // guided mode: probability of sampling the guide
     int guide_max_order;        // guided mode: last guided scattering order (0: all)
     CollectView col;            // collection mode: where vertices go
@@ -514,9 +520,10 @@ struct RenderArgs {
     int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
     float gpos[3];              // network position input: (x - lo) * gpos - 1 spans [-1, 1] over the box
     nc_counters *counters;
-    unsigned long long *queue;  // 8 queue heads, 16 words apart
+    unsigned long long *queue;  // 8 queue heads per queue set, 16 words apart
     unsigned long long items;
-    unsigned long long q_span;  // items per queue (a multiple of kChunk)
+    unsigned long long q_span;  // items per queue of the first (plain: only) queue set, a multiple of kChunk
+    int n_sets;                 // guided mode: queue sets (described in the launch record)
     int lds_first, lds_nodes;
 };
 
@@ -540,7 +547,8 @@ __device__ inline int voxel_phase(const Ray &r, float tau)
 // block-level event counters in LDS (same order as nc_counters)
 enum BlockCounter {
     kCPaths = 0, kCSegments, kCTentative, kCNulls, kCReals, kCLeaf, kCGathers, kCReads, kCNee, kCTrunc,
-    kCTrips0, kCLanes0 = kCTrips0 + 6, kCCycles0 = kCLanes0 + 6, kNumBlockCounters = kCCycles0 + 6
+    kCTrips0, kCLanes0 = kCTrips0 + 6, kCCycles0 = kCLanes0 + 6, kCDeep = kCCycles0 + 6,
+    kNumBlockCounters = kCDeep + 1
 };
 
 __device__ inline void wave_count(unsigned long long *s_cnt, int k, bool pred)
@@ -990,10 +998,20 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     extern __shared__ __align__(16) float2 s_nodes[];
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     __shared__ unsigned long long s_cnt[kNumBlockCounters];
+    __shared__ int s_next_set;
     for (int i = threadIdx.x; i < kNumBlockCounters; i += blockDim.x) s_cnt[i] = 0ull;
+    int cur = 0;   // workgroup-uniform: the queue set (and network) this workgroup serves
     if (kMode == kGuided) {
+        const int grp = (int)(blockIdx.x >> 3);
+        for (int k = 1; k < A.n_sets; ++k)
+            if (grp >= A.rare->set_group[k]) cur = k;
         char *gb = reinterpret_cast<char *>(s_nodes) + A.guide_lds;
-        stage_guide(A.gw, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
+        if (cur == 0) {
+            stage_guide(A.gw, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
+        } else {
+            const GuideWeights W = A.rare->gw[cur];
+            stage_guide(W, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
+        }
     }
     stage_levels(A.g, A.lds_first, A.lds_nodes, s_nodes, s_off);   // ends with a block barrier
     const GridView &g = A.g;
@@ -1040,7 +1058,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     bool queue_done = false;
     int q_seen = 0;                      // wave-uniform: queues found drained (its XCD's first)
     int guide_wait = 0;                  // wave-uniform: trips that lanes have waited for the network
+    uint32_t tried = 0;                  // workgroup-uniform: queue sets this workgroup has served
 
+    // the current queue set's items and queues, read where used (the plain
+    // and collection kernels have one set)
+#define NC_SET_LO() (kMode == kGuided && A.n_sets > 1 ? R.set_begin[cur] : 0ull)
+#define NC_SET_HI() (kMode == kGuided && A.n_sets > 1 ? R.set_begin[cur + 1] : A.items)
+#define NC_SET_SPAN() (kMode == kGuided && A.n_sets > 1 ? R.set_span[cur] : A.q_span)
+#define NC_SET_QUEUE() (kMode == kGuided ? A.queue + 128 * cur : A.queue)
+    for (;;) {   // one queue set at a time (a single pass unless guides differ across jobs)
     for (;;) {
         const int n_cross = __popcll(__ballot(phase == kPhCross));
         const int n_coll = __popcll(__ballot(phase == kPhCollide));
@@ -1106,6 +1132,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             wave_count(cnt, kCSegments, active);
             wave_count(cnt, kCLeaf, leaf);
+            wave_count(cnt, kCDeep, leaf && r.lev < A.lds_first);
             wave_count(cnt, kCTrunc, trunc);
         } else if (run == kPhCollide) {
             // ---- tentative collision in the current voxel: real or null
@@ -1330,6 +1357,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             wave_count(cnt, kCNee, active && shadow);
             wave_count(cnt, kCLeaf, hit);
+            wave_count(cnt, kCDeep, hit && r.lev < A.lds_first);
         } else if (kMode == kGuided && run == kPhGuide) {
             // ---- guided scattering: network inference on the matrix cores,
             // then the MIS step in the same layout.  The first `best` waiting
@@ -1419,31 +1447,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const int n_need = __popcll(need);
                 const int rank = (int)lanes_below(need);
                 const int take_new = n_need - chunk_left;
-                unsigned long long nb = A.items;
+                unsigned long long nb = NC_SET_HI();
                 if (take_new > 0 && !queue_done) {
                     const int leader = __ffsll((unsigned long long)need) - 1;
                     if (lane == leader) {
                         // workgroups are dealt to the 8 XCDs in turn (blockIdx mod 8);
-                        // queue q holds the q-th eighth of the items, so each XCD's L2
-                        // serves its own band of the image; a drained queue sends the
+                        // queue q holds the q-th eighth of the set's items, so each XCD's
+                        // L2 serves its own band of the image; a drained queue sends the
                         // wave on to the next one
                         for (;;) {
                             const int q = (int)((blockIdx.x + (unsigned)q_seen) & 7u);
-                            const unsigned long long lo = (unsigned long long)q * A.q_span;
-                            const unsigned long long hi = lo + A.q_span < A.items ? lo + A.q_span : A.items;
-                            const unsigned long long b = lo + atomicAdd(A.queue + 16 * q, (unsigned long long)kChunk);
+                            const unsigned long long lo = NC_SET_LO() + (unsigned long long)q * NC_SET_SPAN();
+                            const unsigned long long hi = lo + NC_SET_SPAN() < NC_SET_HI() ? lo + NC_SET_SPAN() : NC_SET_HI();
+                            const unsigned long long b = lo + atomicAdd(NC_SET_QUEUE() + 16 * q, (unsigned long long)kChunk);
                             if (b < hi) { nb = b; break; }
-                            if (++q_seen == 8) { nb = A.items; break; }
+                            if (++q_seen == 8) { nb = NC_SET_HI(); break; }
                         }
                     }
                     nb = __shfl(nb, leader);
                     q_seen = __shfl(q_seen, leader);
-                    if (nb >= A.items) queue_done = true;
+                    if (nb >= NC_SET_HI()) queue_done = true;
                 }
                 if (need_item) {
                     const unsigned long long w = rank < chunk_left ? chunk_base + (unsigned long long)rank
                                                                    : nb + (unsigned long long)(rank - chunk_left);
-                    if (w >= A.items) {
+                    if (w >= NC_SET_HI()) {
                         phase = kPhIdle;
                     } else {
                         // the job holding item w: last job whose first item is <= w
@@ -1553,6 +1581,48 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         }
         if (stats && lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
     }
+    if (kMode != kGuided || A.n_sets == 1) break;
+    // every lane of this wave is idle: once all waves of the workgroup are, serve
+    // a queue set (network) that still has work, if any
+    tried |= 1u << cur;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int nxt = -1;
+        for (int k = 0; k < A.n_sets && nxt < 0; ++k) {
+            if ((tried >> k) & 1u) continue;
+            const unsigned long long lo = R.set_begin[k], hi = R.set_begin[k + 1], span = R.set_span[k];
+            for (int q = 0; q < 8; ++q) {
+                const unsigned long long qlo = lo + (unsigned long long)q * span;
+                if (qlo >= hi) break;
+                const unsigned long long head =
+                    __hip_atomic_load(A.queue + 128 * k + 16 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                if (qlo + head < hi) { nxt = k; break; }
+            }
+        }
+        s_next_set = nxt;
+    }
+    __syncthreads();
+    const int nxt = __builtin_amdgcn_readfirstlane(s_next_set);   // workgroup-uniform
+    if (nxt < 0) break;
+    cur = nxt;
+    {
+        char *gb = reinterpret_cast<char *>(s_nodes) + A.guide_lds;
+        const GuideWeights W = A.rare->gw[cur];
+        stage_guide(W, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
+    }
+    __syncthreads();
+    phase = kPhSample;
+    have_item = false;
+    traced = false;
+    chunk_left = 0;
+    queue_done = false;
+    q_seen = 0;
+    guide_wait = 0;
+    }   // queue sets
+#undef NC_SET_LO
+#undef NC_SET_HI
+#undef NC_SET_SPAN
+#undef NC_SET_QUEUE
     // per-lane reads, then the block's counters to global memory
     const unsigned long long rsum = wave_sum(reads);
     if (lane == 0) atomicAdd(s_cnt + kCReads, rsum);
@@ -1567,6 +1637,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         unsigned long long *sch = reinterpret_cast<unsigned long long *>(A.counters->sched);
         for (int k = 0; k < 18; ++k)
             if (s_cnt[kCTrips0 + k]) atomicAdd(sch + k, s_cnt[kCTrips0 + k]);
+        if (s_cnt[kCDeep]) atomicAdd(sch + 18, s_cnt[kCDeep]);
     }
 }
 
@@ -1596,10 +1667,10 @@ hipError_t launch_collect_finish(const nc_ctx *ctx, const CollectView &cv)
 
 hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc, const OptView &op,
                          const JobView *jobs_host, int n_jobs, const nc_sampling &s, double *sum, double *sumsq,
-                         nc_counters *counters, const RenderScratch &scr, const nc_guide *guide,
+                         nc_counters *counters, const RenderScratch &scr, const nc_guide *const *guides,
                          const CollectView *collect)
 {
-    const int mode = guide ? kGuided : collect ? kCollect : kPlain;
+    const int mode = guides ? kGuided : collect ? kCollect : kPlain;
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
     const size_t guide_bytes =
         mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
@@ -1638,6 +1709,16 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         jobs[j].item_begin = items;
         items += (unsigned long long)jobs[j].tiles_x * jobs[j].tiles_y * 64ull * blocks;   // < 2^32 per job
     }
+    // queue sets: one per run of consecutive jobs sharing a guide (one set otherwise)
+    int n_sets = 0;
+    int set_first_job[kMaxQueueSets + 1];
+    for (int j = 0; j < n_jobs; ++j) {
+        if (j == 0 || (guides && guides[j] != guides[j - 1])) {
+            if (n_sets == kMaxQueueSets || n_sets >= scr.max_sets) return hipErrorInvalidValue;
+            set_first_job[n_sets++] = j;
+        }
+    }
+    set_first_job[n_sets] = n_jobs;
     RenderArgs A;
     A.g = grid_view(g, d_kc);
     A.op = op;
@@ -1649,7 +1730,15 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.items = items;
     A.counters = counters;
     A.queue = scr.queue;
-    A.q_span = ((items + 8 * kChunk - 1) / (8 * kChunk)) * kChunk;
+    A.n_sets = n_sets;
+    for (int k = 0; k <= n_sets; ++k)
+        rare.set_begin[k] = set_first_job[k] < n_jobs ? jobs[set_first_job[k]].item_begin : items;
+    for (int k = 0; k < n_sets; ++k) {
+        const unsigned long long n = rare.set_begin[k + 1] - rare.set_begin[k];
+        rare.set_span[k] = ((n + 8 * kChunk - 1) / (8 * kChunk)) * kChunk;
+        rare.set_group[k] = 0;
+    }
+    A.q_span = rare.set_span[0];
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
     const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
@@ -1658,19 +1747,15 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.guide_frac = s.guide_frac;
     A.guide_max_order = (int)std::min<uint32_t>(s.guide_max_order, 1u << 30);
     A.col_spp = s.spp;
-    A.gw = GuideWeights{};
+    for (int k = 0; k < kMaxQueueSets; ++k) rare.gw[k] = GuideWeights{};
     A.col = CollectView{};
-    if (guide) A.gw = guide_weights(guide);
+    if (guides)
+        for (int k = 0; k < n_sets; ++k) rare.gw[k] = guide_weights(guides[set_first_job[k]]);
+    A.gw = rare.gw[0];
     if (collect) A.col = *collect;
     static_assert(sizeof(RenderRare) <= kRareBytes &&
                       kRareBytes <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
-    hipError_t e = hipMemcpyAsync(scr.jobs, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
-                                  ctx->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(scr.rare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(2), dim3(64), 0, ctx->stream, scr.queue, 128);
-    if (collect) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, collect->count, 1);
     // register budget: waves per SIMD the kernel is compiled for (3..6)
     // (default 4: the plain kernel fits 128 registers without spilling)
     const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 4;
@@ -1715,6 +1800,24 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         sh.wgs = ctx->num_cus * resident;
     const long long max_wgs = (long long)((items + sh.block - 1) / sh.block);
     const int wgs = (int)std::max<long long>(1, std::min<long long>(max_wgs, sh.wgs));
+    if (n_sets > 1) {
+        // each set's first workgroups: groups of 8 (one per XCD) in proportion
+        // to its items, at least one group each when there are enough
+        const long long groups = std::max<long long>(1, (wgs + 7) / 8);
+        long long acc = 0;
+        for (int k = 0; k < n_sets; ++k) {
+            rare.set_group[k] = (int)std::min<long long>(groups - 1, std::max<long long>(
+                k == 0 ? 0 : rare.set_group[k - 1] + (groups >= n_sets ? 1 : 0),
+                (long long)((double)acc / (double)std::max(items, 1ull) * (double)groups)));
+            acc += rare.set_begin[k + 1] - rare.set_begin[k];
+        }
+    }
+    hipError_t e = hipMemcpyAsync(scr.jobs, jobs.data(), sizeof(JobView) * (size_t)n_jobs, hipMemcpyHostToDevice,
+                                  ctx->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(scr.rare, &rare, sizeof(rare), hipMemcpyHostToDevice, ctx->stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(2 * n_sets), dim3(64), 0, ctx->stream, scr.queue, 128 * n_sets);
+    if (collect) hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(64), 0, ctx->stream, collect->count, 1);
     void *args[] = {&A};
     return hipLaunchKernel(fn, dim3(wgs), dim3(sh.block), args, lds, ctx->stream);
 }

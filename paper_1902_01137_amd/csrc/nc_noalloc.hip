@@ -50,10 +50,10 @@ RenderScratch noalloc_render_scratch(int device)
         std::lock_guard<std::mutex> lock(g_mu);
         base = g_addr[device];
     }
-    if (!base) return RenderScratch{nullptr, nullptr, nullptr};
+    if (!base) return RenderScratch{nullptr, nullptr, nullptr, 0};
     return RenderScratch{reinterpret_cast<JobView *>(base + kJobsOffset),
                          reinterpret_cast<unsigned long long *>(base + kRareOffset),
-                         reinterpret_cast<unsigned long long *>(base)};
+                         reinterpret_cast<unsigned long long *>(base), 1};
 }
 
 }  // namespace nc

@@ -50,3 +50,31 @@ def test_profile_record_is_used_only_for_the_sources_it_was_measured_on(monkeypa
     monkeypatch.setattr(b, "kernel_sources_digest", lambda: "0" * 64)
     assert b.measured_traffic() is None
     assert b.measured_valu_issue(ms) is None
+
+
+def test_roofline_counts_the_methods_reads(monkeypatch):
+    """frac comes from field gathers plus voxels entered below the LDS-staged
+    levels (one 64-byte granule each); the kernel's extra mask and cell reads
+    are reported apart."""
+    b = _bench_module()
+    monkeypatch.setattr(b, "kernel_sources_digest", lambda: "0" * 64)
+    c = {"paths": 1000, "gathers": 800, "deep_visits": 20000, "node_reads": 90000}
+    r = b.roofline(c, 2.0, True)
+    assert r["bound"] == "hbm" and r["peak"] == 8000.0 and r["traffic"] is None
+    assert r["achieved"] == (800 + 20000) * 64 / 2e-3 / 1e9
+    assert r["frac"] == r["achieved"] / 8000.0
+    assert r["method_reads_per_path"] == 20.8 and r["implementation_reads_per_path"] == 90.8
+
+
+def test_spread_error_of_independent_renders():
+    """Renders whose pixel means scatter by exactly their reported standard
+    error give equal spread and reported errors."""
+    import numpy as np
+    b = _bench_module()
+    rng = np.random.default_rng(3)
+    truth = rng.uniform(1.0, 2.0, 4000)
+    se = 0.05 * truth
+    runs = [(truth + se * rng.standard_normal(4000), se) for _ in range(8)]
+    spread, rep = b.spread_err(runs)
+    assert abs(spread / rep - 1.0) < 0.03
+    assert abs(rep - np.sqrt((se ** 2).mean()) / truth.mean()) < 1e-3

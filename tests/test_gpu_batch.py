@@ -138,3 +138,53 @@ def test_guided_batch_equals_single_guided_renders():
         n = cam.width * cam.height
         torch.testing.assert_close(s[offs[j]:offs[j] + n], r.ravel(), rtol=1e-12, atol=1e-12)
         torch.testing.assert_close(s2[offs[j]:offs[j] + n], r2.ravel(), rtol=1e-12, atol=1e-12)
+
+
+def test_guided_batch_with_a_guide_per_run_of_jobs():
+    """Three networks over consecutive runs of jobs in one launch (each
+    workgroup serves one run's queues, then moves to a run with work left):
+    every job equals its single guided render with its own network."""
+    sc, c, kd, g = _scene()
+    jobs = _jobs(sc) * 2
+    guides = [api.Guide(c, seed=s) for s in (9, 10, 11)]
+    per_job = [guides[0]] * 3 + [guides[1]] * 5 + [guides[2]] * 4
+    assert len(per_job) == len(jobs)
+    smp = Sampling(seed=43, spp=6, stream=7, guide_frac=0.5, guide_max_order=0)
+    s, s2, offs = api.render_batch(c, g, kd, jobs, smp, guide=per_job)
+    torch.cuda.synchronize()
+    for j, (cam, op) in enumerate(jobs):
+        one = Sampling(seed=43, spp=6, stream=7 + j, guide_frac=0.5, guide_max_order=0)
+        r, r2 = api.render_guided(c, g, kd, op, cam, one, per_job[j])
+        n = cam.width * cam.height
+        torch.testing.assert_close(s[offs[j]:offs[j] + n], r.ravel(), rtol=1e-12, atol=1e-12)
+        torch.testing.assert_close(s2[offs[j]:offs[j] + n], r2.ravel(), rtol=1e-12, atol=1e-12)
+
+
+def test_guided_batch_guide_runs_are_limited():
+    from paper_1902_01137_amd import _lib
+    sc, c, kd, g = _scene()
+    jobs = _jobs(sc)[:2] * 5                       # 10 jobs
+    a, b = api.Guide(c, seed=1), api.Guide(c, seed=2)
+    with pytest.raises(_lib.NcError) as e:         # 10 alternating runs > NC_BATCH_MAX_GUIDES
+        api.render_batch(c, g, kd, jobs, Sampling(seed=1, spp=1), guide=[a, b] * 5)
+    assert e.value.status == _lib.NC_ERR_INVALID_ARG
+    api.render_batch(c, g, kd, jobs, Sampling(seed=1, spp=1), guide=[a] * 5 + [b] * 5)
+    torch.cuda.synchronize()
+
+
+def test_autotune_batch_keeps_every_image():
+    """nc_autotune_batch leaves a launch shape in the context; the batch
+    rendered on it holds the same images (only the grouping of samples into
+    float32 partial sums per queue item can change)."""
+    sc, c, kd, g = _scene()
+    jobs = _jobs(sc)
+    smp = Sampling(seed=51, spp=8, stream=2)
+    c.set_launch()
+    ref, ref2, _ = api.render_batch(c, g, kd, jobs, smp)
+    launch, ms = api.autotune_batch(c, g, kd, jobs, Sampling(seed=1, spp=2))
+    assert ms > 0 and launch["samples_per_item"] in (1, 2, 4, 8, 16) and launch["block"] in (64, 128, 256)
+    assert c.get_launch() == launch
+    out, out2, _ = api.render_batch(c, g, kd, jobs, smp)
+    torch.testing.assert_close(out, ref, rtol=1e-6, atol=1e-9)
+    torch.testing.assert_close(out2, ref2, rtol=1e-6, atol=1e-9)
+    c.set_launch()
