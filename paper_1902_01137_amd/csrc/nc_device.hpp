@@ -233,23 +233,24 @@ __host__ __device__ inline float face_t(const GridView &g, const Ray &r, int a, 
 __host__ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float o[3], const float d[3], float tmin)
 {
     float tin = tmin, tout = INFINITY;
+    bool miss = false;
+    float tlo[3], thi[3];
+    // per axis, as selects (lanes that disagree would run both sides of a branch)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         r.o[a] = o[a];
         r.d[a] = d[a];
-        if (d[a] == 0.0f) {
-            r.inv[a] = INFINITY;
-            const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
-            if (o[a] < b0 || o[a] > b1) return false;
-        } else {
-            r.inv[a] = 1.0f / d[a];   // correctly rounded (the host twin divides alike)
-            float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
-            if (t0 > t1) { float s = t0; t0 = t1; t1 = s; }
-            tin = fmaxf(tin, t0);
-            tout = fminf(tout, t1);
-        }
+        const bool flat = d[a] == 0.0f;   // parallel to the axis' faces: inside their slab or a miss
+        r.inv[a] = flat ? INFINITY : 1.0f / d[a];   // correctly rounded (the host twin divides alike)
+        const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
+        miss = miss || (flat && (o[a] < b0 || o[a] > b1));
+        const float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
+        tlo[a] = t0 > t1 ? t1 : t0;
+        thi[a] = t0 > t1 ? t0 : t1;
+        tin = flat ? tin : fmaxf(tin, tlo[a]);
+        tout = flat ? tout : fminf(tout, thi[a]);
     }
-    if (!(tin < tout)) return false;
+    if (miss || !(tin < tout)) return false;
     r.t = tin;
     r.tend = tout;
     // starting cell: exact on the axis through whose face the ray enters the
@@ -259,8 +260,9 @@ __host__ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float
     for (int a = 0; a < 3; ++a) {
         int j = (int)floorf((o[a] + tin * d[a] - g.lo[a]) * g.inv_h[a]);
         j = j < 0 ? 0 : (j > g.n[a] - 1 ? g.n[a] - 1 : j);
-        if (d[a] > 0.0f && tin > tmin && face_t(g, r, a, 0) == tin) j = 0;
-        if (d[a] < 0.0f && tin > tmin && face_t(g, r, a, g.n[a]) == tin) j = g.n[a] - 1;
+        const bool entered = tin > tmin && tlo[a] == tin;   // entered through this axis' face
+        j = (entered && d[a] > 0.0f) ? 0 : j;
+        j = (entered && d[a] < 0.0f) ? g.n[a] - 1 : j;
         r.c[a] = j;
     }
     return true;
@@ -308,17 +310,18 @@ __host__ __device__ inline void leaf_exit(const GridView &g, Ray &r)
 {
     const int l = r.lev;
     float te = r.tend;
-    float tf[3] = {INFINITY, INFINITY, INFINITY};
+    float tf[3];
+    // per axis: the face the ray leaves the voxel through, if it lies inside
+    // the field (the box faces are tend); selects, not branches: lanes that
+    // disagree would run both sides anyway
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
         const int i = r.c[a] >> l;
-        if (r.d[a] > 0.0f) {
-            const int e = min((i + 1) << l, g.n[a]);
-            if (e < g.n[a]) tf[a] = face_t(g, r, a, e);
-        } else if (r.d[a] < 0.0f) {
-            const int s = i << l;
-            if (s > 0) tf[a] = face_t(g, r, a, s);
-        }
+        const bool pos = r.d[a] > 0.0f;
+        const int j = pos ? min((i + 1) << l, g.n[a]) : (i << l);
+        const bool inner = pos ? j < g.n[a] : (r.d[a] < 0.0f && j > 0);
+        const float t = face_t(g, r, a, j);
+        tf[a] = inner ? t : INFINITY;
         te = fminf(te, tf[a]);
     }
     r.xmask = (tf[0] == te ? 1 : 0) | (tf[1] == te ? 2 : 0) | (tf[2] == te ? 4 : 0);
@@ -334,15 +337,13 @@ __host__ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, 
     const int l = r.lev;
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (r.d[a] == 0.0f) continue;
         const int vlo = (r.c[a] >> l) << l;
         const int vhi = min(vlo + (1 << l), g.n[a]) - 1;
-        if (r.xmask & (1 << a)) {
-            r.c[a] = r.d[a] > 0.0f ? vhi + 1 : vlo - 1;       // across the exit face
-        } else {
-            int j = (int)floorf((r.o[a] + r.t * r.d[a] - g.lo[a]) * g.inv_h[a]);
-            r.c[a] = j < vlo ? vlo : (j > vhi ? vhi : j);   // still inside the voxel's slab
-        }
+        const int across = r.d[a] > 0.0f ? vhi + 1 : vlo - 1;    // across the exit face
+        int j = (int)floorf((r.o[a] + r.t * r.d[a] - g.lo[a]) * g.inv_h[a]);
+        j = j < vlo ? vlo : (j > vhi ? vhi : j);                  // still inside the voxel's slab
+        const int nc = (r.xmask & (1 << a)) ? across : j;
+        r.c[a] = r.d[a] == 0.0f ? r.c[a] : nc;
     }
     find_leaf(g, ns, r, mscale, node_reads);
     return true;
@@ -354,16 +355,13 @@ __device__ inline size_t collision_cell(const GridView &g, const Ray &r, float t
 {
     const int l = r.lev;
     int cc[3];
+    // (a level-0 voxel clamps to its own cell)
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-        if (l == 0) {
-            cc[a] = r.c[a];
-        } else {
-            const int base = (r.c[a] >> l) << l;
-            const int top = min(base + (1 << l), g.n[a]) - 1;
-            int j = (int)floorf((r.o[a] + t * r.d[a] - g.lo[a]) * g.inv_h[a]);
-            cc[a] = j < base ? base : (j > top ? top : j);
-        }
+        const int base = (r.c[a] >> l) << l;
+        const int top = min(base + (1 << l), g.n[a]) - 1;
+        int j = (int)floorf((r.o[a] + t * r.d[a] - g.lo[a]) * g.inv_h[a]);
+        cc[a] = j < base ? base : (j > top ? top : j);
     }
     const uint32_t row = (uint32_t)cc[2] * (uint32_t)g.n[1] + (uint32_t)cc[1];
     return (size_t)((uint64_t)row * (uint32_t)g.n[0] + (uint32_t)cc[0]);

@@ -1068,12 +1068,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
 #define NC_SET_QUEUE() (kMode == kGuided ? A.queue + 128 * cur : A.queue)
     for (;;) {   // one queue set at a time (a single pass unless guides differ across jobs)
     for (;;) {
-        const int n_cross = __popcll(__ballot(phase == kPhCross));
-        const int n_coll = __popcll(__ballot(phase == kPhCollide));
-        const int n_event = __popcll(__ballot(phase == kPhEvent));
-        const int n_ray = __popcll(__ballot(phase == kPhRay));
-        const int n_sample = __popcll(__ballot(phase == kPhSample));
-        const int n_guide = kMode == kGuided ? __popcll(__ballot(phase == kPhGuide)) : 0;
+        // lane counts per phase (scalar: 32-bit popcounts of the ballots)
+        const int n_cross = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhCross)));
+        const int n_coll = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhCollide)));
+        const int n_event = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhEvent)));
+        const int n_ray = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhRay)));
+        const int n_sample = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhSample)));
+        const int n_guide =
+            kMode == kGuided ? (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhGuide))) : 0;
         const int n_other = n_cross + n_coll + n_event + n_ray + n_sample;
         if (n_other + n_guide == 0) break;
         int run = kPhCross, best = n_cross;
@@ -1132,7 +1134,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             wave_count(cnt, kCSegments, active);
             wave_count(cnt, kCLeaf, leaf);
-            wave_count(cnt, kCDeep, leaf && r.lev < A.lds_first);
+            wave_count(cnt, kCDeep, leaf && r.lev < ns.lds_first);
             wave_count(cnt, kCTrunc, trunc);
         } else if (run == kPhCollide) {
             // ---- tentative collision in the current voxel: real or null
@@ -1357,7 +1359,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             wave_count(cnt, kCNee, active && shadow);
             wave_count(cnt, kCLeaf, hit);
-            wave_count(cnt, kCDeep, hit && r.lev < A.lds_first);
+            wave_count(cnt, kCDeep, hit && r.lev < ns.lds_first);
         } else if (kMode == kGuided && run == kPhGuide) {
             // ---- guided scattering: network inference on the matrix cores,
             // then the MIS step in the same layout.  The first `best` waiting
