@@ -159,8 +159,13 @@ def main():
     cnt = api.new_counters("cuda")
     ev = []
 
+    # the grid's memory is allocated once; every step rebuilds it in place
+    # over the field (as for a field that changes between renders), then renders
+    g_step = api.build_grid(ctx, kc, sc.desc, sc.grid)
+
     def step(i, counters=None):
-        g = api.build_grid(ctx, kc, sc.desc, sc.grid)
+        g = g_step
+        g.rebuild(kc)
         s = torch.zeros((cam.height, cam.width), dtype=torch.float64, device="cuda")
         s2 = torch.zeros_like(s)
         e0 = torch.cuda.Event(enable_timing=True)
@@ -646,11 +651,22 @@ def grid_variants(ctx, sc, kc, spp):
     return res
 
 
+def build_bytes(g):
+    """Bytes a grid build must move at least: the field read once, every
+    level's nodes (8 bytes each) and the level-1 ancestry masks (2 bytes
+    each) written once."""
+    d = g.desc
+    nodes = sum(int(np.prod(g.level_dims(l))) for l in range(1, g.L + 1))
+    return 4 * d.nx * d.ny * d.nz + 8 * nodes + 2 * int(np.prod(g.level_dims(1)))
+
+
 def refinement_sweep(ctx, sc, fine):
     """Grid build time and render rate against the voxel count: the 12.5 m
     field and its 2, 4 and 8 regional averages, tau_tilde = 1 and 0; the
     workload's camera at 512^2, 32 spp; render time is the best of 3 after
-    a warm-up render."""
+    a warm-up render.  build_ms is the in-place rebuild (the build kernels,
+    the field check's read-back and a stream synchronisation), beside the
+    build with its allocation and the bytes a build must move at least."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -670,7 +686,18 @@ def refinement_sweep(ctx, sc, fine):
             for _ in range(reps):
                 g = api.build_grid(ctx, kc, desc, gp)
             torch.cuda.synchronize()
+            alloc_ms = (time.perf_counter() - t0) * 1e3 / reps
+            # the build proper: in place over the same allocation (the
+            # field check's flag read back and the stream synchronised each time)
+            for _ in range(3):
+                g.rebuild(kc)
+            reps = 20
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                g.rebuild(kc)
+            torch.cuda.synchronize()
             build_ms = (time.perf_counter() - t0) * 1e3 / reps
+            nbytes = build_bytes(g)
             # a short warm-up render first (the first pass over a freshly
             # built grid pays for page-table and cache fills), then the best of 3
             api.render(ctx, g, kc, sc.optics, cam, inputs.Sampling(seed=sc.sampling.seed + 50, spp=2, flags=FLAGS))
@@ -684,7 +711,10 @@ def refinement_sweep(ctx, sc, fine):
                 e1.record()
                 torch.cuda.synchronize()
                 ms = min(ms, e0.elapsed_time(e1))
-            row["tau%g" % tau] = {"build_ms": build_ms, "render_ms": ms, "paths_per_s": 512 * 512 * spp / (ms / 1e3)}
+            row["tau%g" % tau] = {"build_ms": build_ms, "build_with_allocation_ms": alloc_ms,
+                                  "build_bytes": nbytes, "build_GBps": nbytes / (build_ms / 1e3) / 1e9,
+                                  "build_frac": nbytes / (build_ms / 1e3) / 1e9 / HBM_PEAK_GBS,
+                                  "render_ms": ms, "paths_per_s": 512 * 512 * spp / (ms / 1e3)}
             del g
         out.append(row)
         del kc

@@ -252,6 +252,13 @@ const char *nc_last_error(const nc_ctx *ctx);
  * d_kc; estimators take the field again and check its shape. */
 nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *desc, const nc_grid_params *params,
                         nc_grid **out);
+/* Rebuild `grid` in place over the field d_kc, which has the shape the grid
+ * was built for (same levels, criterion and parameters; Section 3.1.1): for
+ * a field that changes between renders (a time series, a new extinction
+ * scale) without a new allocation.  Synchronises like nc_grid_build.  On
+ * NC_ERR_RANGE (NaN, Inf or negative extinction) the grid's contents are
+ * unspecified until a rebuild over a valid field succeeds. */
+nc_status nc_grid_rebuild(nc_ctx *ctx, nc_grid *grid, const float *d_kc);
 void nc_grid_destroy(nc_grid *grid);
 /* Number of levels L above the cells, and the node counts of level l. */
 nc_status nc_grid_info(const nc_grid *grid, int32_t *levels, int32_t level, int32_t dims_out[3]);
@@ -260,6 +267,12 @@ nc_status nc_grid_info(const nc_grid *grid, int32_t *levels, int32_t level, int3
  * or inside one).  Any output pointer may be NULL. */
 nc_status nc_grid_export(nc_ctx *ctx, const nc_grid *grid, int32_t level, float *d_kmin, float *d_kmax,
                          uint8_t *d_merged);
+/* The ancestry mask the crossing reads (Section 3.1.3's descent from the
+ * coarsest merged ancestor): one uint16 per level-1 node, [z][y][x] over
+ * level 1's node counts, bit l (1..L) set if the node's level-l ancestor
+ * (itself for l = 1) is merged.  d_mask: device, caller-owned.  A grid with
+ * L = 0 has none (NC_ERR_INVALID_ARG). */
+nc_status nc_grid_export_mask(nc_ctx *ctx, const nc_grid *grid, uint16_t *d_mask);
 /* Per-cell voxel level (uint8 [nz][ny][nx]). */
 nc_status nc_grid_leaf_levels(nc_ctx *ctx, const nc_grid *grid, uint8_t *d_leaf_level);
 

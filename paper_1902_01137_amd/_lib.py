@@ -102,6 +102,8 @@ _SIGS = [
     ("nc_grid_info", C.c_int32, [_P, C.POINTER(C.c_int32), C.c_int32, _P]),
     ("nc_grid_export", C.c_int32, [_P, _P, C.c_int32, _P, _P, _P]),
     ("nc_grid_leaf_levels", C.c_int32, [_P, _P, _P]),
+    ("nc_grid_rebuild", C.c_int32, [_P, _P, _P]),
+    ("nc_grid_export_mask", C.c_int32, [_P, _P, _P]),
     ("nc_trace_leaves", C.c_int32, [_P, _P, _P, C.c_int32, C.c_int32, _P, _P, _P]),
     ("nc_transmittance", C.c_int32, [_P, _P, _P, C.POINTER(Optics), _P, C.c_int32, C.POINTER(Sampling), _P, _P, _P]),
     ("nc_render", C.c_int32, [_P, _P, _P, C.POINTER(Optics), C.POINTER(Camera), C.POINTER(Sampling), _P, _P, _P]),

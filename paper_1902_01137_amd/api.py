@@ -191,6 +191,19 @@ class Grid:
         except Exception:
             pass
 
+    def rebuild(self, kc: torch.Tensor):
+        """Rebuild in place over a field of the same shape."""
+        assert kc.is_cuda and kc.dtype == torch.float32 and kc.is_contiguous()
+        assert tuple(kc.shape) == (self.desc.nz, self.desc.ny, self.desc.nx)
+        _check(_lib.load().nc_grid_rebuild(self.ctx.handle, self.handle, _ptr(kc)), self.ctx.handle)
+
+    def mask(self):
+        """Ancestry mask per level-1 node (int32 view of the uint16 bits)."""
+        nx, ny, nz = self.level_dims(1)
+        m = torch.empty((nz, ny, nx), dtype=torch.int16, device=torch.device("cuda", self.ctx.device))
+        _check(_lib.load().nc_grid_export_mask(self.ctx.handle, self.handle, _ptr(m)), self.ctx.handle)
+        return m.to(torch.int32) & 0xFFFF
+
     def level_dims(self, level):
         d = (C.c_int32 * 3)()
         _check(_lib.load().nc_grid_info(self.handle, None, level, C.cast(d, C.c_void_p)))

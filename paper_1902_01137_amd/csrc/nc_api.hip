@@ -352,6 +352,30 @@ nc_status nc_set_launch(nc_ctx *ctx, const nc_launch *launch)
     return NC_OK;
 }
 
+// Levels, ancestry masks and the field check over d_kc into g's memory;
+// synchronises (reads the check's flag back).
+static nc_status grid_fill(nc_ctx *ctx, nc_grid *g, const float *d_kc)
+{
+    unsigned int *d_bad = reinterpret_cast<unsigned int *>(ctx->d_scratch + 1);
+    unsigned int h_bad = 0;
+    hipError_t e = hipMemcpyAsync(d_bad, &h_bad, sizeof(unsigned int), hipMemcpyHostToDevice, ctx->stream);
+    int *d_zc = reinterpret_cast<int *>(ctx->d_scratch + 2);
+    if (e == hipSuccess) e = nc::launch_build(ctx, g, d_kc, d_bad, d_zc);
+    if (e == hipSuccess && g->L == 0) {
+        // a single cell: validate it on the host
+        float v = 0.0f;
+        e = hipMemcpyAsync(&v, d_kc, sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e == hipSuccess && (!(v >= 0.0f) || std::isinf(v))) h_bad = 1;
+    }
+    if (e == hipSuccess && g->L > 0)
+        e = hipMemcpyAsync(&h_bad, d_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return hip_fail(ctx, e, "grid build");
+    if (h_bad) return fail(ctx, NC_ERR_RANGE, "field holds NaN, Inf or negative extinction");
+    return NC_OK;
+}
+
 nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *desc, const nc_grid_params *params,
                         nc_grid **out)
 {
@@ -414,31 +438,39 @@ nc_status nc_grid_build(nc_ctx *ctx, const float *d_kc, const nc_field_desc *des
         return hip_fail(ctx, e, "hipMalloc(grid)");
     }
     e = hipMemcpyAsync(g->d_off, g->off, sizeof(int) * (NC_MAX_LEVELS + 2), hipMemcpyHostToDevice, ctx->stream);
-    unsigned int *d_bad = reinterpret_cast<unsigned int *>(ctx->d_scratch + 1);
-    unsigned int h_bad = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(d_bad, &h_bad, sizeof(unsigned int), hipMemcpyHostToDevice, ctx->stream);
-    int *d_zc = reinterpret_cast<int *>(ctx->d_scratch + 2);
-    if (e == hipSuccess) e = nc::launch_build(ctx, g, d_kc, d_bad, d_zc);
-    if (e == hipSuccess && L == 0) {
-        // a single cell: validate it on the host
-        float v = 0.0f;
-        e = hipMemcpyAsync(&v, d_kc, sizeof(float), hipMemcpyDeviceToHost, ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
-        if (e == hipSuccess && (!(v >= 0.0f) || std::isinf(v))) h_bad = 1;
-    }
-    if (e == hipSuccess && L > 0)
-        e = hipMemcpyAsync(&h_bad, d_bad, sizeof(unsigned int), hipMemcpyDeviceToHost, ctx->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) {
         nc_grid_destroy(g);
         return hip_fail(ctx, e, "grid build");
     }
-    if (h_bad) {
+    st = grid_fill(ctx, g, d_kc);
+    if (st != NC_OK) {
         nc_grid_destroy(g);
-        return fail(ctx, NC_ERR_RANGE, "field holds NaN, Inf or negative extinction");
+        return st;
     }
     *out = g;
     return NC_OK;
+}
+
+nc_status nc_grid_rebuild(nc_ctx *ctx, nc_grid *grid, const float *d_kc)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!grid) return fail(ctx, NC_ERR_INVALID_ARG, "grid is NULL");
+    if (!d_kc) return fail(ctx, NC_ERR_INVALID_ARG, "field pointer is NULL");
+    if (grid->device != ctx->device) return fail(ctx, NC_ERR_INVALID_ARG, "grid and context are on different devices");
+    DeviceGuard guard(ctx->device);
+    return grid_fill(ctx, grid, d_kc);
+}
+
+nc_status nc_grid_export_mask(nc_ctx *ctx, const nc_grid *grid, uint16_t *d_mask)
+{
+    if (!ctx) return fail(nullptr, NC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!grid) return fail(ctx, NC_ERR_INVALID_ARG, "grid is NULL");
+    if (!d_mask) return fail(ctx, NC_ERR_INVALID_ARG, "mask pointer is NULL");
+    if (grid->L < 1) return fail(ctx, NC_ERR_INVALID_ARG, "a one-cell grid has no level 1");
+    DeviceGuard guard(ctx->device);
+    const size_t n = (size_t)nc::level_dim(grid->n[0], 1) * nc::level_dim(grid->n[1], 1) * nc::level_dim(grid->n[2], 1);
+    const hipError_t e = hipMemcpyAsync(d_mask, grid->d_mask, n * sizeof(uint16_t), hipMemcpyDeviceToDevice, ctx->stream);
+    return e == hipSuccess ? NC_OK : hip_fail(ctx, e, "hipMemcpyAsync(mask)");
 }
 
 void nc_grid_destroy(nc_grid *g)

@@ -68,43 +68,6 @@ __device__ inline float2 encode_node(float kmin, float kmax, bool merged)
     return make_float2(__uint_as_float(b), kmax);
 }
 
-// Level 1 straight from the field: each node reduces its (up to) 2x2x2
-// cells and validates them (finite, >= 0).
-__global__ void build_level1_kernel(const float *__restrict__ kc, int nx, int ny, int nz, float2 *__restrict__ out,
-                                    int d0, int d1, int d2, double k_gas, double dz_node, double tau, int crit,
-                                    LayerRule lr, unsigned int *bad)
-{
-    const long long total = (long long)d0 * d1 * d2;
-    bool flag = false;
-    for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
-         id += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(id % d0);
-        const int j = (int)((id / d0) % d1);
-        const int m = (int)(id / ((long long)d0 * d1));
-        float lo = INFINITY, hi = -INFINITY;
-        for (int dm = 0; dm < 2; ++dm) {
-            const int z = 2 * m + dm;
-            if (z >= nz) break;
-            for (int dj = 0; dj < 2; ++dj) {
-                const int y = 2 * j + dj;
-                if (y >= ny) break;
-                const float *row = kc + ((size_t)z * ny + y) * nx;
-                for (int di = 0; di < 2; ++di) {
-                    const int x = 2 * i + di;
-                    if (x >= nx) break;
-                    const float v = row[x];
-                    if (!(v >= 0.0f) || isinf(v)) flag = true;
-                    lo = fminf(lo, v);
-                    hi = fmaxf(hi, v);
-                }
-            }
-        }
-        out[id] = encode_node(lo, hi, node_merged_rule(lo, hi, k_gas, dz_node, tau, crit, lr, 1, 2 * m,
-                                                       min(2 * m + 2, nz) - 1));
-    }
-    if (flag) atomicOr(bad, 1u);
-}
-
 // Level l >= 2 from level l-1: min and max of the (up to) 8 children.
 __global__ void build_level_kernel(const float2 *__restrict__ child, int c0, int c1, int c2, float2 *__restrict__ out,
                                    int d0, int d1, int d2, double k_gas, double dz_node, double tau, int crit,
@@ -137,26 +100,203 @@ __global__ void build_level_kernel(const float2 *__restrict__ child, int c0, int
     }
 }
 
-// Ancestry mask of every level-1 node: bit l set if its level-l ancestor
-// (l = 1..L) is merged.
-__global__ void build_mask_kernel(const float2 *__restrict__ nodes, const int *__restrict__ off, int n0, int n1,
-                                  int n2, int L, uint16_t *__restrict__ mask)
+// Waves (level-4 nodes along x) per workgroup of the fused pass.
+constexpr int kBuildWaves = 16;
+
+// Merge settings of the levels the fused pass builds (index 1..4).
+struct LevelRules {
+    double dz_node[5];
+    double tau[5];
+    int crit[5];
+};
+
+__device__ inline float2 level_node(float lo, float hi, double k_gas, const LevelRules &R, const LayerRule &lr, int l,
+                                    int m, int nz, bool &merged)
+{
+    merged = node_merged_rule(lo, hi, k_gas, R.dz_node[l], R.tau[l], R.crit[l], lr, l, m << l,
+                              min((m + 1) << l, nz) - 1);
+    return encode_node(lo, hi, merged);
+}
+
+// Levels 1..4 and their bits of the ancestry mask in one pass over the field
+// (the field is read once; each level is written once).  A wave owns one
+// level-4 node (16^3 cells), a lane one level-2 node (4^3 cells, read as 16
+// rows of 4 cells).  The lane reduces its 8 level-1 nodes and its level-2
+// node in registers, level 3 over 8 lanes and level 4 over the wave by lane
+// exchange.  Lane bits 0..2: the level-2 node's octant in its level-3 parent
+// (x, y, z); bits 3..5: that parent's octant in its level-4 parent.  The
+// waves of a workgroup are consecutive level-4 nodes along x, so a workgroup
+// reads 16 kBuildWaves consecutive cells of each row it touches.  Cells
+// outside the field take no part in any reduction; nodes outside their level
+// are not written.  Levels above L are neither written nor set in the mask.  kVec: nx is a multiple of
+// 4, so a row's 4 cells are one 16-byte load and a level-1 node pair (and its
+// mask pair) one store.  Launch: (ceil(d4x / kBuildWaves), d4y, d4z) x
+// 64 kBuildWaves threads.
+template <bool kVec>
+__global__ __launch_bounds__(64 * kBuildWaves) void build_fused_kernel(const float *__restrict__ kc, int nx, int ny, int nz,
+                                                          float2 *__restrict__ nodes, int off1, int off2, int off3,
+                                                          int off4, uint16_t *__restrict__ mask, int L, double k_gas,
+                                                          LevelRules R, LayerRule lr, unsigned int *bad)
+{
+    const int lane = (int)(threadIdx.x & 63u);
+    const int X4 = (int)blockIdx.x * kBuildWaves + (int)(threadIdx.x >> 6);
+    if (X4 >= level_dim(nx, 4)) return;   // wave-uniform, and the kernel has no block barrier
+    const int a2 = 4 * X4 + (lane & 1) + ((lane >> 2) & 2);
+    const int b2 = 4 * (int)blockIdx.y + ((lane >> 1) & 1) + ((lane >> 3) & 2);
+    const int c2 = 4 * (int)blockIdx.z + ((lane >> 2) & 1) + ((lane >> 4) & 2);
+    const int x0 = 4 * a2, y0 = 4 * b2, z0 = 4 * c2;
+    float lo1[8], hi1[8];   // level-1 nodes of the lane, index 4 ez + 2 ey + ex
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        lo1[k] = INFINITY;
+        hi1[k] = -INFINITY;
+    }
+    // all 16 rows are loaded first, unconditionally, from clamped in-bounds
+    // addresses (so they are in flight together); cells outside the field
+    // then take the reductions' identities
+    float v[16][4];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int y = min(y0 + (r & 3), ny - 1), z = min(z0 + (r >> 2), nz - 1);
+        const float *row = kc + ((size_t)z * ny + y) * nx;
+        if (kVec) {
+            const float4 f = *reinterpret_cast<const float4 *>(row + min(x0, nx - 4));
+            v[r][0] = f.x;
+            v[r][1] = f.y;
+            v[r][2] = f.z;
+            v[r][3] = f.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[r][e] = row[min(x0 + e, nx - 1)];
+        }
+    }
+    bool flag = false;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+        const int dy = r & 3, dz = r >> 2;
+        const bool row_in = (y0 + dy < ny) & (z0 + dz < nz);
+        const int k0 = (dz >> 1) * 4 + (dy >> 1) * 2;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const bool in = row_in & (kVec ? x0 < nx : x0 + e < nx);
+            const float c = v[r][e];
+            flag |= in & !((c >= 0.0f) & (c < INFINITY));
+            lo1[k0 + (e >> 1)] = fminf(lo1[k0 + (e >> 1)], in ? c : INFINITY);
+            hi1[k0 + (e >> 1)] = fmaxf(hi1[k0 + (e >> 1)], in ? c : -INFINITY);
+        }
+    }
+    // level 2 (the lane's node), 3 (8 lanes) and 4 (the wave)
+    float lo = lo1[0], hi = hi1[0];
+#pragma unroll
+    for (int k = 1; k < 8; ++k) {
+        lo = fminf(lo, lo1[k]);
+        hi = fmaxf(hi, hi1[k]);
+    }
+    const float lo2 = lo, hi2 = hi;
+#pragma unroll
+    for (int s = 1; s < 8; s <<= 1) {
+        lo = fminf(lo, __shfl_xor(lo, s));
+        hi = fmaxf(hi, __shfl_xor(hi, s));
+    }
+    const float lo3 = lo, hi3 = hi;
+#pragma unroll
+    for (int s = 8; s < 64; s <<= 1) {
+        lo = fminf(lo, __shfl_xor(lo, s));
+        hi = fmaxf(hi, __shfl_xor(hi, s));
+    }
+    const float lo4 = lo, hi4 = hi;
+    const unsigned long long any_bad = __ballot(flag);
+    if (lane == 0 && any_bad) atomicOr(bad, 1u);
+
+    bool mg2 = false, mg3 = false, mg4 = false;
+    const float2 n2 = level_node(lo2, hi2, k_gas, R, lr, 2, c2, nz, mg2);
+    const float2 n3 = level_node(lo3, hi3, k_gas, R, lr, 3, c2 >> 1, nz, mg3);
+    const float2 n4 = level_node(lo4, hi4, k_gas, R, lr, 4, c2 >> 2, nz, mg4);
+    const uint32_t up = (L >= 2 && mg2 ? 4u : 0u) | (L >= 3 && mg3 ? 8u : 0u) | (L >= 4 && mg4 ? 16u : 0u);
+
+    const int d1x = level_dim(nx, 1), d1y = level_dim(ny, 1), d1z = level_dim(nz, 1);
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez) {
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey) {
+            const int i1 = 2 * a2, j1 = 2 * b2 + ey, m1 = 2 * c2 + ez;
+            if (j1 >= d1y || m1 >= d1z || i1 >= d1x) continue;
+            const size_t at = ((size_t)m1 * d1y + j1) * d1x + i1;
+            const int k0 = 4 * ez + 2 * ey;
+            bool g0 = false, g1 = false;
+            const float2 v0 = level_node(lo1[k0], hi1[k0], k_gas, R, lr, 1, m1, nz, g0);
+            const float2 v1 = level_node(lo1[k0 + 1], hi1[k0 + 1], k_gas, R, lr, 1, m1, nz, g1);
+            const uint32_t b0 = up | (g0 ? 2u : 0u), b1 = up | (g1 ? 2u : 0u);
+            if (kVec) {
+                // d1x is even: the pair is whole, 16-byte aligned in the nodes and 4-byte aligned in the mask
+                *reinterpret_cast<float4 *>(nodes + off1 + at) = make_float4(v0.x, v0.y, v1.x, v1.y);
+                *reinterpret_cast<uint32_t *>(mask + at) = b0 | (b1 << 16);
+            } else {
+                nodes[off1 + at] = v0;
+                mask[at] = (uint16_t)b0;
+                if (i1 + 1 < d1x) {
+                    nodes[off1 + at + 1] = v1;
+                    mask[at + 1] = (uint16_t)b1;
+                }
+            }
+        }
+    }
+    if (L >= 2 && a2 < level_dim(nx, 2) && b2 < level_dim(ny, 2) && c2 < level_dim(nz, 2))
+        nodes[off2 + ((size_t)c2 * level_dim(ny, 2) + b2) * level_dim(nx, 2) + a2] = n2;
+    const int a3 = a2 >> 1, b3 = b2 >> 1, c3 = c2 >> 1;
+    if (L >= 3 && (lane & 7) == 0 && a3 < level_dim(nx, 3) && b3 < level_dim(ny, 3) && c3 < level_dim(nz, 3))
+        nodes[off3 + ((size_t)c3 * level_dim(ny, 3) + b3) * level_dim(nx, 3) + a3] = n3;
+    if (L >= 4 && lane == 0 && X4 < level_dim(nx, 4) && (int)blockIdx.y < level_dim(ny, 4) &&
+        (int)blockIdx.z < level_dim(nz, 4))
+        nodes[off4 + ((size_t)blockIdx.z * level_dim(ny, 4) + blockIdx.y) * level_dim(nx, 4) + X4] = n4;
+}
+
+// Mask bits of levels first..L (the levels above the fused pass), OR-ed into
+// every level-1 node's mask.  One thread per run of 8 level-1 nodes along x
+// in 4 consecutive rows (y = 4q .. 4q+3): the runs lie inside one level-4
+// node, so their ancestors from level 4 up are shared, and the 4 rows' loads
+// are in flight together.
+__global__ void mask_upper_kernel(const float2 *__restrict__ nodes, const int *__restrict__ off, int n0, int n1,
+                                  int n2, int L, int first, uint16_t *__restrict__ mask)
 {
     const int d0 = level_dim(n0, 1), d1 = level_dim(n1, 1), d2 = level_dim(n2, 1);
-    const long long total = (long long)d0 * d1 * d2;
+    const int runs = (d0 + 7) >> 3, quads = (d1 + 3) >> 2;
+    const long long total = (long long)runs * quads * d2;
     for (long long id = blockIdx.x * (long long)blockDim.x + threadIdx.x; id < total;
          id += (long long)gridDim.x * blockDim.x) {
-        const int i = (int)(id % d0);
-        const int j = (int)((id / d0) % d1);
-        const int m = (int)(id / ((long long)d0 * d1));
+        const int i = (int)(id % runs) * 8;
+        const int j0 = (int)((id / runs) % quads) * 4;
+        const int m = (int)(id / ((long long)runs * quads));
         uint32_t bits = 0;
-        for (int l = 1; l <= L; ++l) {
+        for (int l = first; l <= L; ++l) {
             const int e0 = level_dim(n0, l), e1 = level_dim(n1, l);
             const int sh = l - 1;
-            const float2 v = nodes[off[l] + ((m >> sh) * e1 + (j >> sh)) * e0 + (i >> sh)];
-            if (node_merged(v)) bits |= 1u << l;
+            if (node_merged(nodes[off[l] + ((m >> sh) * e1 + (j0 >> sh)) * e0 + (i >> sh)])) bits |= 1u << l;
         }
-        mask[id] = (uint16_t)bits;
+        if (!bits) continue;
+        const int nj = min(4, d1 - j0);
+        if ((d0 & 7) == 0) {
+            // 8 masks a row, 16-byte aligned
+            const uint32_t b2 = bits | (bits << 16);
+            uint4 w[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (r < nj) w[r] = *reinterpret_cast<const uint4 *>(mask + ((size_t)m * d1 + j0 + r) * d0 + i);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                if (r >= nj) break;
+                w[r].x |= b2;
+                w[r].y |= b2;
+                w[r].z |= b2;
+                w[r].w |= b2;
+                *reinterpret_cast<uint4 *>(mask + ((size_t)m * d1 + j0 + r) * d0 + i) = w[r];
+            }
+        } else {
+            for (int r = 0; r < nj; ++r) {
+                uint16_t *row = mask + ((size_t)m * d1 + j0 + r) * d0;
+                for (int e = 0; e < 8 && i + e < d0; ++e) row[i + e] = (uint16_t)(row[i + e] | bits);
+            }
+        }
     }
 }
 
@@ -207,38 +347,50 @@ hipError_t launch_build(const nc_ctx *ctx, nc_grid *g, const float *d_kc, unsign
                            cells, g->n[0] * g->n[1], d_zc);
         lr.zc = d_zc;
     }
-    for (int l = 1; l <= g->L; ++l) {
-        const int d0 = level_dim(g->n[0], l), d1 = level_dim(g->n[1], l), d2 = level_dim(g->n[2], l);
-        const long long total = (long long)d0 * d1 * d2;
-        const double dz_node = g->h[2] * (double)(1 << l);
-        // the flat grid merges whole levels: criterion 0 against +inf
-        // (always true for finite k) or 0 (never true)
+    if (g->L < 1) return hipSuccess;
+    // merge settings per level: the flat grid merges whole levels, as
+    // criterion 0 against +inf (always true for finite k) or 0 (never true)
+    auto rule = [&](int l, double &dz_node, double &tau, int &crit) {
         const bool flat = g->params.criterion == 2;
-        const double tau = flat ? (l <= g->params.flat_level ? INFINITY : 0.0) : g->params.tau_tilde;
-        const int crit = flat ? 0 : g->params.criterion;
-        float2 *out = g->d_nodes + g->off[l];
-        if (l == 1) {
-            hipLaunchKernelGGL(build_level1_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream, d_kc,
-                               g->n[0], g->n[1], g->n[2], out, d0, d1, d2, g->params.k_gas, dz_node, tau, crit, lr,
-                               d_bad);
-        } else {
-            const int c0 = level_dim(g->n[0], l - 1), c1 = level_dim(g->n[1], l - 1), c2 = level_dim(g->n[2], l - 1);
-            hipLaunchKernelGGL(build_level_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream,
-                               (const float2 *)(g->d_nodes + g->off[l - 1]), c0, c1, c2, out, d0, d1, d2,
-                               g->params.k_gas, dz_node, tau, crit, lr, l, g->n[2]);
-        }
-        hipError_t e = hipGetLastError();
+        dz_node = g->h[2] * (double)(1 << l);
+        tau = flat ? (l <= g->params.flat_level ? INFINITY : 0.0) : g->params.tau_tilde;
+        crit = flat ? 0 : g->params.criterion;
+    };
+    LevelRules R{};
+    for (int l = 1; l <= 4; ++l) rule(l, R.dz_node[l], R.tau[l], R.crit[l]);
+    const int n0 = g->n[0], n1 = g->n[1], n2 = g->n[2];
+    const dim3 fgrid((level_dim(n0, 4) + kBuildWaves - 1) / kBuildWaves, level_dim(n1, 4), level_dim(n2, 4));
+    const int lvl = std::min(g->L, 4);
+    const int o2 = g->off[std::min(2, lvl)], o3 = g->off[std::min(3, lvl)], o4 = g->off[lvl];
+    if (n0 % 4 == 0 && reinterpret_cast<uintptr_t>(d_kc) % 16 == 0)
+        hipLaunchKernelGGL(build_fused_kernel<true>, fgrid, dim3(64 * kBuildWaves), 0, ctx->stream, d_kc, n0, n1, n2, g->d_nodes,
+                           g->off[1], o2, o3, o4, g->d_mask, g->L, g->params.k_gas, R, lr, d_bad);
+    else
+        hipLaunchKernelGGL(build_fused_kernel<false>, fgrid, dim3(64 * kBuildWaves), 0, ctx->stream, d_kc, n0, n1, n2, g->d_nodes,
+                           g->off[1], o2, o3, o4, g->d_mask, g->L, g->params.k_gas, R, lr, d_bad);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    // the levels above: one launch each from the level below (small)
+    for (int l = 5; l <= g->L; ++l) {
+        const int d0 = level_dim(n0, l), d1 = level_dim(n1, l), d2 = level_dim(n2, l);
+        const int c0 = level_dim(n0, l - 1), c1 = level_dim(n1, l - 1), c2 = level_dim(n2, l - 1);
+        double dz_node = 0.0, tau = 0.0;
+        int crit = 0;
+        rule(l, dz_node, tau, crit);
+        hipLaunchKernelGGL(build_level_kernel, dim3(blocks_for((long long)d0 * d1 * d2, block)), dim3(block), 0,
+                           ctx->stream, (const float2 *)(g->d_nodes + g->off[l - 1]), c0, c1, c2,
+                           g->d_nodes + g->off[l], d0, d1, d2, g->params.k_gas, dz_node, tau, crit, lr, l, n2);
+        e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
-    if (g->L >= 1) {
-        const long long total =
-            (long long)level_dim(g->n[0], 1) * level_dim(g->n[1], 1) * level_dim(g->n[2], 1);
-        hipLaunchKernelGGL(build_mask_kernel, dim3(blocks_for(total, block)), dim3(block), 0, ctx->stream,
-                           (const float2 *)g->d_nodes, (const int *)g->d_off, g->n[0], g->n[1], g->n[2], g->L,
-                           g->d_mask);
-        return hipGetLastError();
+    if (g->L >= 5) {
+        const long long runs =
+            (long long)((level_dim(n0, 1) + 7) / 8) * ((level_dim(n1, 1) + 3) / 4) * level_dim(n2, 1);
+        hipLaunchKernelGGL(mask_upper_kernel, dim3(blocks_for(runs, block)), dim3(block), 0, ctx->stream,
+                           (const float2 *)g->d_nodes, (const int *)g->d_off, n0, n1, n2, g->L, 5, g->d_mask);
+        e = hipGetLastError();
     }
-    return hipSuccess;
+    return e;
 }
 
 hipError_t launch_export(const nc_ctx *ctx, const nc_grid *g, int l, float *kmin, float *kmax, uint8_t *mg)

@@ -28,7 +28,22 @@ def _compare(desc, k, tau, kg=0.0, crit=0, flat=3):
         assert np.array_equal(kmax, okmax), l
         assert np.array_equal(mg, omg), l
     assert np.array_equal(g.leaf_levels().cpu().numpy(), og.leaf_levels())
+    if g.L >= 1:
+        assert np.array_equal(g.mask().cpu().numpy(), _oracle_mask(og))
     return g
+
+
+def _oracle_mask(og):
+    """Ancestry bits per level-1 node from the oracle's merged flags: bit l
+    set if the level-l ancestor (the node itself at l = 1) is merged."""
+    d0, d1, d2 = og.level_dims(1)
+    m, j, i = np.meshgrid(np.arange(d2), np.arange(d1), np.arange(d0), indexing="ij")
+    bits = np.zeros((d2, d1, d0), np.int64)
+    for l in range(1, og.L + 1):
+        mg = og.level(l)[2]
+        sh = l - 1
+        bits |= mg[m >> sh, j >> sh, i >> sh].astype(np.int64) << l
+    return bits
 
 
 @pytest.mark.parametrize("tau", [0.0, 0.5, 1.0, 10.0, math.inf])
@@ -46,6 +61,59 @@ def test_ragged(shape):
     desc = FieldDesc(nx, ny, nz, 0, 0, 0, 0.05, 0.05, 0.05)
     for tau in (0.0, 0.3, 3.0):
         _compare(desc, k, tau, 0.02)
+
+
+def test_row_aligned_and_misaligned_field():
+    """A field whose rows are whole 16-byte groups (nx a multiple of 4), with
+    ragged y and z over several 16^3 blocks: built from an aligned buffer and
+    from one offset by a single float (read cell by cell), both against the
+    oracle."""
+    rng = np.random.default_rng(52)
+    shape = (37, 45, 52)
+    k = (rng.random(shape) ** 8 * 60).astype(np.float32)
+    nz, ny, nx = shape
+    desc = FieldDesc(nx, ny, nz, 0, 0, 0, 0.05, 0.05, 0.05)
+    for tau in (0.0, 0.3, 3.0):
+        _compare(desc, k, tau, 0.02)
+    c = ctx()
+    buf = torch.empty(k.size + 1, dtype=torch.float32, device="cuda")
+    buf[1:] = torch.from_numpy(k.ravel()).cuda()
+    kd = buf[1:].view(shape)
+    assert kd.data_ptr() % 16 == 4
+    g = api.build_grid(c, kd, desc, GridParams(0.3, 0.02, 0, 3))
+    og = oracle.OracleGrid(desc, k, tau_tilde=0.3, k_gas=0.02)
+    for l in range(1, g.L + 1):
+        kmin, kmax, mg = (t.cpu().numpy() for t in g.level(l))
+        assert all(np.array_equal(a, b) for a, b in zip((kmin, kmax, mg), og.level(l))), l
+    assert np.array_equal(g.mask().cpu().numpy(), _oracle_mask(og))
+
+
+def test_rebuild_in_place():
+    """A grid rebuilt over a second field of its shape equals a fresh build
+    over that field (every level and the mask); a rebuild over an invalid
+    field is refused, and a later valid rebuild restores the grid."""
+    desc, k = inputs.lognormal_blob()
+    c = ctx()
+    gp = GridParams(1.0, 0.01, 0, 3)
+    g = api.build_grid(c, device_field(k), desc, gp)
+    k2 = (k * 0.37)[::-1].copy()
+    kd2 = device_field(k2)
+    g.rebuild(kd2)
+    f = api.build_grid(c, kd2, desc, gp)
+    og = oracle.OracleGrid(desc, k2, tau_tilde=1.0, k_gas=0.01)
+    for l in range(1, g.L + 1):
+        a = [t.cpu().numpy() for t in g.level(l)]
+        b = [t.cpu().numpy() for t in f.level(l)]
+        assert all(np.array_equal(x, y) for x, y in zip(a, b)), l
+        assert all(np.array_equal(x, y) for x, y in zip(a, og.level(l))), l
+    assert np.array_equal(g.mask().cpu().numpy(), f.mask().cpu().numpy())
+    bad = k2.copy()
+    bad[3, 4, 5] = np.nan
+    with pytest.raises(_lib.NcError) as e:
+        g.rebuild(device_field(bad))
+    assert e.value.status == _lib.NC_ERR_RANGE
+    g.rebuild(kd2)
+    assert np.array_equal(g.mask().cpu().numpy(), _oracle_mask(og))
 
 
 @pytest.mark.parametrize("flat", [0, 1, 3, 9])
