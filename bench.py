@@ -24,7 +24,7 @@ HBM_PEAK_GBS = 8000.0
 GRANULE = 64  # bytes moved by one random 4- or 8-byte read from HBM
 MI355X_SIMDS = 256 * 4       # compute units x SIMDs per compute unit
 MI355X_CLOCK_HZ = 2.4e9      # peak engine clock
-PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
+PHASES = ("step", "collide", "event", "sample", "guide")   # step: voxel crossings and ray starts
 
 
 def kernel_sources_digest():
@@ -603,11 +603,11 @@ def tau_sweep(ctx, sc, kc):
         api.render(ctx, g, kc, sc.optics, cam, smp, counters=cnt)   # the same paths, with statistics
         torch.cuda.synchronize()
         c = api.counters_dict(cnt)
-        ticks = {k: c["ticks_" + k] for k in ("cross", "collide", "event", "ray", "sample")}
+        ticks = {k: c["ticks_" + k] for k in ("step", "collide", "event", "sample")}
         tot = max(sum(ticks.values()), 1)
         res.append({"tau_tilde": tt if math.isfinite(tt) else "inf", "render_ms": e0.elapsed_time(e1),
                     "leaf_visits_per_path": c["leaf_visits"] / paths, "tentative_per_path": c["tentative"] / paths,
-                    "nulls_per_path": c["nulls"] / paths, "crossing_share": ticks["cross"] / tot,
+                    "nulls_per_path": c["nulls"] / paths, "step_share": ticks["step"] / tot,
                     "collision_share": ticks["collide"] / tot})
         del g
     return res

@@ -206,10 +206,11 @@ typedef struct {
     uint64_t node_reads;     /* grid node reads from global memory */
     uint64_t nee_rays;       /* sun rays traced */
     uint64_t truncated;      /* paths stopped at max_segments */
-    uint64_t sched[24];      /* renderer scheduling, per phase (voxel crossing, collision, event, ray
-                                start, sample, guide network): [0..5] wave trips, [6..11] active lanes
-                                summed over the trips, [12..17] wave wall-clock ticks spent in the
-                                phase; [18] voxels entered whose level is not staged in LDS (the
+    uint64_t sched[24];      /* renderer scheduling, per phase (step = voxel crossings and ray
+                                starts, collision, event, (unused), sample, guide network):
+                                [0..5] wave trips, [6..11] active lanes summed over the trips,
+                                [12..17] wave wall-clock ticks spent in the phase; [18] voxels
+                                entered whose level is not staged in LDS (the
                                 method's grid reads from memory: leaf_visits less those served
                                 from LDS); [19..23] unused */
 } nc_counters;

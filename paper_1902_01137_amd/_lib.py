@@ -65,7 +65,9 @@ class Launch(C.Structure):
                 ("lds_levels", C.c_int32)]
 
 
-PHASES = ("cross", "collide", "event", "ray", "sample", "guide")
+# scheduler slots per phase: "step" = voxel crossings and ray starts (one
+# phase); slot 3 is unused (kept so that the layout of nc_counters holds)
+PHASES = ("step", "collide", "event", "unused", "sample", "guide")
 COUNTER_NAMES = ["paths", "segments", "tentative", "nulls", "reals", "leaf_visits", "gathers", "node_reads",
                  "nee_rays", "truncated"] + ["%s_%s" % (a, b) for a in ("trips", "lanes", "ticks")
                                               for b in PHASES] + ["deep_visits"] + ["sched_pad%d" % i for i in range(5)]

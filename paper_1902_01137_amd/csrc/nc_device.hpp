@@ -271,12 +271,13 @@ __host__ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float
 __host__ __device__ inline void leaf_exit(const GridView &g, Ray &r);
 
 // Voxel of the current cell: its coarsest merged ancestor (the cell itself
-// when no ancestor is merged).  The ancestry mask of the cell's level-1 node
-// gives the level in one read (highest set bit); the cell's own value is
-// read at the same time, so a level-0 voxel costs one round trip to memory
-// and a coarser one at most two (none when its level is staged in LDS).
-__host__ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
-                                          uint32_t &node_reads)
+// when no ancestor is merged), with its majorant and minimum.  The ancestry
+// mask of the cell's level-1 node gives the level in one read (highest set
+// bit); the cell's own value is read at the same time, so a level-0 voxel
+// costs one round trip to memory and a coarser one at most two (none when
+// its level is staged in LDS).
+__host__ __device__ inline void locate_voxel(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
+                                             uint32_t &node_reads)
 {
     float kmin, kmax;
     int l = 0;
@@ -302,6 +303,12 @@ __host__ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, 
     r.lev = l;
     r.khat = mscale * (g.kscale * kmax + g.k_gas);
     r.kmin = kmin;
+}
+
+__host__ __device__ inline void find_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
+                                          uint32_t &node_reads)
+{
+    locate_voxel(g, ns, r, mscale, node_reads);
     leaf_exit(g, r);
 }
 
@@ -319,7 +326,7 @@ __host__ __device__ inline void leaf_exit(const GridView &g, Ray &r)
         const int i = r.c[a] >> l;
         const bool pos = r.d[a] > 0.0f;
         const int j = pos ? min((i + 1) << l, g.n[a]) : (i << l);
-        const bool inner = pos ? j < g.n[a] : (r.d[a] < 0.0f && j > 0);
+        const bool inner = pos ? j < g.n[a] : ((r.d[a] < 0.0f) & (j > 0));
         const float t = face_t(g, r, a, j);
         tf[a] = inner ? t : INFINITY;
         te = fminf(te, tf[a]);
@@ -328,9 +335,10 @@ __host__ __device__ inline void leaf_exit(const GridView &g, Ray &r)
     r.texit = te < r.t ? r.t : te;
 }
 
-// Move to the voxel after the current one; false when the ray leaves the box.
-__host__ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
-                                          uint32_t &node_reads)
+// Cross the current voxel's exit face: the ray moves to its exit parameter
+// and its cell to the first one past the face (false when the ray leaves the
+// box).  The voxel there is not located.
+__host__ __device__ inline bool step_cell(const GridView &g, Ray &r)
 {
     r.t = r.texit;
     if (!(r.t < r.tend)) return false;
@@ -345,6 +353,14 @@ __host__ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, 
         const int nc = (r.xmask & (1 << a)) ? across : j;
         r.c[a] = r.d[a] == 0.0f ? r.c[a] : nc;
     }
+    return true;
+}
+
+// Move to the voxel after the current one; false when the ray leaves the box.
+__host__ __device__ inline bool next_leaf(const GridView &g, const NodeSrc &ns, Ray &r, float mscale,
+                                          uint32_t &node_reads)
+{
+    if (!step_cell(g, r)) return false;
     find_leaf(g, ns, r, mscale, node_reads);
     return true;
 }

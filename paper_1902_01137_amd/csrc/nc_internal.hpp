@@ -169,7 +169,7 @@ hipError_t launch_philox(const nc_ctx *ctx, const uint32_t *ctr, const uint32_t 
 // launch record (the renderer's rarely used parameters, at most kRareBytes)
 // and the 8 work-queue heads (128 words, 16 apart, zeroed by a kernel at each
 // launch).  Either the context's buffers or the no-allocation scratch.
-constexpr size_t kRareBytes = 1024;
+constexpr size_t kRareBytes = 1536;
 struct RenderScratch {
     JobView *jobs;
     unsigned long long *rare;

@@ -639,9 +639,9 @@ __device__ inline unsigned int lanes_below(unsigned long long mask)
     return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// Parameters of the renderer that only the sample phase needs.  They live in
-// device memory and are read with volatile loads when used, so that they do
-// not occupy scalar registers across the whole loop.
+// Parameters of the renderer that only the sample, event and guide phases
+// need (the launch record).  They live in device memory; each workgroup
+// stages the ones its loop reads in LDS.
 struct RenderRare {
     uint64_t seed, sample_offset;
     double *sum, *sumsq;
@@ -653,9 +653,52 @@ struct RenderRare {
     // 8 per-XCD queues of set_span[k] items) and each set's network
     unsigned long long set_begin[kMaxQueueSets + 1];
     unsigned long long set_span[kMaxQueueSets];
+    unsigned long long *queue;      // 8 queue heads per queue set, 16 words apart
     int set_group[kMaxQueueSets];   // a workgroup starts on the last set k with set_group[k] <= blockIdx / 8
     GuideWeights gw[kMaxQueueSets];
+    // the event phase's medium constants (read when an event runs)
+    HGc hg;
+    float ssa;
+    int max_scatter;
 };
+
+// The fields of the launch record that the persistent loop reads, staged in
+// LDS by each workgroup and read there where used (relaxed atomic LDS loads,
+// which the compiler neither hoists out of the loop nor merges): no scalar
+// registers are held for them across the loop.
+struct RareShared {
+    HGc hg;
+    float ssa;
+    int max_scatter;
+    const JobView *jobs;
+    double *sum, *sumsq;
+    unsigned long long *queue;
+    int n_jobs, spi, spp;
+    unsigned long long set_begin[kMaxQueueSets + 1];
+    unsigned long long set_span[kMaxQueueSets];
+};
+
+template <class T>
+__device__ inline T lds_get(const T &x)
+{
+    return __hip_atomic_load(&x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ inline void stage_rare(const RenderRare &R, RareShared &S)
+{
+    S.hg = R.hg;
+    S.ssa = R.ssa;
+    S.max_scatter = R.max_scatter;
+    S.jobs = R.jobs;
+    S.sum = R.sum;
+    S.sumsq = R.sumsq;
+    S.queue = R.queue;
+    S.n_jobs = R.n_jobs;
+    S.spi = R.spi;
+    S.spp = R.spp;
+    for (int k = 0; k <= kMaxQueueSets; ++k) S.set_begin[k] = R.set_begin[k];
+    for (int k = 0; k < kMaxQueueSets; ++k) S.set_span[k] = R.set_span[k];
+}
 
 struct RenderArgs {
     GridView g;
@@ -672,9 +715,6 @@ struct RenderArgs {
     int guide_lds;              // byte offset of the per-wave guide scratch in dynamic LDS
     float gpos[3];              // network position input: (x - lo) * gpos - 1 spans [-1, 1] over the box
     nc_counters *counters;
-    unsigned long long *queue;  // 8 queue heads per queue set, 16 words apart
-    unsigned long long items;
-    unsigned long long q_span;  // items per queue of the first (plain: only) queue set, a multiple of kChunk
     int n_sets;                 // guided mode: queue sets (described in the launch record)
     int lds_first, lds_nodes;
 };
@@ -710,7 +750,7 @@ __device__ inline void wave_count(unsigned long long *s_cnt, int k, bool pred)
     if (m && __lane_id() == 0) atomicAdd(s_cnt + k, (unsigned long long)__popcll(m));
 }
 
-__device__ inline void camera_ray_v(const volatile CamView &c, int px, int py, float u1, float u2, float o[3],
+__device__ inline void camera_ray_v(const CamView &c, int px, int py, float u1, float u2, float o[3],
                                     float d[3])
 {
     const float W = (float)c.W, H = (float)c.H;
@@ -1151,7 +1191,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     __shared__ unsigned long long s_cnt[kNumBlockCounters];
     __shared__ int s_next_set;
+    __shared__ RareShared s_rare;
     for (int i = threadIdx.x; i < kNumBlockCounters; i += blockDim.x) s_cnt[i] = 0ull;
+    if (threadIdx.x == 0) stage_rare(*A.rare, s_rare);   // visible after the barrier in stage_levels
     int cur = 0;   // workgroup-uniform: the queue set (and network) this workgroup serves
     if (kMode == kGuided) {
         const int grp = (int)(blockIdx.x >> 3);
@@ -1169,7 +1211,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     const GridView &g = A.g;
     const NodeSrc ns{g.nodes, s_nodes, s_off, A.lds_first, s_off[A.lds_first <= g.L ? A.lds_first : 0], g.n[0],
                      g.n[1]};
-    const volatile RenderRare &R = *A.rare;
+    // launch-record fields, read from LDS at each use
+#define NC_R(f) lds_get(s_rare.f)
     const int lane = __lane_id();
     // statistics (ballots, LDS atomics, clock reads) only when counters are asked for
     const bool stats = A.counters != nullptr;
@@ -1214,26 +1257,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
 
     // the current queue set's items and queues, read where used (the plain
     // and collection kernels have one set)
-#define NC_SET_LO() (kMode == kGuided && A.n_sets > 1 ? R.set_begin[cur] : 0ull)
-#define NC_SET_HI() (kMode == kGuided && A.n_sets > 1 ? R.set_begin[cur + 1] : A.items)
-#define NC_SET_SPAN() (kMode == kGuided && A.n_sets > 1 ? R.set_span[cur] : A.q_span)
-#define NC_SET_QUEUE() (kMode == kGuided ? A.queue + 128 * cur : A.queue)
+#define NC_SET_LO() NC_R(set_begin[cur])
+#define NC_SET_HI() NC_R(set_begin[cur + 1])
+#define NC_SET_SPAN() NC_R(set_span[cur])
+#define NC_SET_QUEUE() (NC_R(queue) + 128 * cur)
     for (;;) {   // one queue set at a time (a single pass unless guides differ across jobs)
     for (;;) {
-        // lane counts per phase (scalar: 32-bit popcounts of the ballots)
-        const int n_cross = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhCross)));
+        // lane counts per phase (scalar: 32-bit popcounts of the ballots); a
+        // crossing step and a ray start run in the same trip (the step phase)
+        const int n_step = (int)__builtin_amdgcn_readfirstlane(
+            __popcll(__ballot((phase == kPhCross) | (phase == kPhRay))));
         const int n_coll = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhCollide)));
         const int n_event = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhEvent)));
-        const int n_ray = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhRay)));
         const int n_sample = (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhSample)));
         const int n_guide =
             kMode == kGuided ? (int)__builtin_amdgcn_readfirstlane(__popcll(__ballot(phase == kPhGuide))) : 0;
-        const int n_other = n_cross + n_coll + n_event + n_ray + n_sample;
+        const int n_other = n_step + n_coll + n_event + n_sample;
         if (n_other + n_guide == 0) break;
-        int run = kPhCross, best = n_cross;
+        int run = kPhCross, best = n_step;
         if (n_coll >= best) { run = kPhCollide; best = n_coll; }
         if (n_event >= best) { run = kPhEvent; best = n_event; }
-        if (n_ray >= best) { run = kPhRay; best = n_ray; }
         if (n_sample > best) { run = kPhSample; best = n_sample; }
         if (kMode == kGuided && n_guide > 0) {
             // lanes waiting for the network run as full tiles of 16; a partial
@@ -1254,40 +1297,81 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         const long long t_trip = stats ? wall_clock64() : 0;
 
         if (run == kPhCross) {
-            // ---- move to the next voxel, carrying the optical thickness
-            const bool active = phase == kPhCross;
-            bool leaf = false, trunc = false;
-            if (active) {
-                const bool resid = shadow && kSun == 2;
-                if (resid) {
-                    t_sun *= __expf(-(g.kscale * r.kmin + path_kg()) * (r.texit - r.t));
-                    if (t_sun < kSunRoulette) {     // Russian roulette on small estimates
-                        rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
-                                 A.key1);
-                        t_sun = rng.take() * kSunRoulette < t_sun ? kSunRoulette : 0.0f;
-                    }
-                }
+            // ---- a step of the ordered crossing: lanes crossing into the next
+            // voxel (carrying the optical thickness) and lanes starting a ray
+            // (from an event point along pd or towards the sun, or from the
+            // camera) share the location of the voxel (ancestry mask, node)
+            // and its exit face
+            const bool crossing = phase == kPhCross, starting = phase == kPhRay;
+            const bool resid = crossing && shadow && kSun == 2;
+            bool locate = false, known = false, leaf = false, hit = false, trunc = false;
+            if (resid) t_sun *= __expf(-(g.kscale * r.kmin + path_kg()) * (r.texit - r.t));
+            // one random number at most: the Russian roulette of a small residual
+            // estimate, or the optical thickness of a new ray
+            const bool roul = resid && t_sun < kSunRoulette;
+            if (roul || starting)
+                rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
+            if (roul) t_sun = rng.take() * kSunRoulette < t_sun ? kSunRoulette : 0.0f;
+            if (crossing) {
                 tau -= r.khat * (r.texit - r.t);
                 if (resid && t_sun == 0.0f) {
                     res = kReal;                    // the estimate is zero: the sun ray ends here
                     phase = kPhEvent;
-                } else if (!next_leaf(g, ns, r, A.op.mscale, reads)) {
+                } else if (!step_cell(g, r)) {
                     res = kExit;
                     phase = kPhEvent;
                 } else {
-                    leaf = true;
-                    if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
-                    phase = voxel_phase(r, tau);
-                    if (++segs >= A.op.max_segments) {
-                        trunc = true;
-                        phase = kPhSample;      // stop the path
+                    locate = true;
+                }
+            } else if (starting) {
+                const float o[3] = {r.o[0], r.o[1], r.o[2]};
+                const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
+                if (ray_setup(g, r, o, rd, 0.0f)) {
+                    hit = true;
+                    // a ray leaving an event point starts in the event's voxel unless
+                    // rounding put its origin in a neighbouring cell
+                    if ((r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 && (r.c[2] >> vc.lev) == vc.i2) {
+                        r.lev = vc.lev;
+                        r.khat = vc.khat;
+                        r.kmin = vc.kmin;
+                        known = true;
+                    } else {
+                        locate = true;
                     }
+                } else {
+                    // misses the box: the next step finds the ray outside
+                    r.t = r.tend = r.texit = 0.0f;
+                    r.khat = 0.0f;
+                    r.kmin = 0.0f;
+                    r.lev = vc.lev;
                 }
             }
-            wave_count(cnt, kCSegments, active);
-            wave_count(cnt, kCLeaf, leaf);
-            wave_count(cnt, kCDeep, leaf && r.lev < ns.lds_first);
-            wave_count(cnt, kCTrunc, trunc);
+            if (locate) locate_voxel(g, ns, r, A.op.mscale, reads);
+            if (locate || known) leaf_exit(g, r);
+            if (crossing && locate) {
+                leaf = true;
+                if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
+                phase = voxel_phase(r, tau);
+                if (++segs >= A.op.max_segments) {
+                    trunc = true;
+                    phase = kPhSample;      // stop the path
+                }
+            }
+            if (starting) {
+                if (kSun != 0 && shadow) {
+                    t_sun = 1.0f;
+                    if (kSun == 2) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
+                }
+                tau = rng.take_exp1();
+                phase = voxel_phase(r, tau);
+            }
+            if (stats) {
+                wave_count(cnt, kCSegments, crossing);
+                wave_count(cnt, kCLeaf, leaf || hit);
+                wave_count(cnt, kCDeep, (leaf || hit) && r.lev < ns.lds_first);
+                wave_count(cnt, kCTrunc, trunc);
+                wave_count(cnt, kCNee, starting && shadow);
+            }
         } else if (run == kPhCollide) {
             // ---- tentative collision in the current voxel: real or null
             const bool active = phase == kPhCollide;
@@ -1356,14 +1440,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 }
             }
-            wave_count(cnt, kCSegments, active);
-            wave_count(cnt, kCTentative, active);
-            wave_count(cnt, kCReals, real);
-            wave_count(cnt, kCNulls, active && !real);
-            wave_count(cnt, kCGathers, gathered);
-            wave_count(cnt, kCTrunc, trunc);
+            if (stats) {
+                wave_count(cnt, kCSegments, active);
+                wave_count(cnt, kCTentative, active);
+                wave_count(cnt, kCReals, real);
+                wave_count(cnt, kCNulls, active && !real);
+                wave_count(cnt, kCGathers, gathered);
+                wave_count(cnt, kCTrunc, trunc);
+            }
         } else if (run == kPhEvent) {
             if (phase == kPhEvent) {
+                const HGc hg{NC_R(hg.a), NC_R(hg.b), NC_R(hg.c), NC_R(hg.e), NC_R(hg.d), NC_R(hg.r2g)};
+                const int max_scatter = NC_R(max_scatter);
                 // three numbers cover an event (absorption, then two for the new
                 // direction); a guided step takes absorption plus three
                 rng.need(kMode == kGuided ? 4 : 3, (uint32_t)pix, A.sample_base + (uint32_t)s,
@@ -1382,11 +1470,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                     const float kd = g.kscale * kc_hit;
                     kev = kd + path_kg();
-                    const float ssa = A.op.ssa * kd * __builtin_amdgcn_rcpf(kd + path_kg());
+                    const float ssa = NC_R(ssa) * kd * __builtin_amdgcn_rcpf(kd + path_kg());
                     float gain = 1.0f;
                     if (kExt && A.op.cone) {
                         // solar disc: the local estimate's direction drawn in its cone
-                        const volatile JobView &J = R.jobs[job];
+                        const JobView &J = NC_R(jobs)[job];
                         const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
                         const float c1 = rng.take(), c2 = rng.take();
                         float w[3];
@@ -1397,11 +1485,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         gain = A.op.cone_gain;
                     }
                     const float mu = pd[0] * sun[0] + pd[1] * sun[1] + pd[2] * sun[2];
-                    w_nee = ssa * (kExt ? phase_eval(A.op.hg, A.op.tab, mu) : hg_phase(A.op.hg, mu)) * gain;
+                    w_nee = ssa * (kExt ? phase_eval(hg, A.op.tab, mu) : hg_phase(hg, mu)) * gain;
                     p_cont = ssa;
                     ground_ev = false;
                     ++order;
-                    if (A.op.max_scatter >= 0 && order > A.op.max_scatter) {
+                    if (max_scatter >= 0 && order > max_scatter) {
                         phase = kPhSample;
                     } else if (w_nee > 0.0f) {
                         shadow = true;
@@ -1417,10 +1505,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     r.o[0] = r.o[0] + tg * r.d[0];
                     r.o[1] = r.o[1] + tg * r.d[1];
                     r.o[2] = 0.0f;
-                    const float rho = R.jobs[job].rho;
+                    const float rho = NC_R(jobs)[job].rho;
                     float gain = 1.0f;
                     if (kExt && A.op.cone) {
-                        const volatile JobView &J = R.jobs[job];
+                        const JobView &J = NC_R(jobs)[job];
                         const float s0[3] = {J.sun[0], J.sun[1], J.sun[2]};
                         const float c1 = rng.take(), c2 = rng.take();
                         float w[3];
@@ -1436,7 +1524,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     vc.lev = g.L;
                     vc.i0 = -1;                  // outside the field: no voxel to reuse
                     ++order;
-                    if (A.op.max_scatter >= 0 && order > A.op.max_scatter) {
+                    if (max_scatter >= 0 && order > max_scatter) {
                         phase = kPhSample;
                     } else if (w_nee > 0.0f) {
                         shadow = true;
@@ -1447,7 +1535,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 } else {
                     // escaped upward: a camera ray that met nothing may look into the solar disc
                     if (kExt && A.op.cone && order == 0 && !ground_ev) {
-                        const volatile JobView &J = R.jobs[job];
+                        const JobView &J = NC_R(jobs)[job];
                         if (r.d[0] * J.sun[0] + r.d[1] * J.sun[1] + r.d[2] * J.sun[2] >= A.op.cone_cos)
                             Lp += beta * A.op.cone_L;
                     }
@@ -1459,7 +1547,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     if (kExt && A.op.cone)
                         rng.need(kMode == kGuided ? 4 : 3, (uint32_t)pix, A.sample_base + (uint32_t)s,
                                  A.stream_base + (uint32_t)job, A.key0, A.key1);
-                    if (A.op.max_scatter >= 0 && order >= A.op.max_scatter) {
+                    if (max_scatter >= 0 && order >= max_scatter) {
                         phase = kPhSample;
                     } else if (rng.take() >= p_cont) {
                         phase = kPhSample;       // absorbed (volume) or not reflected (ground)
@@ -1472,7 +1560,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         if (ground_ev)
                             lambert(pd, u1, u2);
                         else
-                            turn(pd, kExt ? phase_sample_mu(A.op.hg, A.op.tab, u1) : hg_sample_mu(A.op.hg, u1), u2);
+                            turn(pd, kExt ? phase_sample_mu(hg, A.op.tab, u1) : hg_sample_mu(hg, u1), u2);
                         phase = kPhRay;
                         if (kMode == kCollect && !ground_ev) {
                             // training record: vertex, incoming and outgoing directions, radiance so far
@@ -1493,25 +1581,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     }
                 }
             }
-        } else if (run == kPhRay) {
-            // ---- start the next ray at r.o along pd (path) or towards the sun
-            const bool active = phase == kPhRay;
-            bool hit = false;
-            if (active) {
-                const float o[3] = {r.o[0], r.o[1], r.o[2]};
-                const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
-                hit = start_ray_cached_r(g, ns, r, o, rd, vc, A.op.mscale, reads);
-                if (kSun != 0 && shadow) {
-                    t_sun = 1.0f;
-                    if (kSun == 2) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
-                }
-                rng.need(1, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0, A.key1);
-                tau = rng.take_exp1();
-                phase = voxel_phase(r, tau);
-            }
-            wave_count(cnt, kCNee, active && shadow);
-            wave_count(cnt, kCLeaf, hit);
-            wave_count(cnt, kCDeep, hit && r.lev < ns.lds_first);
         } else if (kMode == kGuided && run == kPhGuide) {
             // ---- guided scattering: network inference on the matrix cores,
             // then the MIS step in the same layout.  The first `best` waiting
@@ -1554,7 +1623,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 wave_sync();
                 float z[12];
                 guide_tile_forward(wl, bl, tin, lane, z);
-                const GuidedStep st = guided_turn_tile<kExt>(z, tf + col * 8, A.guide_frac, A.op.hg, A.op.tab, kq);
+                const GuidedStep st = guided_turn_tile<kExt>(z, tf + col * 8, A.guide_frac,
+                                                                HGc{NC_R(hg.a), NC_R(hg.b), NC_R(hg.c), NC_R(hg.e),
+                                                                    NC_R(hg.d), NC_R(hg.r2g)},
+                                                                A.op.tab, kq);
                 // each owner takes its column's result
                 const int src = owner ? row : lane;
                 const float d0 = __shfl(st.d[0], src), d1 = __shfl(st.d[1], src), d2 = __shfl(st.d[2], src);
@@ -1580,10 +1652,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         ++s;
                     }
                     if (s >= s_end) {
-                        const unsigned long long q = R.jobs[job].out_off + (unsigned long long)pix;
-                        const double S = (double)R.jobs[job].S;   // radiances are in units of the sun irradiance
-                        unsafeAtomicAdd(R.sum + q, S * (double)acc);
-                        unsafeAtomicAdd(R.sumsq + q, S * S * (double)acc2);
+                        const unsigned long long q = NC_R(jobs)[job].out_off + (unsigned long long)pix;
+                        const double S = (double)NC_R(jobs)[job].S;   // radiances are in units of the sun irradiance
+                        unsafeAtomicAdd(NC_R(sum) + q, S * (double)acc);
+                        unsafeAtomicAdd(NC_R(sumsq) + q, S * S * (double)acc2);
                         have_item = false;
                         need_item = true;
                     }
@@ -1592,7 +1664,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 }
             }
             const bool finished = phase == kPhSample && traced;
-            wave_count(cnt, kCPaths, finished);
+            if (stats) wave_count(cnt, kCPaths, finished);
             if (phase == kPhSample) traced = false;   // only lanes in this phase: others are mid-path
             // queue refill in uniform control flow: ballot + prefix count over
             // the wave's chunk, one global atomic per kChunk items
@@ -1629,17 +1701,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         phase = kPhIdle;
                     } else {
                         // the job holding item w: last job whose first item is <= w
-                        int lo = 0, hi = R.n_jobs - 1;
+                        int lo = 0, hi = NC_R(n_jobs) - 1;
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
-                            if (R.jobs[mid].item_begin <= w)
+                            if (NC_R(jobs)[mid].item_begin <= w)
                                 lo = mid;
                             else
                                 hi = mid - 1;
                         }
                         job = lo;
-                        const volatile JobView &J = R.jobs[job];
-                        const int tx = J.tiles_x, spi = R.spi, spp = R.spp;
+                        const JobView &J = NC_R(jobs)[job];
+                        const int tx = J.tiles_x, spi = NC_R(spi), spp = NC_R(spp);
                         const int W = J.cam.W, H = J.cam.H;
                         // a job has fewer than 2^32 items (checked at launch): 32-bit divisions
                         const uint32_t lw = (uint32_t)(w - J.item_begin);
@@ -1675,7 +1747,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             }
             if (phase == kPhSample && have_item) {
                 rng.reset();
-                const volatile JobView &J = R.jobs[job];
+                const JobView &J = NC_R(jobs)[job];
                 const int W = J.cam.W;
                 const int py = pix / W, px = pix - py * W;
                 rng.need(kExt && A.op.kd_n ? 3 : 2, (uint32_t)pix, A.sample_base + (uint32_t)s, A.stream_base + (uint32_t)job, A.key0,
@@ -1744,12 +1816,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         int nxt = -1;
         for (int k = 0; k < A.n_sets && nxt < 0; ++k) {
             if ((tried >> k) & 1u) continue;
-            const unsigned long long lo = R.set_begin[k], hi = R.set_begin[k + 1], span = R.set_span[k];
+            const unsigned long long lo = NC_R(set_begin[k]), hi = NC_R(set_begin[k + 1]), span = NC_R(set_span[k]);
             for (int q = 0; q < 8; ++q) {
                 const unsigned long long qlo = lo + (unsigned long long)q * span;
                 if (qlo >= hi) break;
                 const unsigned long long head =
-                    __hip_atomic_load(A.queue + 128 * k + 16 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_load(NC_R(queue) + 128 * k + 16 * q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 if (qlo + head < hi) { nxt = k; break; }
             }
         }
@@ -1777,6 +1849,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
 #undef NC_SET_HI
 #undef NC_SET_SPAN
 #undef NC_SET_QUEUE
+#undef NC_R
     // per-lane reads, then the block's counters to global memory
     const unsigned long long rsum = wave_sum(reads);
     if (lane == 0) atomicAdd(s_cnt + kCReads, rsum);
@@ -1881,9 +1954,8 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     A.key1 = (uint32_t)(s.seed >> 32);
     A.sample_base = (uint32_t)s.sample_offset;
     A.stream_base = s.stream;
-    A.items = items;
     A.counters = counters;
-    A.queue = scr.queue;
+    rare.queue = scr.queue;
     A.n_sets = n_sets;
     for (int k = 0; k <= n_sets; ++k)
         rare.set_begin[k] = set_first_job[k] < n_jobs ? jobs[set_first_job[k]].item_begin : items;
@@ -1892,7 +1964,6 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         rare.set_span[k] = ((n + 8 * kChunk - 1) / (8 * kChunk)) * kChunk;
         rare.set_group[k] = 0;
     }
-    A.q_span = rare.set_span[0];
     A.lds_first = sh.lds_first;
     A.lds_nodes = sh.lds_nodes;
     const size_t node_bytes = ((size_t)sh.lds_nodes * sizeof(float2) + 15) & ~(size_t)15;
@@ -1907,6 +1978,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         for (int k = 0; k < n_sets; ++k) rare.gw[k] = guide_weights(guides[set_first_job[k]]);
     A.gw = rare.gw[0];
     if (collect) A.col = *collect;
+    rare.hg = op.hg;
+    rare.ssa = op.ssa;
+    rare.max_scatter = op.max_scatter;
     static_assert(sizeof(RenderRare) <= kRareBytes &&
                       kRareBytes <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
