@@ -16,6 +16,11 @@ HIPCC_FLAGS = [
     # no packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-munsafe-fp-atomics",
+    # branches on wave-uniform values (the renderer's phase dispatch) stay
+    # plain scalar branches instead of being folded into one structured chain:
+    # far fewer register copies at the joins (renderer: 115 -> 88 VGPRs,
+    # no scalar spills, 11 % faster)
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
 ]
 
 
