@@ -55,13 +55,13 @@ def measured_traffic():
 
 
 def measured_valu_issue(render_ms):
-    """Share of the SIMDs' cycles spent issuing VALU instructions during one render launch:
-    SQ_ACTIVE_INST_VALU of the committed counter run (units of 4 cycles, summed over waves)
-    x 4 over SIMDs x clock x this run's kernel time; None if the record is stale or lacks it."""
+    """VALU issue load of one render launch: SQ_INSTS_VALU of the committed counter run x 4 cycles
+    (a wave64 VALU instruction on a 16-lane SIMD) over SIMDs x 2.4 GHz x this run's kernel time.
+    Near 1: the VALU pipes are saturated.  None if the record is stale or lacks it."""
     rec = _profile_record()
-    if not rec or "sq_active_inst_valu" not in rec:
+    if not rec or "sq_insts_valu" not in rec:
         return None
-    return rec["sq_active_inst_valu"] * 4.0 / (MI355X_SIMDS * MI355X_CLOCK_HZ * render_ms / 1e3)
+    return rec["sq_insts_valu"] * 4.0 / (MI355X_SIMDS * MI355X_CLOCK_HZ * render_ms / 1e3)
 
 
 def parse():
