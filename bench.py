@@ -828,7 +828,9 @@ def guided_run(ctx, sc, kc, spp, args, build_ms, plain):
 def batch_run(ctx, sc, kc, spp):
     """48 views (256^2 .. 1024^2) x 4 sun zeniths of the same field in one
     persistent launch, on the launch shape the autotuner picks for it (tuned
-    at 1 spp; the context keeps the shape for the guided batch that follows)."""
+    at the batch's own spp, since the grouping of samples into queue items is
+    one of the knobs; the context keeps the shape for the guided batch that
+    follows)."""
     import torch
 
     from paper_1902_01137_amd import api, inputs
@@ -838,11 +840,11 @@ def batch_run(ctx, sc, kc, spp):
     px = sum(c.width * c.height for c, _ in jobs)
     default_launch = ctx.get_launch()
     t0 = time.perf_counter()
-    tuned, tuned_ms = api.autotune_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 16, spp=1,
+    tuned, tuned_ms = api.autotune_batch(ctx, g, kc, jobs, inputs.Sampling(seed=sc.sampling.seed + 16, spp=spp,
                                                                            flags=FLAGS))
     tune_s = time.perf_counter() - t0
     res = {"jobs": len(jobs), "pixels": px, "spp": spp, "paths": px * spp, "tuned_launch": tuned,
-           "tuned_1spp_ms": tuned_ms, "tune_s": tune_s, "default_launch": default_launch}
+           "tuned_ms": tuned_ms, "tune_s": tune_s, "default_launch": default_launch}
     for name in ("default", "tuned"):
         ctx.set_launch(**(default_launch if name == "default" else tuned))
         smp = inputs.Sampling(seed=sc.sampling.seed + 17, spp=spp, flags=FLAGS)

@@ -502,7 +502,7 @@ nc_status nc_render_batch(nc_ctx *ctx, const nc_grid *grid, const float *d_kc, i
  * capture, tight serving loops, harnesses that forbid allocation):
  * nc_render_batch without any device allocation.  Its job table, launch
  * record and work-queue heads live in a fixed array inside the library
- * (NC_NOALLOC_MAX_JOBS job records, about 124 KB), one copy per GPU, held
+ * (NC_NOALLOC_MAX_JOBS job records, about 125 KB), one copy per GPU, held
  * until the process ends; its address on a device is resolved when the
  * first context is created there.  n_jobs above NC_NOALLOC_MAX_JOBS is
  * NC_ERR_INVALID_ARG.  Every call on a GPU uses that GPU's one array and
