@@ -45,7 +45,7 @@ def test_profile_record_is_used_only_for_the_sources_it_was_measured_on(monkeypa
     assert b.measured_traffic() == rec["bytes_per_launch"]
     ms = 150.0
     frac = b.measured_valu_issue(ms)
-    assert frac == rec["sq_active_inst_valu"] * 4.0 / (1024 * 2.4e9 * ms / 1e3)
+    assert frac == rec["sq_insts_valu"] * 4.0 / (1024 * 2.4e9 * ms / 1e3)
     assert 0.0 < frac < 1.5
     monkeypatch.setattr(b, "kernel_sources_digest", lambda: "0" * 64)
     assert b.measured_traffic() is None
