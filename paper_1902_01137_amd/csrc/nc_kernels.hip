@@ -874,26 +874,22 @@ __device__ inline bf16x4 relu_bf16x4(f32x4 c)
     return cvt_bf16x4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), fmaxf(c[3], 0.0f));
 }
 
-// Two 16-row blocks nt0, nt0 + 1 of a K = 64 layer: their four weight
-// fragments are read from LDS before the first product, so the read
-// latencies overlap instead of adding up (a whole layer at once would need
-// more registers than the renderer has to spare).
+// Two 16-row blocks nt0, nt0 + 1 of a K = 64 layer.  Each weight fragment is
+// read from LDS where its product needs it: reading all four ahead overlapped
+// their latencies but held 16 more registers, which kept the guided renderer
+// at 3 waves per SIMD (at 4 the other waves hide the latency).
 __device__ inline void guide_pair32(const short *w, const float *b, int nt0, bf16x8 x0, bf16x8 x1, int n, int kq,
                                     f32x4 &c0, f32x4 &c1)
 {
-    bf16x8 wa[4];
-    f32x4 bb[2];
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-        const short *row = w + ((nt0 + j) * 16 + n) * kWStride + 8 * kq;
-        wa[2 * j] = *reinterpret_cast<const bf16x8 *>(row);
-        wa[2 * j + 1] = *reinterpret_cast<const bf16x8 *>(row + 32);
-        bb[j] = *reinterpret_cast<const f32x4 *>(b + (nt0 + j) * 16 + 4 * kq);
-    }
-    __builtin_amdgcn_sched_barrier(0);
+    const short *r0 = w + (nt0 * 16 + n) * kWStride + 8 * kq;
+    const short *r1 = r0 + 16 * kWStride;
     // the bias is the accumulator's starting value
-    c0 = mfma32(wa[1], x1, mfma32(wa[0], x0, bb[0]));
-    c1 = mfma32(wa[3], x1, mfma32(wa[2], x0, bb[1]));
+    c0 = mfma32(*reinterpret_cast<const bf16x8 *>(r0 + 32), x1,
+                mfma32(*reinterpret_cast<const bf16x8 *>(r0), x0,
+                       *reinterpret_cast<const f32x4 *>(b + nt0 * 16 + 4 * kq)));
+    c1 = mfma32(*reinterpret_cast<const bf16x8 *>(r1 + 32), x1,
+                mfma32(*reinterpret_cast<const bf16x8 *>(r1), x0,
+                       *reinterpret_cast<const f32x4 *>(b + (nt0 + 1) * 16 + 4 * kq)));
 }
 
 __device__ inline void guide_hidden32(const short *w, const float *b, const bf16x4 *x, bf16x4 *y, int n, int kq)
@@ -919,16 +915,10 @@ __device__ inline void guide_tile_forward(const short *wl, const float *bl, cons
     const int n = lane & 15, kq = lane >> 4;
     bf16x4 h[4], y[4];
     const bf16x4 x0 = *reinterpret_cast<const bf16x4 *>(in + n * 16 + 4 * kq);
-    bf16x4 w1[4];
-    f32x4 b1[4];
 #pragma unroll
-    for (int nt = 0; nt < 4; ++nt) {
-        w1[nt] = *reinterpret_cast<const bf16x4 *>(wl + (nt * 16 + n) * kW1Stride + 4 * kq);
-        b1[nt] = *reinterpret_cast<const f32x4 *>(bl + kBOff[0] + nt * 16 + 4 * kq);
-    }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int nt = 0; nt < 4; ++nt) y[nt] = relu_bf16x4(mfma16(w1[nt], x0, b1[nt]));
+    for (int nt = 0; nt < 4; ++nt)
+        y[nt] = relu_bf16x4(mfma16(*reinterpret_cast<const bf16x4 *>(wl + (nt * 16 + n) * kW1Stride + 4 * kq), x0,
+                                   *reinterpret_cast<const f32x4 *>(bl + kBOff[0] + nt * 16 + 4 * kq)));
     guide_hidden32(wl + kWOff[1], bl + kBOff[1], y, h, n, kq);
     guide_hidden32(wl + kWOff[2], bl + kBOff[2], h, y, n, kq);
     const bf16x8 y0 = __builtin_shufflevector(y[0], y[1], 0, 1, 2, 3, 4, 5, 6, 7);
@@ -1224,7 +1214,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     int job = 0;                           // the lane's current view x sun
     float sun[3] = {0.0f, 0.0f, 1.0f};     // that job's sun direction (its irradiance is applied at the flush)
 
-    uint32_t reads = 0;        // global grid and field reads of this lane
     int phase = kPhSample;
     bool shadow = false;       // the current ray is a sun ray
     bool have_item = false;    // the lane holds a queue item with samples left
@@ -1334,7 +1323,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     hit = true;
                     // a ray leaving an event point starts in the event's voxel unless
                     // rounding put its origin in a neighbouring cell
-                    if ((r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 && (r.c[2] >> vc.lev) == vc.i2) {
+                    // (the guided kernels keep no cache: its six registers are what
+                    // lets them run 4 waves per SIMD)
+                    if (kMode != kGuided && (r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 &&
+                        (r.c[2] >> vc.lev) == vc.i2) {
                         r.lev = vc.lev;
                         r.khat = vc.khat;
                         r.kmin = vc.kmin;
@@ -1347,10 +1339,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     r.t = r.tend = r.texit = 0.0f;
                     r.khat = 0.0f;
                     r.kmin = 0.0f;
-                    r.lev = vc.lev;
+                    r.lev = kMode != kGuided ? vc.lev : g.L;
                 }
             }
-            if (locate) locate_voxel(g, ns, r, A.op.mscale, reads);
+            if (locate) {
+                uint32_t nr = 0;   // (counted by ballot below when statistics are on)
+                locate_voxel(g, ns, r, A.op.mscale, nr);
+            }
             if (locate || known) leaf_exit(g, r);
             if (crossing && locate) {
                 leaf = true;
@@ -1370,6 +1365,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 phase = voxel_phase(r, tau);
             }
             if (stats) {
+                // memory reads of a voxel lookup: the cell, the ancestry mask, and the
+                // node when its level is not staged in LDS
+                wave_count(cnt, kCReads, locate);
+                if (g.L >= 1) wave_count(cnt, kCReads, locate);
+                wave_count(cnt, kCReads, locate && r.lev >= 1 && r.lev < ns.lds_first);
                 wave_count(cnt, kCSegments, crossing);
                 wave_count(cnt, kCLeaf, leaf || hit);
                 wave_count(cnt, kCDeep, (leaf || hit) && r.lev < ns.lds_first);
@@ -1393,7 +1393,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 float kx = kmin;                // a level-0 voxel is one cell: k is known
                 if (r.lev != 0) {
                     kx = g.kscale * g.kc[collision_cell(g, r, r.t)] + path_kg();
-                    ++reads;
                     gathered = true;
                 }
                 t_sun *= __expf(-kctrl * (r.t - t0)) * fmaxf(0.0f, 1.0f - (kx - kctrl) * __builtin_amdgcn_rcpf(r.khat));
@@ -1427,8 +1426,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                         kc_hit = r.kmin;        // a level-0 voxel is one cell: k is known
                     } else {
                         kc_hit = g.kc[collision_cell(g, r, r.t)];
-                        ++reads;
-                        gathered = true;
+                            gathered = true;
                     }
                     real = thr < g.kscale * kc_hit + path_kg();
                 }
@@ -1854,15 +1852,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
 #undef NC_SET_SPAN
 #undef NC_SET_QUEUE
 #undef NC_R
-    // per-lane reads, then the block's counters to global memory
-    const unsigned long long rsum = wave_sum(reads);
-    if (lane == 0) atomicAdd(s_cnt + kCReads, rsum);
+    // the block's counters to global memory
     __syncthreads();
     if (A.counters && threadIdx.x == 0) {
         unsigned long long *o = reinterpret_cast<unsigned long long *>(A.counters);
         const unsigned long long v[10] = {s_cnt[kCPaths], s_cnt[kCSegments], s_cnt[kCTentative], s_cnt[kCNulls],
                                           s_cnt[kCReals], s_cnt[kCLeaf], s_cnt[kCGathers],
-                                          s_cnt[kCReads] - s_cnt[kCGathers], s_cnt[kCNee], s_cnt[kCTrunc]};
+                                          s_cnt[kCReads], s_cnt[kCNee], s_cnt[kCTrunc]};
         for (int k = 0; k < 10; ++k)
             if (v[k]) atomicAdd(o + k, v[k]);
         unsigned long long *sch = reinterpret_cast<unsigned long long *>(A.counters->sched);
@@ -1907,7 +1903,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
         mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
     // the guided kernel and the extended-medium kernels hold 3 waves per SIMD (12 per CU) by their register counts
     const bool ext = op.kd_n > 0 || op.tab.n > 0 || op.cone;
-    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (mode == kGuided || (ext && mode != kPlain)) ? 12 : 0);
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (ext && mode == kCollect) ? 12 : 0);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -1997,9 +1993,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     if (op.kd_n > 0 || op.tab.n > 0 || op.cone) {
         // the extended medium (k-distribution, phase table, solar disc): its own kernel variants
         if (mode == kGuided)
-            fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0, true>
-                 : est == 1 ? (const void *)render_kernel<3, kGuided, 1, true>
-                            : (const void *)render_kernel<3, kGuided, 2, true>;
+            fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, true>
+                 : est == 1 ? (const void *)render_kernel<4, kGuided, 1, true>
+                            : (const void *)render_kernel<4, kGuided, 2, true>;
         else if (mode == kCollect)
             fn = est == 0 ? (const void *)render_kernel<3, kCollect, 0, true>
                  : est == 1 ? (const void *)render_kernel<3, kCollect, 1, true>
@@ -2009,9 +2005,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
                  : est == 1 ? (const void *)render_kernel<4, kPlain, 1, true>
                             : (const void *)render_kernel<4, kPlain, 2, true>;
     } else if (mode == kGuided) {
-        fn = est == 0 ? (const void *)render_kernel<3, kGuided, 0, false>
-             : est == 1 ? (const void *)render_kernel<3, kGuided, 1, false>
-                        : (const void *)render_kernel<3, kGuided, 2, false>;
+        fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, false>
+             : est == 1 ? (const void *)render_kernel<4, kGuided, 1, false>
+                        : (const void *)render_kernel<4, kGuided, 2, false>;
     } else if (mode == kCollect) {
         fn = est == 0 ? (const void *)render_kernel<4, kCollect, 0, false>
              : est == 1 ? (const void *)render_kernel<4, kCollect, 1, false>
