@@ -667,32 +667,6 @@ __device__ inline void start_ray_cached(const GridView &g, const NodeSrc &ns, Ra
     }
 }
 
-__device__ inline bool start_ray_cached_r(const GridView &g, const NodeSrc &ns, Ray &r, const float o[3],
-                                          const float d[3], const VoxelCache &vc, float mscale, uint32_t &reads)
-{
-    if (ray_setup(g, r, o, d, 0.0f)) {
-        if ((r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 && (r.c[2] >> vc.lev) == vc.i2) {
-            r.lev = vc.lev;
-            r.khat = vc.khat;
-            r.kmin = vc.kmin;
-            leaf_exit(g, r);
-        } else {
-            find_leaf(g, ns, r, mscale, reads);
-        }
-        return true;
-    }
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-        r.o[a] = o[a];
-        r.d[a] = d[a];
-    }
-    r.t = r.tend = r.texit = 0.0f;
-    r.khat = 0.0f;
-    r.kmin = 0.0f;
-    r.lev = vc.lev;
-    return false;
-}
-
 __device__ inline void stage_levels(const GridView &g, int lds_first, int lds_nodes, float2 *s_nodes, int *s_off)
 {
     for (int i = threadIdx.x; i < NC_MAX_LEVELS + 2; i += blockDim.x) s_off[i] = i <= g.L + 1 ? g.off[i] : 0;

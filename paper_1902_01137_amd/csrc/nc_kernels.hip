@@ -1233,7 +1233,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     float p_cont = 0.0f;       // probability that the path goes on after the event
     bool ground_ev = false;
     int order = 0, segs = 0;
-    VoxelCache vc{g.L, -1, 0, 0, 0.0f, 0.0f};
     float beta = 1.0f;                   // path weight (guided mode)
     float kev = 0.0f;                    // extinction at the current event (guided and collection modes)
     float kg = g.k_gas;                  // the path's gas extinction: a k-distribution point (kExt)
@@ -1297,7 +1296,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
             // and its exit face
             const bool crossing = phase == kPhCross, starting = phase == kPhRay;
             const bool resid = crossing && shadow && kSun == 2;
-            bool locate = false, known = false, leaf = false, hit = false, trunc = false;
+            bool locate = false, leaf = false, hit = false, trunc = false;
             if (resid) t_sun *= __expf(-(g.kscale * r.kmin + path_kg()) * (r.texit - r.t));
             // one random number at most: the Russian roulette of a small residual
             // estimate, or the optical thickness of a new ray
@@ -1321,32 +1320,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 const float rd[3] = {shadow ? sun[0] : pd[0], shadow ? sun[1] : pd[1], shadow ? sun[2] : pd[2]};
                 if (ray_setup(g, r, o, rd, 0.0f)) {
                     hit = true;
-                    // a ray leaving an event point starts in the event's voxel unless
-                    // rounding put its origin in a neighbouring cell
-                    // (the guided kernels keep no cache: its six registers are what
-                    // lets them run 4 waves per SIMD)
-                    if (kMode != kGuided && (r.c[0] >> vc.lev) == vc.i0 && (r.c[1] >> vc.lev) == vc.i1 &&
-                        (r.c[2] >> vc.lev) == vc.i2) {
-                        r.lev = vc.lev;
-                        r.khat = vc.khat;
-                        r.kmin = vc.kmin;
-                        known = true;
-                    } else {
-                        locate = true;
-                    }
+                    // the start voxel is located afresh: keeping the event's voxel
+                    // per lane to skip this lookup cost six registers through the
+                    // whole loop, which cost more than the lookups
+                    locate = true;
                 } else {
                     // misses the box: the next step finds the ray outside
                     r.t = r.tend = r.texit = 0.0f;
                     r.khat = 0.0f;
                     r.kmin = 0.0f;
-                    r.lev = kMode != kGuided ? vc.lev : g.L;
+                    r.lev = g.L;
                 }
             }
             if (locate) {
                 uint32_t nr = 0;   // (counted by ballot below when statistics are on)
                 locate_voxel(g, ns, r, A.op.mscale, nr);
             }
-            if (locate || known) leaf_exit(g, r);
+            if (locate) leaf_exit(g, r);
             if (crossing && locate) {
                 leaf = true;
                 if (resid) r.khat = fmaxf(r.khat - (g.kscale * r.kmin + path_kg()), 0.0f);
@@ -1464,7 +1454,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     cont = true;
                 } else if (res == kReal) {
                     // volume event: local estimate of the sun, then scatter or absorb
-                    vc = voxel_of(r);
 #pragma unroll
                     for (int a = 0; a < 3; ++a) {
                         pd[a] = r.d[a];
@@ -1523,8 +1512,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                     w_nee = rho * (1.0f / kPi) * sun[2] * gain;   // <= 0 (no sun ray) when the direction is below the horizon
                     p_cont = rho;
                     ground_ev = true;
-                    vc.lev = g.L;
-                    vc.i0 = -1;                  // outside the field: no voxel to reuse
                     ++order;
                     if (max_scatter >= 0 && order > max_scatter) {
                         phase = kPhSample;
@@ -1778,8 +1765,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
                 segs = 0;
                 shadow = false;
                 traced = true;
-                vc.lev = g.L;
-                vc.i0 = -1;
                 phase = kPhRay;
                 if (J.cam.type == 2) {
                     // irradiance sensor: first the sun's direct beam (a sun ray of
