@@ -55,9 +55,10 @@ def measured_traffic():
 
 
 def measured_valu_issue(render_ms):
-    """VALU issue load of one render launch: SQ_INSTS_VALU of the committed counter run x 4 cycles
-    (a wave64 VALU instruction on a 16-lane SIMD) over SIMDs x 2.4 GHz x this run's kernel time.
-    Near 1: the VALU pipes are saturated.  None if the record is stale or lacks it."""
+    """VALU instruction rate of one render launch: SQ_INSTS_VALU of the committed counter run x 4 cycles
+    (one wave64 instruction on a 16-lane SIMD) over SIMDs x 2.4 GHz x this run's kernel time.  A rate,
+    not a bounded share (it exceeds 1 when instructions issue faster than one per 4 cycles on average).
+    None if the record is stale or lacks it."""
     rec = _profile_record()
     if not rec or "sq_insts_valu" not in rec:
         return None
@@ -327,7 +328,7 @@ def roofline(c, render_ms, with_record):
             "implementation_request_GBps_at_64B": impl * GRANULE / t / 1e9,
             "method_bytes_GBps": (4 * c["gathers"] + 8 * c["deep_visits"] + 16 * c["paths"]) / t / 1e9,
             "measured_hbm_GBps": traffic / t / 1e9 if traffic else None,
-            "valu_issue_frac": measured_valu_issue(render_ms) if with_record else None}
+            "valu_insts_x4_per_simd_cycle": measured_valu_issue(render_ms) if with_record else None}
 
 
 def gather_ceiling(ctx):
