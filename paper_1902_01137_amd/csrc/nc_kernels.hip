@@ -1886,9 +1886,7 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const int block0 = ctx->launch.block > 0 ? std::max(64, std::min(256, (ctx->launch.block / 64) * 64)) : 256;
     const size_t guide_bytes =
         mode == kGuided ? (size_t)kGuideWeightBytes + (size_t)(block0 / 64) * kGuideScratchPerWave : 0;
-    // the guided kernel and the extended-medium kernels hold 3 waves per SIMD (12 per CU) by their register counts
-    const bool ext = op.kd_n > 0 || op.tab.n > 0 || op.cone;
-    Shape sh = choose_shape(ctx, g, 256, guide_bytes, (ext && mode == kCollect) ? 12 : 0);
+    Shape sh = choose_shape(ctx, g, 256, guide_bytes, 0);
     RenderRare rare;
     rare.seed = s.seed;
     rare.sample_offset = s.sample_offset;
@@ -1970,7 +1968,9 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
                       kRareBytes <= (kScratchErr - kScratchRare) * sizeof(unsigned long long),
                   "scratch too small for the renderer parameters");
     // register budget: waves per SIMD the kernel is compiled for (3..6)
-    // (default 4: the plain kernel fits 128 registers without spilling)
+    // (default 4, a cap of 128 registers: the plain and collection kernels
+    // take 80-95, so the occupancy query then gives them 5-6 waves per SIMD;
+    // the guided ones fill the 128 with a few spilled)
     const int wpe = ctx->launch.waves_per_cu > 0 ? std::max(3, std::min(6, ctx->launch.waves_per_cu / 4)) : 4;
     // kernel variant: mode, sun-ray estimator, register budget (waves per SIMD)
     const int est = s.flags & NC_SUN_ESTIMATOR_MASK;
@@ -1982,10 +1982,10 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
                  : est == 1 ? (const void *)render_kernel<4, kGuided, 1, true>
                             : (const void *)render_kernel<4, kGuided, 2, true>;
         else if (mode == kCollect)
-            fn = est == 0 ? (const void *)render_kernel<3, kCollect, 0, true>
-                 : est == 1 ? (const void *)render_kernel<3, kCollect, 1, true>
-                            : (const void *)render_kernel<3, kCollect, 2, true>;
-        else   // 4 waves per SIMD, a few registers spilled: 15 % faster than 3 with the solar disc
+            fn = est == 0 ? (const void *)render_kernel<4, kCollect, 0, true>
+                 : est == 1 ? (const void *)render_kernel<4, kCollect, 1, true>
+                            : (const void *)render_kernel<4, kCollect, 2, true>;
+        else
             fn = est == 0 ? (const void *)render_kernel<4, kPlain, 0, true>
                  : est == 1 ? (const void *)render_kernel<4, kPlain, 1, true>
                             : (const void *)render_kernel<4, kPlain, 2, true>;
