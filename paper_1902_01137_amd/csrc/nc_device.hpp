@@ -160,6 +160,7 @@ struct GridView {
     float lo[3];
     float h[3];
     float inv_h[3];
+    float hi[3];         // the box's far faces, (float)n h + lo rounded as the crossing rounds a face position
     float k_gas;
     float kscale;        // droplet extinction is kscale * kc (the grid holds kc's min and max)
     const float *kc;
@@ -242,9 +243,12 @@ __host__ __device__ inline bool ray_setup(const GridView &g, Ray &r, const float
         r.d[a] = d[a];
         const bool flat = d[a] == 0.0f;   // parallel to the axis' faces: inside their slab or a miss
         r.inv[a] = flat ? INFINITY : 1.0f / d[a];   // correctly rounded (the host twin divides alike)
-        const float b0 = g.lo[a], b1 = (float)g.n[a] * g.h[a] + g.lo[a];
+        // (both faces straight from the grid view, not through face_t: the
+        // compiler cannot fold 0 h, and the hoisted per-axis values held through a
+        // persistent loop cost registers)
+        const float b0 = g.lo[a], b1 = g.hi[a];
         miss = miss || (flat && (o[a] < b0 || o[a] > b1));
-        const float t0 = face_t(g, r, a, 0), t1 = face_t(g, r, a, g.n[a]);
+        const float t0 = (b0 - r.o[a]) * r.inv[a], t1 = (b1 - r.o[a]) * r.inv[a];
         tlo[a] = t0 > t1 ? t1 : t0;
         thi[a] = t0 > t1 ? t0 : t1;
         tin = flat ? tin : fmaxf(tin, tlo[a]);

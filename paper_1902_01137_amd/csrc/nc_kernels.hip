@@ -2114,6 +2114,7 @@ GridView grid_view(const nc_grid *g, const float *d_kc)
         v.lo[a] = (float)g->lo[a];
         v.h[a] = (float)g->h[a];
         v.inv_h[a] = (float)(1.0 / g->h[a]);
+        v.hi[a] = (float)g->n[a] * v.h[a] + v.lo[a];   // float arithmetic, no contraction: as face_t rounds it
     }
     v.L = g->L;
     v.k_gas = (float)g->params.k_gas;

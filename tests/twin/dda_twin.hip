@@ -63,6 +63,7 @@ extern "C" int twin_trace(int nx, int ny, int nz, double x0, double y0, double z
         g.lo[a] = (float)lo[a];
         g.h[a] = (float)h[a];
         g.inv_h[a] = (float)(1.0 / h[a]);
+        g.hi[a] = (float)dims[a] * g.h[a] + g.lo[a];
     }
     g.L = L;
     g.k_gas = 0.0f;
