@@ -869,9 +869,23 @@ __device__ inline bf16x4 cvt_bf16x4(float a, float b, float c, float d)
 // as the A operand (rows = output neurons) and the activations as the B
 // operand (columns = vertices).  Lane l receives
 // out[vertex l % 16][16 nt + 4 (l / 16) + i] of block nt: the next layer's B slots.
+// The ReLU acts on the rounded values as a signed 16-bit max with zero: a
+// negative bf16 has its sign bit set, so it reads as a negative integer and
+// becomes +0, while a positive one is unchanged; that is bf16(max(x, 0)) bit
+// for bit up to the sign of a zero.  One packed instruction per pair, where
+// fmaxf on the floats takes two per value (it first quiets a possible
+// signalling NaN).
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 b16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+__device__ inline s16x2 relu_bf16x2(float a, float b)
+{
+    const s16x2 v = __builtin_bit_cast(s16x2, __builtin_convertvector(f32x2{a, b}, b16x2));
+    return __builtin_elementwise_max(v, s16x2{0, 0});
+}
 __device__ inline bf16x4 relu_bf16x4(f32x4 c)
 {
-    return cvt_bf16x4(fmaxf(c[0], 0.0f), fmaxf(c[1], 0.0f), fmaxf(c[2], 0.0f), fmaxf(c[3], 0.0f));
+    return __builtin_shufflevector(relu_bf16x2(c[0], c[1]), relu_bf16x2(c[2], c[3]), 0, 1, 2, 3);
 }
 
 // Two 16-row blocks nt0, nt0 + 1 of a K = 64 layer.  Each weight fragment is
@@ -1025,14 +1039,22 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
     // the choice would fall on (used only in lane group qs) and the HG draw
     const float lo = kq == 0 ? 0.0f : kq == 1 ? c1 : kq == 2 ? c2 : c3;
     const bool second = target >= lo + e0;
-    const float m[3] = {second ? z[6] : z[1], second ? z[7] : z[2], second ? z[8] : z[3]};
-    const float inv = rsqrtf(fmaxf(m[0] * m[0] + m[1] * m[1] + m[2] * m[2], 1e-24f));
-    const float kap = __expf(fminf(fmaxf(second ? z[9] : z[4], kLogKappaMin), kLogKappaMax));
+    // per lobe of this lane: the reciprocal length of its mean, kappa and
+    // exp(-2 kappa), shared by the draw and the mixture density
+    float il[2], kl[2], el[2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const float m0 = z[5 * h + 1], m1 = z[5 * h + 2], m2 = z[5 * h + 3];
+        il[h] = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
+        kl[h] = __expf(fminf(fmaxf(z[5 * h + 4], kLogKappaMin), kLogKappaMax));
+        el[h] = __expf(-2.0f * kl[h]);
+    }
+    const float inv = second ? il[1] : il[0], kap = second ? kl[1] : kl[0];
     // the stable vMF cosine inversion (Jakob 2012)
-    const float t =
-        fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * __expf(-2.0f * kap)) * __builtin_amdgcn_rcpf(kap)));
+    const float t = fminf(1.0f, fmaxf(-1.0f, 1.0f + __logf(u1 + (1.0f - u1) * (second ? el[1] : el[0])) *
+                                                       __builtin_amdgcn_rcpf(kap)));
     const float sp = __builtin_amdgcn_sinf(u2), cp = __builtin_amdgcn_cosf(u2);   // the azimuth of both candidates
-    float v[3] = {m[0] * inv, m[1] * inv, m[2] * inv};
+    float v[3] = {(second ? z[6] : z[1]) * inv, (second ? z[7] : z[2]) * inv, (second ? z[8] : z[3]) * inv};
     turn_sc(v, t, sp, cp);
     float hgd[3] = {pd[0], pd[1], pd[2]};
     turn_sc(hgd, kTab ? phase_sample_mu(g, tab, u1) : hg_sample_mu(g, u1), sp, cp);
@@ -1050,12 +1072,10 @@ __device__ inline GuidedStep guided_turn_tile(const float z[12], const float *sl
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const float m0 = z[5 * h + 1], m1 = z[5 * h + 2], m2 = z[5 * h + 3];
-        const float inv = rsqrtf(fmaxf(m0 * m0 + m1 * m1 + m2 * m2, 1e-24f));
-        const float cw = (m0 * o.d[0] + m1 * o.d[1] + m2 * o.d[2]) * inv;
-        const float kap = __expf(fminf(fmaxf(z[5 * h + 4], kLogKappaMin), kLogKappaMax));
+        const float cw = (m0 * o.d[0] + m1 * o.d[1] + m2 * o.d[2]) * il[h];
         // kappa >= e^-3, so 1 - exp(-2 kappa) >= 0.095 keeps its relative precision
-        const float norm = kap * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - __expf(-2.0f * kap)));
-        qp += (h == 0 ? e0 : e1) * norm * __expf(kap * (cw - 1.0f));
+        const float norm = kl[h] * __builtin_amdgcn_rcpf(2.0f * kPi * (1.0f - el[h]));
+        qp += (h == 0 ? e0 : e1) * norm * __expf(kl[h] * (cw - 1.0f));
     }
     qp = lane_sum32(lane_sum16(qp));   // the same sum in every lane of the column
     o.q = qp * __builtin_amdgcn_rcpf(psum);
@@ -1178,9 +1198,15 @@ hipError_t launch_guide_sample(const nc_ctx *ctx, const nc_guide *gd, const floa
     return hipGetLastError();
 }
 
-template <int kWavesPerEU, int kMode, int kSun, bool kExt>
+// kSets: the guided batch with more than one network (queue set); a
+// workgroup whose set has drained moves to another.  Compiled only where a
+// launch has several sets: the loop around the tracing loop keeps many more
+// values live (a single-view guided kernel without it issues 11 % fewer
+// vector instructions and keeps its scalars in scalar registers).
+template <int kWavesPerEU, int kMode, int kSun, bool kExt, bool kSets = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU))) void render_kernel(RenderArgs A)
 {
+    static_assert(!kSets || kMode == kGuided, "queue sets are for guided batches");
     extern __shared__ __align__(16) float2 s_nodes[];
     __shared__ int s_off[NC_MAX_LEVELS + 2];
     __shared__ unsigned long long s_cnt[kNumBlockCounters];
@@ -1191,8 +1217,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
     int cur = 0;   // workgroup-uniform: the queue set (and network) this workgroup serves
     if (kMode == kGuided) {
         const int grp = (int)(blockIdx.x >> 3);
-        for (int k = 1; k < A.n_sets; ++k)
-            if (grp >= A.rare->set_group[k]) cur = k;
+        if (kSets)
+            for (int k = 1; k < A.n_sets; ++k)
+                if (grp >= A.rare->set_group[k]) cur = k;
         char *gb = reinterpret_cast<char *>(s_nodes) + A.guide_lds;
         if (cur == 0) {
             stage_guide(A.gw, reinterpret_cast<short *>(gb), reinterpret_cast<float *>(gb + kWOff[4] * 2));
@@ -1794,7 +1821,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(kWavesPerEU
         }
         if (stats && lane == 0) atomicAdd(s_cnt + kCCycles0 + run, (unsigned long long)(wall_clock64() - t_trip));
     }
-    if (kMode != kGuided || A.n_sets == 1) break;
+    if (!kSets || A.n_sets == 1) break;
     // every lane of this wave is idle: once all waves of the workgroup are, serve
     // a queue set (network) that still has work, if any
     tried |= 1u << cur;
@@ -1977,7 +2004,11 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
     const void *fn = nullptr;
     if (op.kd_n > 0 || op.tab.n > 0 || op.cone) {
         // the extended medium (k-distribution, phase table, solar disc): its own kernel variants
-        if (mode == kGuided)
+        if (mode == kGuided && n_sets > 1)
+            fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, true, true>
+                 : est == 1 ? (const void *)render_kernel<4, kGuided, 1, true, true>
+                            : (const void *)render_kernel<4, kGuided, 2, true, true>;
+        else if (mode == kGuided)
             fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, true>
                  : est == 1 ? (const void *)render_kernel<4, kGuided, 1, true>
                             : (const void *)render_kernel<4, kGuided, 2, true>;
@@ -1989,6 +2020,10 @@ hipError_t launch_render(const nc_ctx *ctx, const nc_grid *g, const float *d_kc,
             fn = est == 0 ? (const void *)render_kernel<4, kPlain, 0, true>
                  : est == 1 ? (const void *)render_kernel<4, kPlain, 1, true>
                             : (const void *)render_kernel<4, kPlain, 2, true>;
+    } else if (mode == kGuided && n_sets > 1) {
+        fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, false, true>
+             : est == 1 ? (const void *)render_kernel<4, kGuided, 1, false, true>
+                        : (const void *)render_kernel<4, kGuided, 2, false, true>;
     } else if (mode == kGuided) {
         fn = est == 0 ? (const void *)render_kernel<4, kGuided, 0, false>
              : est == 1 ? (const void *)render_kernel<4, kGuided, 1, false>
