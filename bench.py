@@ -84,7 +84,10 @@ def parse():
     p.add_argument("--collect-spp", type=int, default=64, help="plain samples per pixel whose vertices train the guide")
     p.add_argument("--train-steps", type=int, default=80000, help="Adam steps of the single-view network")
     p.add_argument("--batch-train-steps", type=int, default=20000, help="Adam steps of each per-sun network of the batch")
-    p.add_argument("--train-batch", type=int, default=65536)
+    p.add_argument("--train-batch", type=int, default=131072,
+                   help="records per Adam step of the single-view network (131072 at 80k steps: guided variance "
+                        "0.346 of plain for 18.8 s of training, against 0.371 for 11.6 s at 65536)")
+    p.add_argument("--batch-train-batch", type=int, default=65536, help="records per Adam step of each batch network")
     p.add_argument("--lr", type=float, default=3e-3, help="Adam step size at the start (cosine decay to 1 %% of it)")
     p.add_argument("--guide-frac", type=float, default=0.5, help="probability of sampling the guide at a scattering")
     p.add_argument("--guide-max-order", type=int, default=0, help="last guided scattering order (0: all)")
@@ -919,7 +922,7 @@ def batch_guided_run(ctx, sc, kc, spp, args):
         gen = torch.Generator(device="cuda")
         gen.manual_seed(1)
         for it in range(args.batch_train_steps):
-            idx = torch.randint(0, rec.shape[0], (args.train_batch,), device="cuda", generator=gen)
+            idx = torch.randint(0, rec.shape[0], (args.batch_train_batch,), device="cuda", generator=gen)
             gd.train_step(rec[idx], lr_at(it, args.batch_train_steps, args.lr))
         guides[sz] = gd
         del rec
