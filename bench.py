@@ -106,6 +106,9 @@ def parse():
     p.add_argument("--no-guide-kernels", action="store_true", help="skip the network training / inference timing")
     p.add_argument("--no-time-to-eps", action="store_true", help="skip the measured runs to 3%% per-pixel error")
     p.add_argument("--eps", type=float, default=0.03, help="target of the measured time-to-error runs")
+    p.add_argument("--eps-rounds", action="store_true",
+                   help="run the time-to-error legs as rounds of render calls sized from the error so far (a progress "
+                        "line per round on stderr) instead of one progressive call")
     p.add_argument("--spread-renders", type=int, default=4,
                    help="independent renders whose spread checks the reported standard error")
     p.add_argument("--cpu-workers", type=int, default=0, help="oracle processes of the all-core baseline (0: host)")
@@ -377,6 +380,43 @@ def progressive_run(ctx, sc, kc, gd, args, guided_info=None):
     return out
 
 
+def eps_rounds(ctx, g, kc, sc, smp, eps, guide, name):
+    """Render calls continuing one sample sequence (sample offsets) into the
+    same sums until the per-pixel relative standard error reaches eps; each
+    round is sized from the error so far (at most 16384 spp), the time is the
+    render calls' own (synchronised) and the error is the bench's per-pixel
+    definition."""
+    import dataclasses
+
+    import torch
+
+    from paper_1902_01137_amd import api
+    cam = sc.camera
+    s = torch.zeros((cam.height, cam.width), dtype=torch.float64, device="cuda")
+    s2 = torch.zeros_like(s)
+    n, spent, rounds, R = 0, 0.0, 0, 64
+    while True:
+        step = dataclasses.replace(smp, spp=R, sample_offset=smp.sample_offset + n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        if guide is None:
+            api.render(ctx, g, kc, sc.optics, cam, step, s, s2)
+        else:
+            api.render_guided(ctx, g, kc, sc.optics, cam, step, guide, s, s2)
+        torch.cuda.synchronize()
+        spent += time.perf_counter() - t0
+        n += R
+        rounds += 1
+        m = s / n
+        var = torch.clamp(s2 / n - m * m, min=0.0) * n / (n - 1)
+        err = float(torch.sqrt(torch.mean(var / n)) / torch.mean(m))
+        print("%s: round %d, %d spp, error %.5f, %.1f s" % (name, rounds, n, err, spent), file=sys.stderr, flush=True)
+        if err <= eps:
+            return {"spp_done": n, "rounds": rounds, "rel_err": err, "mean": float(torch.mean(m)), "seconds": spent}
+        need = n * (err / eps) ** 2 * 1.002 - n
+        R = int(min(16384, max(1024, math.ceil(need / 1024) * 1024)))
+
+
 def time_to_eps_run(ctx, sc, kc, gd, args, guided_info=None):
     """Measured time to a per-pixel relative standard error of args.eps on the
     full image (RMS over pixels of the standard error relative to the mean):
@@ -392,8 +432,11 @@ def time_to_eps_run(ctx, sc, kc, gd, args, guided_info=None):
             continue
         smp = inputs.Sampling(seed=sc.sampling.seed + 37, spp=0, flags=FLAGS, guide_frac=args.guide_frac,
                               guide_max_order=args.guide_max_order)
-        _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, args.eps, first_spp=64,
-                                           max_spp=1 << 17, block=1, guide=guide)
+        if args.eps_rounds:
+            rep = eps_rounds(ctx, g, kc, sc, smp, args.eps, guide, name)
+        else:
+            _, _, rep = api.render_progressive(ctx, g, kc, sc.optics, sc.camera, smp, args.eps, first_spp=64,
+                                               max_spp=1 << 20, block=1, guide=guide)
         torch.cuda.synchronize()
         rep["total_s"] = rep["seconds"]
         if name == "guided" and guided_info:
