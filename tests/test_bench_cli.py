@@ -78,3 +78,32 @@ def test_spread_error_of_independent_renders():
     spread, rep = b.spread_err(runs)
     assert abs(spread / rep - 1.0) < 0.03
     assert abs(rep - np.sqrt((se ** 2).mean()) / truth.mean()) < 1e-3
+
+
+def test_training_step_size_decays_by_a_cosine():
+    """The guide's Adam step size starts at lr, halves at mid-training and
+    ends at the 1 % floor."""
+    import math
+    b = _bench_module()
+    lr, n = 3e-3, 80000
+    assert b.lr_at(0, n, lr) == lr
+    assert abs(b.lr_at(n // 2, n, lr) - lr / 2) < 1e-12
+    assert b.lr_at(n - 1, n, lr) == lr * 0.01
+    vals = [b.lr_at(i, n, lr) for i in range(0, n, 997)]
+    assert all(x >= y for x, y in zip(vals, vals[1:]))
+    assert abs(b.lr_at(n // 4, n, lr) - lr * 0.5 * (1 + math.cos(math.pi / 4))) < 1e-12
+
+
+def test_rounds_to_a_target_error_are_sized_from_the_error_so_far():
+    """A round asks for what 1/sqrt(spp) scaling predicts is missing, in
+    multiples of 1024 between 1024 and 16384."""
+    b = _bench_module()
+    # 64 spp at twice the target: 3 x 64 missing -> the minimum round
+    assert b.next_round_spp(64, 0.02, 0.01) == 1024
+    # 40000 spp at 1.1 x the target: 21 % more, 8400 spp -> rounded up to 9216
+    n = b.next_round_spp(40000, 0.011, 0.01)
+    assert n % 1024 == 0 and 40000 * (1.1 ** 2 * 1.002 - 1) <= n < 40000 * (1.1 ** 2 * 1.002 - 1) + 1024
+    # far from the target: capped
+    assert b.next_round_spp(1024, 0.1, 0.01) == 16384
+    # at or below the target already: the smallest round
+    assert b.next_round_spp(5000, 0.01, 0.01) == 1024
