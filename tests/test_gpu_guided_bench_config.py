@@ -1,6 +1,7 @@
 """The guided estimator in the configuration the benchmark reports: a network
-trained on the plain tracer's vertices, every scattering order guided, guide
-fraction c = 0.5, residual ratio tracking of the sun rays.
+trained on the plain tracer's vertices (Adam with the benchmark's cosine
+step-size decay, fewer steps), every scattering order guided, guide fraction
+c = 0.5, residual ratio tracking of the sun rays.
 
 Each guided event multiplies the path weight by p / (c q + (1 - c) p), a
 factor in [0, 1 / (1 - c)] with mean 1; along a path of many events the
@@ -20,6 +21,8 @@ product is unbiased but skewed, so two things are checked:
 Scenes: the small blob (nadir view) and a cumulus field at 50 m seen
 obliquely (many scattering orders inside thick cloud).
 """
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -64,7 +67,7 @@ def guided_runs(request):
     steps = 4000
     for it in range(steps):
         idx = torch.randint(0, rec.shape[0], (65536,), device="cuda", generator=gen)
-        gd.train_step(rec[idx], 3e-3 * (0.2 if it >= 0.8 * steps else 1.0))
+        gd.train_step(rec[idx], 3e-3 * max(0.01, 0.5 * (1.0 + math.cos(math.pi * it / steps))))
     del rec
     runs = []
     for k in range(K):
